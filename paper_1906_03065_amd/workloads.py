@@ -1,0 +1,307 @@
+"""Seeded synthetic inputs shared by the GPU library's tests and benchmark and
+by the CPU oracle's tests.
+
+This module builds parameter dictionaries, initial macroscopic fields and
+initial membrane marker sets.  It holds none of the method's arithmetic: no
+equilibria, stencils, chemical potentials, forces or kernels.  Initial fields
+are diffuse tanh profiles of analytic distances (circles, spheres, planes),
+the shape the paper uses for every interface (Sec. 2.4, eq. CmProfile), and
+markers are points placed evenly on circles or on icosphere meshes.
+
+Workloads (the paper publishes no datasets; these stand in for its geometries):
+  * ``capsule_at_interface``: one capsule of fluid 3 centred on a flat C1/C2
+    interface (Sec. 4.1, Fig. 1a), the paper's benchmark configuration.
+  * ``c1``: 128x128, periodic x, walls in y, R = 20, 128 markers, kappa 0.02,
+    alpha 1, mobility 0.1, +-1e-4 perturbation: the FP64 parity workload.
+  * ``c2``: 2048x2048 with 16 capsules of radius 24..64 on a flat interface,
+    kappa_m uniform in [0.01, 0.05]: the FP32 throughput workload.
+  * ``lens``: a pure liquid lens (no membrane) for the Neumann-angle check.
+  * ``drop``: a C3 drop in C1 for the Laplace-law check.
+  * ``flat``: a flat C1/C2 interface for the tanh-profile / tension checks.
+  * ``capsule3d`` / ``c3``: D3Q19 icosphere capsules with a C3 bridge.
+  * ``c4``: 64 capsule-at-interface runs of seeded uneven sizes.
+Seeds: ``1906030650 + k`` for workload k unless a seed is given.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SEED_BASE = 1906030650
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def base_params(nx, ny, nz=1, lattice=0, wall_y=0, wall_z=0, kappa=(0.02, 0.02, 0.02), alpha=1.0,
+                kappa_c=0.01, tau=1.0, tau_phi=1.0, tau_psi=1.0, mobility=None, gamma=1.0,
+                r_cut=0.0) -> dict:
+    """Parameter dictionary.  ``mobility`` M sets Gamma = M/(tau - 1/2) for both
+    order parameters (eq. RelaxationTimes); otherwise ``gamma`` is used."""
+    gphi = gpsi = gamma
+    if mobility is not None:
+        gphi = mobility / (tau_phi - 0.5)
+        gpsi = mobility / (tau_psi - 0.5)
+    return dict(lattice=lattice, nx=int(nx), ny=int(ny), nz=int(nz), wall_y=int(wall_y),
+                wall_z=int(wall_z), tau=float(tau), tau_phi=float(tau_phi), tau_psi=float(tau_psi),
+                gamma_phi=float(gphi), gamma_psi=float(gpsi),
+                kappa=[float(k) for k in kappa], alpha=float(alpha), kappa_c=float(kappa_c),
+                r_cut=float(r_cut))
+
+
+def tanh_profile(d, alpha):
+    """(1 + tanh(d / 2 alpha)) / 2 of a signed distance d (eq. CmProfile)."""
+    return 0.5 * (1.0 + np.tanh(np.asarray(d, dtype=np.float64) / (2.0 * alpha)))
+
+
+def circle_markers(cx, cy, R, n, phase=None):
+    """n markers evenly spaced counter-clockwise on a circle, marker l at angle
+    (2 l + 1) pi / n by default.  The half-step phase keeps the polygon
+    symmetric under both axis mirrors while no vertex lies on the vertical
+    axis, so lattice nodes on that axis have a unique closest membrane point."""
+    if phase is None:
+        phase = np.pi / n
+    t = phase + 2.0 * np.pi * np.arange(n) / n
+    return np.stack([cx + R * np.cos(t), cy + R * np.sin(t)], axis=1)
+
+
+def _grid2(nx, ny):
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    return x, y
+
+
+def _min_image(dx, n):
+    return dx - n * np.round(dx / n)
+
+
+def fields_from_C(C1, C2, C3, perturb=0.0, seed=0, u=None):
+    """rho, phi, psi from concentrations (eq. VariableTransform), after adding a
+    seeded uniform perturbation in [-perturb, perturb] to every C_m."""
+    C1, C2, C3 = (np.array(c, dtype=np.float64) for c in (C1, C2, C3))
+    if perturb:
+        g = rng(seed)
+        C1 = C1 + g.uniform(-perturb, perturb, C1.shape)
+        C2 = C2 + g.uniform(-perturb, perturb, C2.shape)
+        C3 = C3 + g.uniform(-perturb, perturb, C3.shape)
+    rho = C1 + C2 + C3
+    out = dict(rho=rho, phi=C1 - C2, psi=C3)
+    if u is not None:
+        out["u"] = [np.full(rho.shape, float(c)) for c in u]
+    return out
+
+
+def capsule_at_interface(nx=128, ny=128, R=20.0, n_markers=128, centre=None, y0=None,
+                         kappa=(0.02, 0.02, 0.02), alpha=1.0, kappa_c=0.01, kappa_s=0.01,
+                         kappa_b=1e-4, wall_y=1, mobility=0.1, tau=1.0, tau_phi=1.0, tau_psi=1.0,
+                         perturb=1e-4, seed=SEED_BASE, u0=None, r_cut=0.0):
+    """One capsule of fluid 3 centred on a flat C1/C2 interface at y = y0
+    (C1 below, C2 above), in a box periodic in x (Sec. 4.1)."""
+    if centre is None:
+        centre = (nx / 2.0, (ny - 1) / 2.0)
+    if y0 is None:
+        y0 = centre[1]
+    p = base_params(nx, ny, wall_y=wall_y, kappa=kappa, alpha=alpha, kappa_c=kappa_c, tau=tau,
+                    tau_phi=tau_phi, tau_psi=tau_psi, mobility=mobility, r_cut=r_cut)
+    x, y = _grid2(nx, ny)
+    dx = _min_image(x - centre[0], nx)
+    dy = y - centre[1] if wall_y else _min_image(y - centre[1], ny)
+    C3 = tanh_profile(R - np.hypot(dx, dy), alpha)
+    below = 0.5 * (1.0 - np.tanh((y - y0) / (2.0 * alpha)))
+    if not wall_y:
+        # periodic in y: a second interface half a box away keeps C1 a band
+        dyy = _min_image(y - y0 + ny / 4.0, ny)
+        below = tanh_profile(ny / 4.0 - np.abs(dyy), alpha)
+    C1 = (1.0 - C3) * below
+    C2 = 1.0 - C1 - C3
+    fields = fields_from_C(C1, C2, C3, perturb, seed, u=(u0 if u0 is None else (u0, 0.0)))
+    mem = [dict(X=circle_markers(centre[0], centre[1], R, n_markers), tris=None,
+                kappa_s=kappa_s, kappa_b=kappa_b)]
+    return dict(params=p, fields=fields, membranes=mem, name=f"capsule_at_interface_{nx}x{ny}")
+
+
+def c1(seed=SEED_BASE + 0, **kw):
+    """128x128 D2Q9, periodic x / walls y, lower half C1, upper half C2, one
+    capsule R = 20 of 128 markers (shear modulus 0.01, bending 1e-4), tau 1,
+    kappa 0.02 x3, alpha 1, mobility 0.1, +-1e-4 perturbation."""
+    args = dict(nx=128, ny=128, R=20.0, n_markers=128, kappa=(0.02, 0.02, 0.02), alpha=1.0,
+                kappa_c=0.01, kappa_s=0.01, kappa_b=1e-4, wall_y=1, mobility=0.1, perturb=1e-4,
+                seed=seed)
+    args.update(kw)
+    w = capsule_at_interface(**args)
+    w["name"] = "c1_capsule_128x128"
+    return w
+
+
+def c2(seed=SEED_BASE + 1, n=2048, n_caps=16, with_fields=True):
+    """n x n D2Q9 (FP32 throughput workload), walls in y, flat C1/C2 interface
+    at y0 = (n-1)/2, n_caps capsules with radii U[24, 64] laid left to right
+    with equal gaps, markers clamp(ceil(2 pi R / 0.8), 256, 512), kappa_m
+    U[0.01, 0.05], shear 0.01, bending 1e-4, alpha 1, mobility 0.1."""
+    g = rng(seed)
+    scale = n / 2048.0
+    while True:
+        R = g.uniform(24.0, 64.0, n_caps) * min(1.0, scale)
+        gap = (n - 2.0 * R.sum()) / n_caps
+        if gap >= 8.0:
+            break
+    kappa = g.uniform(0.01, 0.05, 3)
+    y0 = (n - 1) / 2.0
+    p = base_params(n, n, wall_y=1, kappa=kappa, alpha=1.0, kappa_c=0.01, mobility=0.1)
+    cx = []
+    pos = gap / 2.0
+    for r in R:
+        cx.append(pos + r)
+        pos += 2.0 * r + gap
+    mems = []
+    for k in range(n_caps):
+        nm = int(min(512, max(256, math.ceil(2.0 * math.pi * R[k] / 0.8))))
+        mems.append(dict(X=circle_markers(cx[k], y0, R[k], nm), tris=None, kappa_s=0.01,
+                         kappa_b=1e-4))
+    w = dict(params=p, membranes=mems, name=f"c2_{n_caps}caps_{n}x{n}")
+    if with_fields:
+        x, y = _grid2(n, n)
+        C3 = np.zeros((n, n))
+        for k in range(n_caps):
+            C3 += tanh_profile(R[k] - np.hypot(_min_image(x - cx[k], n), y - y0), 1.0)
+        C3 = np.minimum(C3, 1.0)
+        below = 0.5 * (1.0 - np.tanh((y - y0) / 2.0))
+        C1 = (1.0 - C3) * below
+        C2 = 1.0 - C1 - C3
+        w["fields"] = fields_from_C(C1, C2, C3, 1e-4, seed)
+    return w
+
+
+def flat(nx=4, ny=64, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_y=1, seed=None):
+    """Flat C1/C2 interface at y = (ny-1)/2, C1 below; no membrane."""
+    p = base_params(nx, ny, wall_y=wall_y, kappa=kappa, alpha=alpha, kappa_c=0.0, mobility=mobility)
+    x, y = _grid2(nx, ny)
+    y0 = (ny - 1) / 2.0
+    if wall_y:
+        C1 = 0.5 * (1.0 - np.tanh((y - y0) / (2.0 * alpha)))
+    else:
+        C1 = tanh_profile(ny / 4.0 - np.abs(_min_image(y - y0 + ny / 4.0, ny)), alpha)
+    C2 = 1.0 - C1
+    C3 = np.zeros_like(C1)
+    return dict(params=p, fields=fields_from_C(C1, C2, C3), membranes=[], name="flat")
+
+
+def drop(n=64, R=12.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1):
+    """C3 drop of radius R in C1, fully periodic box, no membrane."""
+    p = base_params(n, n, wall_y=0, kappa=kappa, alpha=alpha, kappa_c=0.0, mobility=mobility)
+    x, y = _grid2(n, n)
+    c = (n - 1) / 2.0
+    C3 = tanh_profile(R - np.hypot(x - c, y - c), alpha)
+    C1 = 1.0 - C3
+    C2 = np.zeros_like(C1)
+    return dict(params=p, fields=fields_from_C(C1, C2, C3), membranes=[], name="drop")
+
+
+def lens(nx=120, ny=80, R=20.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1):
+    """Pure liquid lens (Sec. 4.1, filled squares of Fig. 2): a circular C3 drop
+    on a flat C1/C2 interface, walls in y, no membrane."""
+    w = capsule_at_interface(nx=nx, ny=ny, R=R, n_markers=8, kappa=kappa, alpha=alpha, kappa_c=0.0,
+                             wall_y=1, mobility=mobility, perturb=0.0)
+    w["membranes"] = []
+    w["name"] = "lens"
+    return w
+
+
+# ---------------------------------------------------------------------------
+# 3D inputs
+# ---------------------------------------------------------------------------
+def icosphere(subdiv: int):
+    """Unit icosphere: 10*4^k + 2 vertices, 20*4^k triangles, counter-clockwise
+    seen from outside."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t),
+         (0, 1, -t), (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    V = [np.array(v, dtype=np.float64) / np.linalg.norm(v) for v in V]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+         (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+         (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(subdiv):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                cache[key] = len(V) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in F:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = nf
+    return np.array(V), np.array(F, dtype=np.int32)
+
+
+def capsule3d(n=64, R=10.0, subdiv=3, kappa=(0.02, 0.02, 0.02), alpha=1.0, kappa_c=0.01,
+              kappa_s=0.01, kappa_b=1e-3, mobility=0.1, two=True, bridge=True, perturb=1e-4,
+              seed=SEED_BASE + 2, wall_z=1):
+    """D3Q19 box n^3 (periodic x, y; walls in z when wall_z): C2 below
+    z0 = (n-1)/2, C1 above; two icosphere capsules of fluid 3 (radius R) side
+    by side on the interface with a C2 bridge between them.  READING of the
+    bridge: component 3 is reserved for capsule interiors by the coupling
+    energy, so the bridge is component 2."""
+    p = base_params(n, n, n, lattice=1, wall_y=0, wall_z=wall_z, kappa=kappa, alpha=alpha,
+                    kappa_c=kappa_c, mobility=mobility)
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64),) * 3, indexing="ij")
+    z0 = (n - 1) / 2.0
+    yc = (n - 1) / 2.0 + 0.25
+    if two:
+        centres = [(n / 2.0 - 1.25 * R + 0.3, yc, z0 + 0.15), (n / 2.0 + 1.25 * R + 0.3, yc, z0 + 0.15)]
+    else:
+        centres = [(n / 2.0 + 0.3, yc, z0 + 0.15)]
+    V, F = icosphere(subdiv)
+    C3 = np.zeros(x.shape)
+    mems = []
+    for c in centres:
+        d = R - np.sqrt(_min_image(x - c[0], n) ** 2 + _min_image(y - c[1], n) ** 2 + (z - c[2]) ** 2)
+        C3 += tanh_profile(d, alpha)
+        mems.append(dict(X=V * R + np.array(c), tris=F, kappa_s=kappa_s, kappa_b=kappa_b))
+    C3 = np.minimum(C3, 1.0)
+    below = 0.5 * (1.0 - np.tanh((z - z0) / (2.0 * alpha)))
+    C2 = (1.0 - C3) * below
+    if two and bridge:
+        # a C2 column between the capsules, of half-width 0.6 R
+        dxb = np.abs(x - n / 2.0 - 0.3) - 0.25 * R
+        dyb = np.abs(y - yc) - 0.6 * R
+        dzb = np.abs(z - z0) - 0.6 * R
+        inside_box = -np.maximum(np.maximum(dxb, dyb), dzb)
+        C2 = np.maximum(C2, (1.0 - C3) * tanh_profile(inside_box, alpha))
+    C1 = 1.0 - C2 - C3
+    return dict(params=p, fields=fields_from_C(C1, C2, C3, perturb, seed), membranes=mems,
+                name=f"capsule3d_{n}")
+
+
+def c3(n=256, **kw):
+    """D3Q19 at n^3 with two icosphere capsules of radius n/6.4 (40 at 256^3,
+    10 at 64^3) and 5120 triangles, bridged by C2 between them."""
+    R = n / 6.4
+    return capsule3d(n=n, R=R, subdiv=4, **kw)
+
+
+def c4(seed=SEED_BASE + 3, count=64):
+    """Batch of capsule-at-interface runs: square sides 16*U_int[6, 32], radius
+    U[12, min(48, n/4)], markers clamp(ceil(2 pi R/0.8), 64, 384), kappa_m
+    U[0.01, 0.05], shear log-U[1e-3, 1e-1], bending log-U[1e-5, 1e-3]."""
+    g = rng(seed)
+    out = []
+    for k in range(count):
+        n = 16 * int(g.integers(6, 33))
+        R = float(g.uniform(12.0, min(48.0, 0.25 * n)))
+        nm = int(min(384, max(64, math.ceil(2 * math.pi * R / 0.8))))
+        kap = g.uniform(0.01, 0.05, 3)
+        ks = float(10 ** g.uniform(-3, -1))
+        kb = float(10 ** g.uniform(-5, -3))
+        w = capsule_at_interface(nx=n, ny=n, R=R, n_markers=nm, kappa=kap, alpha=1.0, kappa_c=0.01,
+                                 kappa_s=ks, kappa_b=kb, wall_y=1, mobility=0.1, perturb=1e-4,
+                                 seed=seed * 1000 + k)
+        w["name"] = f"c4_{k}_{n}"
+        out.append(w)
+    return out
