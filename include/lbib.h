@@ -1,0 +1,170 @@
+/*
+ * lbib.h -- C ABI of the MI355X (gfx950) ternary free-energy lattice
+ * Boltzmann + immersed-boundary library.
+ *
+ * Method: Pepona, Shek, Semprebon, Krueger, Kusumaatmaja, "Modelling ternary
+ * fluids in contact with elastic membranes".  A simulation holds a lattice of
+ * three population sets f, g, h (Sec. 3.1) and any number of closed elastic
+ * membranes made of Lagrangian markers (Sec. 3.2), coupled by Peskin's
+ * four-point kernel (Sec. 3.3).  One step advances both by one time unit.
+ *
+ * Conventions (all entry points)
+ *   - Node (x, y, z) has linear index x + nx*(y + ny*z); x is periodic; y (and
+ *     z in 3D) are periodic or bounded by half-way bounce-back walls at -1/2
+ *     and n-1/2.  Marker coordinates are lattice units, node (x,y) at (x,y).
+ *   - Memory.  The caller owns every buffer.  Device memory: one workspace of
+ *     lbib_workspace_bytes() bytes, 256-byte aligned, kept alive and
+ *     untouched until lbib_destroy.  The library never allocates device
+ *     memory.  Host arrays passed in are copied before the call returns;
+ *     host arrays passed out are filled by the callee.
+ *   - Streams.  hip_stream is a hipStream_t (NULL = the default stream).
+ *     lbib_step only enqueues work; the getters synchronise the stream.
+ *     One host thread per handle; calls on one handle must not overlap.
+ *   - Errors.  Every call returns an lbib_status; no exception crosses the
+ *     ABI.  A failed call leaves the handle as it was, except LBIB_EHIP,
+ *     after which the handle should be destroyed.
+ *   - Determinism.  For fixed inputs and build, results are bitwise
+ *     reproducible on the same GPU: the only atomics are integer additions
+ *     of fixed-point values.
+ */
+#ifndef LBIB_H
+#define LBIB_H
+#include <stddef.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbib_sim lbib_sim;
+
+typedef enum {
+  LBIB_OK = 0,
+  LBIB_EINVAL = -1,      /* bad argument or parameter                          */
+  LBIB_ENOMEM = -2,      /* workspace too small, or a capacity exceeded         */
+  LBIB_EHIP = -3,        /* a HIP runtime call failed                           */
+  LBIB_ENONFINITE = -4,  /* a non-finite value was found by lbib_check          */
+  LBIB_EUNSTABLE = -5,   /* a force left the fixed-point range                  */
+  LBIB_ESTATE = -6       /* call out of order (e.g. step before set_fields)     */
+} lbib_status;
+
+enum { LBIB_D2Q9 = 0, LBIB_D3Q19 = 1 };
+/* population storage.  FP32/FP64 keep f_i - w_i, g_i and h_i (Sec. 3.1 EDF:
+   f is near its weight, g and h moving populations near zero).  The 16-bit
+   forms keep the moving populations in half or bfloat16 with the rest
+   populations f_0, g_0, h_0 in FP32. */
+enum { LBIB_FP32 = 0, LBIB_FP16 = 1, LBIB_BF16 = 2, LBIB_FP64 = 3 };
+
+typedef struct {
+  int lattice;              /* LBIB_D2Q9 (Sec. 3.1) or LBIB_D3Q19                     */
+  int nx, ny, nz;           /* nz = 1 for D2Q9                                        */
+  int wall_y, wall_z;       /* 0 periodic, 1 bounce-back walls                        */
+  double tau, tau_phi, tau_psi;   /* relaxation times, eq. RelaxationTimes (> 1/2)    */
+  double gamma_phi, gamma_psi;    /* Gamma of g^eq, h^eq, eq. EDF                     */
+  double kappa[3];          /* kappa_1..3 of eq. LandauFE                             */
+  double alpha;             /* interface width of eq. LandauFE                        */
+  double kappa_c;           /* coupling strength of eq. CouplingE                     */
+  double r_cut;             /* coupling band: beyond this distance from a membrane,
+                               the profile I of eq. Iprofile is exactly 0 or 1 and the
+                               node adds no coupling force; <= 0 selects 17 alpha     */
+  int storage;              /* LBIB_FP32, LBIB_FP16, LBIB_BF16 or LBIB_FP64           */
+  int max_markers;          /* capacity: markers over all membranes                   */
+  int max_elems;            /* capacity: triangles over all 3D membranes              */
+  int max_membranes;        /* capacity: membranes                                    */
+} lbib_params;
+
+typedef struct {
+  double mass[3];           /* sum over nodes of C1, C2, C3 (conserved)                */
+  double F_bulk;            /* sum kappa_m/2 C_m^2 (1 - C_m)^2, eq. LandauFE            */
+  double F_grad;            /* sum alpha^2 kappa_m/2 |grad C_m|^2, eq. LandauFE         */
+  double E_c;               /* kappa_c/2 sum (psi - I)^2, eq. DiscreteCE               */
+  double E_s, E_b;          /* membrane strain and bending, eqs. DiscreteSE/BE         */
+  double E_kin;             /* 1/2 sum rho |u|^2 with the bare velocity u               */
+  double p_ideal;           /* sum c_s^2 rho ln rho, the ideal-gas term of LandauFE     */
+} lbib_energies;
+
+/* Device bytes needed for a simulation with these parameters and capacities. */
+int lbib_workspace_bytes(const lbib_params* p, size_t* bytes);
+
+/* Create a simulation in the caller's workspace (see Conventions). */
+int lbib_create(const lbib_params* p, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                lbib_sim** out);
+
+/* Add a closed membrane (Sec. 3.2).  2D: a ring of n_nodes markers, segment l
+   joining markers l and l+1 (n_elems = 0, conn = NULL), counter-clockwise or
+   clockwise.  3D: a closed triangle mesh, conn = 3*n_elems vertex ids.
+   X: host, n_nodes*d doubles.  Rest lengths are the initial edge lengths.
+   kappa_s, kappa_b: the moduli of eqs. StretchingE, BendingE.
+   Must precede lbib_set_fields.  *membrane_id receives 0, 1, 2, ... */
+int lbib_add_membrane(lbib_sim* s, int n_nodes, const double* X, int n_elems, const int* conn,
+                      double kappa_s, double kappa_b, int* membrane_id);
+
+/* Initial macroscopic fields (host, N doubles each; uz may be NULL in 2D and
+   ux, uy may be NULL for a fluid at rest).  Builds the equilibrium
+   populations of eq. EDF, with the chemical potentials of Appendix A taken
+   from these fields and the membranes added so far. */
+int lbib_set_fields(lbib_sim* s, const double* rho, const double* phi, const double* psi,
+                    const double* ux, const double* uy, const double* uz);
+
+/* Enqueue n_steps time steps on the stream.  Each step: moments, coupling
+   profile I(X(t)) and coupling forces, chemical potentials (Appendix A),
+   membrane forces (eq. DiscreteTF), spreading (eq. Spreading), fused
+   collide + stream of f, g, h (eq. LBE), interpolation of the velocity at
+   t+1 (eq. Interpolation) and the Euler marker update (eq. UpdatedXl). */
+int lbib_step(lbib_sim* s, int n_steps);
+
+/* Fields at the current time (host, N doubles each, any may be NULL):
+   rho, C1 = (rho+phi-psi)/2, C2 = (rho-phi-psi)/2, C3 = psi
+   (eq. VariableTransform) and the bare velocity u = sum c_i f_i / rho
+   (eq. MomentsDFs).  Synchronises. */
+int lbib_get_fields(lbib_sim* s, double* rho, double* c1, double* c2, double* c3, double* ux,
+                    double* uy, double* uz);
+
+/* Markers of membrane id (host, n_nodes*d doubles each, any may be NULL):
+   positions X, the velocity U of the last update and the total force F of
+   the last step.  Synchronises. */
+int lbib_get_membrane(lbib_sim* s, int id, double* X, double* U, double* F);
+
+/* Energies and conserved sums at the current time, FP64.  Synchronises. */
+int lbib_energy(lbib_sim* s, lbib_energies* out);
+
+/* Finiteness check of the populations (FP64 sums): LBIB_ENONFINITE when a
+   population is NaN or infinite, LBIB_EUNSTABLE when a marker force left
+   the fixed-point range during the last steps.  Synchronises. */
+int lbib_check(lbib_sim* s);
+
+/* Device view of an internal array for zero-copy inspection:
+   field 0: population buffer holding the current state, 1: coupling profile
+   I (valid on tiles near membranes), 2: marker positions (3 doubles per
+   marker).  *elems receives the element count. */
+int lbib_device_view(lbib_sim* s, int field, void** dev_ptr, size_t* elems);
+
+/* Checkpoint: lbib_save(s, NULL, &bytes) reports the size; with a buffer of
+   at least that size it writes populations, markers and the step counter.
+   lbib_load restores a checkpoint taken from a simulation created with the
+   same parameters and membranes.  Both synchronise. */
+int lbib_save(lbib_sim* s, void* host_buf, size_t* bytes);
+int lbib_load(lbib_sim* s, const void* host_buf, size_t bytes);
+
+/* Kernel timing.  lbib_timing_enable(s, mask) clears the counters and
+   records HIP events on the stream around the phases of every following step
+   whose bit is set in mask (bit k = phase k below; 0 turns timing off);
+   lbib_timing_read synchronises and returns, for n <= 4 phases, the summed
+   milliseconds of [0] the fused lattice kernel, [1] the coupling profile
+   and tile map, [2] membrane forces and spreading, [3] interpolation and
+   marker update, and in *steps the number of steps timed. */
+int lbib_timing_enable(lbib_sim* s, int on);
+int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps);
+
+/* Number of completed steps. */
+long long lbib_steps_done(const lbib_sim* s);
+
+/* Failure injection for tests: write value into population entry idx of
+   the current buffer (field 0) or marker coordinate idx (field 2). */
+int lbib_debug_poke(lbib_sim* s, int field, long long idx, double value);
+
+const char* lbib_strerror(int status);
+void lbib_destroy(lbib_sim* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,279 @@
+// k_lb.h -- the fused lattice-Boltzmann step (Sec. 3.1) for D2Q9.
+//
+// One kernel does, per node and time step: pull-streaming of f, g, h, the
+// moments of eq. MomentsDFs, the Laplacians of rho, phi, psi, the chemical
+// potentials of Appendix A (with the coupling term of Sec. 3.1), their
+// gradients, the force of eqs. ForcingTermLBE / ForceFE plus the spread
+// membrane force, the velocities of eqs. ActualFluidVel / VelCorrection and
+// the BGK + exact-difference collision of eq. LBE, writing the post-collision
+// populations.  Populations are read once and written once per step.
+//
+// Dependency chain: the collision at row c needs grad mu at c, i.e. mu on
+// rows c-1..c+1, i.e. moments on rows c-2..c+2.  A workgroup owns a strip of
+// BX-4 interior columns (BX lanes, two halo columns each side) and marches up
+// a segment of rows with a three-stage software pipeline:
+//   iteration k:  M  pull row r = y0-2+k into registers, moments -> LDS ring
+//                 U  mu on row r-1 from the moment ring -> LDS ring
+//                 C  collide row r-2 with the populations pulled two
+//                    iterations earlier (still in registers) and store.
+// Halo columns are recomputed by the neighbouring strip; halo rows only at
+// segment ends.  Registers hold three rows of populations; the loop is
+// unrolled by three so every register index is a compile-time constant.
+//
+// Precision: moving populations and their collision use the storage's real
+// type R (FP32 or FP64).  Moments, chemical potentials, their stencils and
+// the force are FP64: the chemical potential is a sum of terms much larger
+// than itself near interfaces, and its Laplacian/gradient chain would turn
+// single-precision rounding of phi and psi into force noise.
+#pragma once
+#include <type_traits>
+
+#include "common.h"
+#include "store.h"
+
+namespace lb {
+
+struct LBParams {
+  double inv_tau, inv_tau_phi, inv_tau_psi;  // 1/tau (eq. RelaxationTimes)
+  double gphi, gpsi;                         // Gamma_phi, Gamma_psi (eq. EDF)
+  double k1, k2, k3, a2, kc;                 // kappa_m, alpha^2, kappa_c
+  int nx, ny, nz, wall_y, wall_z;
+  long long N;
+  int ntx, nty, tile;                        // tile grid of the membrane maps
+  int seg;                                   // rows (2D) or planes (3D) per workgroup
+};
+
+// mu_rho (without the ideal-gas part), mu_phi, mu_psi' from local values and
+// Laplacians.  Written through the concentrations: with
+// C1 = (rho+phi-psi)/2, C2 = (rho-phi-psi)/2, C3 = psi (eq. VariableTransform)
+// the derivative of the Landau energy (eq. LandauFE) with respect to C_m is
+// b_m = kappa_m C_m (1-C_m)(1-2C_m) - alpha^2 kappa_m lap C_m, and the chain
+// rule gives mu_rho = (b1+b2)/2, mu_phi = (b1-b2)/2, mu_psi = b3 - (b1+b2)/2;
+// the coupling energy (eq. CouplingE) adds kappa_c (psi - I) to mu_psi.
+__device__ __forceinline__ void chem_pot(const LBParams& P, double drho, double phi, double psi,
+                                         double lr, double lp, double ls, double I, double& mr,
+                                         double& mp, double& ms) {
+  const double rho = 1.0 + drho;
+  const double C1 = 0.5 * (rho + phi - psi), C2 = 0.5 * (rho - phi - psi);
+  const double L1 = 0.5 * (lr + lp - ls), L2 = 0.5 * (lr - lp - ls);
+  const double b1 = P.k1 * (C1 * (1.0 - C1) * (1.0 - 2.0 * C1) - P.a2 * L1);
+  const double b2 = P.k2 * (C2 * (1.0 - C2) * (1.0 - 2.0 * C2) - P.a2 * L2);
+  const double b3 = P.k3 * (psi * (1.0 - psi) * (1.0 - 2.0 * psi) - P.a2 * ls);
+  mr = 0.5 * (b1 + b2);
+  mp = 0.5 * (b1 - b2);
+  ms = b3 - 0.5 * (b1 + b2) + P.kc * (psi - I);
+}
+
+// BGK + exact-difference collision of one node, D2Q9, in place.  pf holds
+// f_i - w_i (all i), pg/ph the moving g_i/h_i (i >= 1), g0/h0 the rest
+// populations.  Moments and the total force (Fx, Fy) are FP64.
+template <typename R>
+__device__ __forceinline__ void collide9(const LBParams& P, R* pf, R* pg, R* ph, double& g0,
+                                         double& h0, double drho, double jx, double jy, double phi,
+                                         double psi, double mphi, double mpsi, double Fx, double Fy) {
+  using L = Lattice<9>;
+  const double rho = 1.0 + drho;
+  const double irho = 1.0 / rho;
+  const double uxd = jx * irho, uyd = jy * irho;
+  const double duxd = Fx * irho, duyd = Fy * irho;  // eq. VelCorrection
+  const R ux = (R)uxd, uy = (R)uyd;
+  const R vx = (R)(uxd + 0.5 * duxd), vy = (R)(uyd + 0.5 * duyd);  // eq. ActualFluidVel
+  const R wx = (R)(uxd + duxd), wy = (R)(uyd + duyd);
+  const R uu = ux * ux + uy * uy, ww = wx * wx + wy * wy, vv = vx * vx + vy * vy;
+  const R rr = (R)rho, dr = (R)drho, ph_ = (R)phi, ps_ = (R)psi;
+  const R gm = (R)(3.0 * P.gphi * mphi), hm = (R)(3.0 * P.gpsi * mpsi);
+  const R itf = (R)P.inv_tau, itg = (R)P.inv_tau_phi, ith = (R)P.inv_tau_psi;
+  double gsum = 0.0, hsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; i++) {
+    const R w = R(L::w(i));
+    const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy;
+    const R cw = R(L::cx[i]) * wx + R(L::cy[i]) * wy;
+    const R pu = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+    const R pw = R(3) * cw + R(4.5) * cw * cw - R(1.5) * ww;
+    const R feq = w * (dr + rr * pu);  // f^eq(rho, u) - w_i
+    const R edm = w * rr * (pw - pu);  // f^eq(rho, u + du) - f^eq(rho, u)
+    pf[i] = pf[i] - (pf[i] - feq) * itf + edm;
+    if (i > 0) {
+      const R cv = R(L::cx[i]) * vx + R(L::cy[i]) * vy;
+      const R pv = R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv;
+      const R geq = w * (gm + ph_ * pv);
+      const R heq = w * (hm + ps_ * pv);
+      gsum += (double)geq;
+      hsum += (double)heq;
+      pg[i] = pg[i] - (pg[i] - geq) * itg;
+      ph[i] = ph[i] - (ph[i] - heq) * ith;
+    }
+  }
+  // rest populations close the zeroth moments (eq. EDF, i = 0)
+  g0 = g0 - (g0 - (phi - gsum)) * P.inv_tau_phi;
+  h0 = h0 - (h0 - (psi - hsum)) * P.inv_tau_psi;
+}
+
+// pull the populations of node (x, y) at the current time: population i
+// arrives from x - c_i; across a wall it is the reversed population that
+// left (x, y) (half-way bounce-back).
+template <class St, typename R>
+__device__ __forceinline__ void pull9(const St& src, const LBParams& P, int x, int y, R* pf, R* pg,
+                                      R* ph, double& g0, double& h0) {
+  using L = Lattice<9>;
+  const long long here = (long long)y * P.nx + x;
+  pf[0] = src.template load<R>(0, 0, here);
+  g0 = src.rest(1, here);
+  h0 = src.rest(2, here);
+#pragma unroll
+  for (int i = 1; i < 9; i++) {
+    const int sy = y - L::cy[i];
+    long long node;
+    int dir = i;
+    if (P.wall_y && (sy < 0 || sy >= P.ny)) {
+      node = here;
+      dir = L::opp[i];
+    } else {
+      node = (long long)wrap(sy, P.ny) * P.nx + wrap(x - L::cx[i], P.nx);
+    }
+    pf[i] = src.template load<R>(0, dir, node);
+    pg[i] = src.template load<R>(1, dir, node);
+    ph[i] = src.template load<R>(2, dir, node);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void moments9(const R* pf, const R* pg, const R* ph, double g0, double h0,
+                                         double& d, double& jx, double& jy, double& phi,
+                                         double& psi) {
+  using L = Lattice<9>;
+  d = 0.0;
+  jx = 0.0;
+  jy = 0.0;
+  phi = g0;
+  psi = h0;
+#pragma unroll
+  for (int i = 0; i < 9; i++) {
+    const double f = (double)pf[i];
+    d += f;
+    jx += L::cx[i] * f;
+    jy += L::cy[i] * f;
+    if (i > 0) {
+      phi += (double)pg[i];
+      psi += (double)ph[i];
+    }
+  }
+}
+
+template <class St, typename R, int BX>
+__global__ __launch_bounds__(BX) void k_lb2d(St src, St dst, LBParams P,
+                                             const int* __restrict__ tflag,
+                                             const double* __restrict__ Ifield,
+                                             long long* __restrict__ fib,
+                                             double* __restrict__ force) {
+  constexpr int W = BX - 4;
+  __shared__ double s_m[3][3][BX];  // moment ring [slot][drho, phi, psi][lane]
+  __shared__ double s_u[3][3][BX];  // chemical-potential ring [slot][mu_rho, mu_phi, mu_psi'][lane]
+
+  const int j = threadIdx.x;
+  const int xc = (int)blockIdx.x * W - 2 + j;
+  const int x = wrap(xc, P.nx);
+  const bool interior = (j >= 2) && (j < BX - 2) && (xc < P.nx);
+  const int y0 = (int)blockIdx.y * P.seg;
+  const int y1 = min(y0 + P.seg, P.ny);
+  const int K = (y1 - y0) + 4;
+
+  R pf[3][9], pg[3][9], ph[3][9];
+  double g0[3], h0[3];
+
+  auto body = [&](auto slot_c, int k) {
+    constexpr int S = decltype(slot_c)::value;
+    constexpr int SC = (S + 1) % 3;
+    const int r = y0 - 2 + k;
+    // ---- M: pull row r, moments -> ring slot k%3
+    {
+      const int ry = fd_row(r, P.ny, P.wall_y);
+      pull9(src, P, x, ry, pf[S], pg[S], ph[S], g0[S], h0[S]);
+      double d, jx, jy, phi, psi;
+      moments9(pf[S], pg[S], ph[S], g0[S], h0[S], d, jx, jy, phi, psi);
+      const int sl = k % 3;
+      s_m[sl][0][j] = d;
+      s_m[sl][1][j] = phi;
+      s_m[sl][2][j] = psi;
+    }
+    __syncthreads();
+    // ---- U: chemical potentials on row r-1 -> ring slot k%3
+    if (k >= 2 && j >= 1 && j < BX - 1) {
+      const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // rows r-2, r-1, r
+      double lap[3], ctr[3];
+#pragma unroll
+      for (int f = 0; f < 3; f++) {
+        const double q = s_m[b][f][j];
+        const double n4 = (s_m[b][f][j - 1] - q) + (s_m[b][f][j + 1] - q) + (s_m[a][f][j] - q) +
+                          (s_m[c][f][j] - q);
+        const double n8 = (s_m[a][f][j - 1] - q) + (s_m[a][f][j + 1] - q) +
+                          (s_m[c][f][j - 1] - q) + (s_m[c][f][j + 1] - q);
+        // lap q = 6 sum_i w_i (q(x + c_i) - q(x)) with the D2Q9 weights
+        lap[f] = (2.0 / 3.0) * n4 + (1.0 / 6.0) * n8;
+        ctr[f] = q;
+      }
+      const int qy = fd_row(r - 1, P.ny, P.wall_y);
+      double I = 0.0;
+      if (tflag[(qy / P.tile) * P.ntx + x / P.tile]) I = Ifield[(long long)qy * P.nx + x];
+      double mr, mp, ms;
+      chem_pot(P, ctr[0], ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
+      const int sl = k % 3;
+      s_u[sl][0][j] = mr;
+      s_u[sl][1][j] = mp;
+      s_u[sl][2][j] = ms;
+    }
+    __syncthreads();
+    // ---- C: collide row r-2 with the registers of slot SC
+    if (k >= 4 && interior) {
+      const int cy = r - 2;
+      const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // mu rows cy-1, cy, cy+1
+      double d, jx, jy, phi, psi;
+      moments9(pf[SC], pg[SC], ph[SC], g0[SC], h0[SC], d, jx, jy, phi, psi);
+      // grad mu = 3 sum_i w_i c_i mu(x + c_i)
+      double gx[3], gy[3];
+#pragma unroll
+      for (int f = 0; f < 3; f++) {
+        const double e = s_u[b][f][j + 1], wv = s_u[b][f][j - 1];
+        const double nn = s_u[c][f][j], ss = s_u[a][f][j];
+        const double ne = s_u[c][f][j + 1], nw = s_u[c][f][j - 1];
+        const double se = s_u[a][f][j + 1], sw = s_u[a][f][j - 1];
+        gx[f] = (1.0 / 3.0) * (e - wv) + (1.0 / 12.0) * ((ne - nw) + (se - sw));
+        gy[f] = (1.0 / 3.0) * (nn - ss) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
+      }
+      const double rho = 1.0 + d;
+      // thermodynamic force, eq. ForceFE with eq. GradPT (potential form)
+      double Fx = -(rho * gx[0] + phi * gx[1] + psi * gx[2]);
+      double Fy = -(rho * gy[0] + phi * gy[1] + psi * gy[2]);
+      const long long node = (long long)cy * P.nx + x;
+      if (tflag[(cy / P.tile) * P.ntx + x / P.tile]) {
+        long long* fp = fib + 2 * node;
+        Fx += from_fix(fp[0]);
+        Fy += from_fix(fp[1]);
+        fp[0] = 0;
+        fp[1] = 0;
+        force[2 * node] = Fx;
+        force[2 * node + 1] = Fy;
+      }
+      collide9(P, pf[SC], pg[SC], ph[SC], g0[SC], h0[SC], d, jx, jy, phi, psi, s_u[b][1][j],
+               s_u[b][2][j], Fx, Fy);
+      dst.template store<R>(0, 0, node, pf[SC][0]);
+      dst.store_rest(1, node, g0[SC]);
+      dst.store_rest(2, node, h0[SC]);
+#pragma unroll
+      for (int i = 1; i < 9; i++) {
+        dst.template store<R>(0, i, node, pf[SC][i]);
+        dst.template store<R>(1, i, node, pg[SC][i]);
+        dst.template store<R>(2, i, node, ph[SC][i]);
+      }
+    }
+  };
+
+  for (int kb = 0; kb < K; kb += 3) {
+    body(std::integral_constant<int, 0>{}, kb);
+    if (kb + 1 < K) body(std::integral_constant<int, 1>{}, kb + 1);
+    if (kb + 2 < K) body(std::integral_constant<int, 2>{}, kb + 2);
+  }
+}
+
+}  // namespace lb

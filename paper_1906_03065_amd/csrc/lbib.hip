@@ -1,0 +1,744 @@
+// lbib.hip -- host runtime and C ABI of the gfx950 ternary LB + IBM library.
+//
+// A simulation is an Engine<Store, Real> living inside the caller's device
+// workspace.  The runtime carves the workspace, validates inputs, uploads
+// membranes and initial fields, and enqueues the per-step kernel sequence
+// (Sec. 3.3 ordering):
+//   k_tiles       bounding boxes of the membranes at X(t), active-tile map
+//   k_coupling    coupling profile I(X(t)) and coupling forces (needs psi(t))
+//   k_memforce    strain + bending + coupling force per marker (FP64)
+//   k_spread      marker forces onto the lattice (fixed-point atomics)
+//   k_lb          fused pull-stream / moments / mu / force / collide
+//   k_interp      v at t+1 interpolated at X(t), Euler update X(t+1)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbib.h"
+#include "common.h"
+#include "k_ibm.h"
+#include "k_lb.h"
+#include "k_misc.h"
+#include "store.h"
+
+using namespace lb;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+#define HIPCHK(call)                         \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return LBIB_EHIP;  \
+  } while (0)
+
+struct Layout {
+  size_t pops[2];       // population buffers A, B
+  size_t pop_bytes;     // bytes of one buffer
+  size_t Ifield, fib, force, tflag, tlist, tcount, stage, part;
+  size_t X, U, F, Facc, rest, moff, mid, ks, kb, mbox, status, memE;
+  size_t total;
+  long long ntiles;
+  int ntx, nty, ntz, tile;
+};
+
+long long pop_bytes_per_node(int Q, int storage) {
+  switch (storage) {
+    case LBIB_FP32: return (3LL * Q - 2) * 4 + 2 * 8;  // FP32 with FP64 g_0, h_0
+    case LBIB_FP64: return 3LL * Q * 8;
+    default: return 3LL * (Q - 1) * 2 + 3LL * 4;       // 16-bit moving + FP32 rest
+  }
+}
+
+int validate(const lbib_params* p) {
+  if (!p) return LBIB_EINVAL;
+  if (p->lattice != LBIB_D2Q9 && p->lattice != LBIB_D3Q19) return LBIB_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LBIB_EINVAL;
+  if (p->lattice == LBIB_D2Q9 && p->nz != 1) return LBIB_EINVAL;
+  if (p->wall_y && p->ny < 2) return LBIB_EINVAL;
+  if (p->lattice == LBIB_D3Q19 && p->wall_z && p->nz < 2) return LBIB_EINVAL;
+  if (!(p->tau > 0.5) || !(p->tau_phi > 0.5) || !(p->tau_psi > 0.5)) return LBIB_EINVAL;
+  if (!(p->alpha > 0.0) || !(p->kappa_c >= 0.0)) return LBIB_EINVAL;
+  if (p->storage < 0 || p->storage > 3) return LBIB_EINVAL;
+  if (p->max_markers < 0 || p->max_elems < 0 || p->max_membranes < 0) return LBIB_EINVAL;
+  if ((long long)p->nx * p->ny * p->nz > (1LL << 40)) return LBIB_EINVAL;
+  if (p->lattice == LBIB_D3Q19) return LBIB_EINVAL;  // D3Q19 engine not built in this library
+  return LBIB_OK;
+}
+
+Layout make_layout(const lbib_params* p) {
+  Layout L{};
+  const int Q = p->lattice == LBIB_D2Q9 ? 9 : 19;
+  const int D = p->lattice == LBIB_D2Q9 ? 2 : 3;
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  L.tile = D == 2 ? TILE2 : 8;
+  L.ntx = (p->nx + L.tile - 1) / L.tile;
+  L.nty = (p->ny + L.tile - 1) / L.tile;
+  L.ntz = D == 3 ? (p->nz + L.tile - 1) / L.tile : 1;
+  L.ntiles = (long long)L.ntx * L.nty * L.ntz;
+  const int M = std::max(p->max_markers, 1), K = std::max(p->max_membranes, 1);
+  Carver c{nullptr};
+  L.pop_bytes = (size_t)(pop_bytes_per_node(Q, p->storage) * N);
+  // 16-bit storage keeps the rest planes behind the moving planes
+  L.pops[0] = c.take(L.pop_bytes + 2 * kAlign);
+  L.pops[1] = c.take(L.pop_bytes + 2 * kAlign);
+  L.Ifield = c.take((size_t)N * 8);
+  L.fib = c.take((size_t)N * D * 8);
+  L.force = c.take((size_t)N * D * 8);
+  L.tflag = c.take((size_t)L.ntiles * 4);
+  L.tlist = c.take((size_t)L.ntiles * 4);
+  L.tcount = c.take(64);
+  L.stage = c.take((size_t)N * 8 * 8);
+  L.part = c.take((size_t)((N + 255) / 256 + 1) * 8 * 8 + (size_t)M * 2 * 8);
+  L.X = c.take((size_t)M * 3 * 8);
+  L.U = c.take((size_t)M * 3 * 8);
+  L.F = c.take((size_t)M * 3 * 8);
+  L.Facc = c.take((size_t)M * 3 * 8);
+  L.rest = c.take((size_t)M * 8);
+  L.moff = c.take((size_t)(K + 1) * 4);
+  L.mid = c.take((size_t)M * 4);
+  L.ks = c.take((size_t)K * 8);
+  L.kb = c.take((size_t)K * 8);
+  L.mbox = c.take((size_t)K * 6 * 8);
+  L.status = c.take(64);
+  L.memE = c.take(64);
+  L.total = c.off;
+  return L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct lbib_sim {
+  lbib_params p{};
+  Layout L{};
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int Q = 9, D = 2;
+  long long N = 0;
+  int cur = 0;  // index of the buffer holding the current state
+  bool ready = false;
+  long long steps = 0;
+  int K = 0, M = 0;
+  std::vector<int> moff{0};
+  double r_cut = 0;
+  int bx = 64, seg = 64;  // fused-kernel launch shape
+  // optional per-phase timing with HIP events on the stream
+  int timing = 0;  // bit mask of timed phases
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
+  size_t ev_used = 0;
+  int timed_steps = 0;
+  double timed_ms[4] = {0, 0, 0, 0};
+  hipEvent_t ev() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+  // begin a timed phase: returns the start event (or null when not timing)
+  hipEvent_t tbeg(int phase) {
+    if (!(timing >> phase & 1)) return nullptr;
+    hipEvent_t e = ev();
+    if (e) (void)hipEventRecord(e, stream);
+    return e;
+  }
+  void tend(int phase, hipEvent_t start) {
+    if (!start) return;
+    hipEvent_t e = ev();
+    if (!e) return;
+    (void)hipEventRecord(e, stream);
+    ev_open.push_back({phase, {start, e}});
+  }
+  int timing_flush() {
+    if (ev_open.empty()) return LBIB_OK;
+    if (hipStreamSynchronize(stream) != hipSuccess) return LBIB_EHIP;
+    for (auto& q : ev_open) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, q.second.first, q.second.second) != hipSuccess) return LBIB_EHIP;
+      timed_ms[q.first] += ms;
+    }
+    ev_open.clear();
+    ev_used = 0;
+    return LBIB_OK;
+  }
+  virtual ~lbib_sim() {
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+  }
+  virtual void setup() = 0;
+  virtual int init(const double* stage_dev) = 0;
+  virtual int step() = 0;
+  virtual int moments(double* out_dev) = 0;
+  virtual int energy_nodes(double* part, long long* nblk) = 0;
+  virtual int coupling(int want_force) = 0;
+  virtual int check(int* bad_dev) = 0;
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  MemDev memdev() const {
+    MemDev m;
+    m.X = at<double>(L.X);
+    m.U = at<double>(L.U);
+    m.F = at<double>(L.F);
+    m.Facc = at<long long>(L.Facc);
+    m.rest = at<double>(L.rest);
+    m.moff = at<int>(L.moff);
+    m.mid = at<int>(L.mid);
+    m.ks = at<double>(L.ks);
+    m.kb = at<double>(L.kb);
+    m.mbox = at<double>(L.mbox);
+    m.status = at<int>(L.status);
+    m.K = K;
+    m.M = M;
+    return m;
+  }
+  TileMap tilemap() const {
+    TileMap t;
+    t.tflag = at<int>(L.tflag);
+    t.tlist = at<int>(L.tlist);
+    t.tcount = at<int>(L.tcount);
+    t.ntx = L.ntx;
+    t.nty = L.nty;
+    t.ntz = L.ntz;
+    t.tile = L.tile;
+    return t;
+  }
+};
+
+namespace {
+
+template <class St>
+St make_store(char* base, long long N);
+template <>
+PlainStore<float, 9> make_store<PlainStore<float, 9>>(char* base, long long N) {
+  return PlainStore<float, 9>{reinterpret_cast<float*>(base), N};
+}
+template <>
+MixStore<9> make_store<MixStore<9>>(char* base, long long N) {
+  size_t fl = align_up((size_t)(MixStore<9>::float_planes() * N * 4));
+  return MixStore<9>{reinterpret_cast<float*>(base), reinterpret_cast<double*>(base + fl), N};
+}
+template <>
+PlainStore<double, 9> make_store<PlainStore<double, 9>>(char* base, long long N) {
+  return PlainStore<double, 9>{reinterpret_cast<double*>(base), N};
+}
+template <>
+Split16Store<__half, 9> make_store<Split16Store<__half, 9>>(char* base, long long N) {
+  size_t mov = align_up((size_t)(3LL * 8 * N * 2));
+  return Split16Store<__half, 9>{reinterpret_cast<__half*>(base), reinterpret_cast<float*>(base + mov), N};
+}
+template <>
+Split16Store<__hip_bfloat16, 9> make_store<Split16Store<__hip_bfloat16, 9>>(char* base, long long N) {
+  size_t mov = align_up((size_t)(3LL * 8 * N * 2));
+  return Split16Store<__hip_bfloat16, 9>{reinterpret_cast<__hip_bfloat16*>(base),
+                                         reinterpret_cast<float*>(base + mov), N};
+}
+
+template <class St, typename R>
+struct Engine2D final : lbib_sim {
+  LBParams P{};
+  St store(int which) const { return make_store<St>(ws + L.pops[which], N); }
+
+  void setup() override {
+    P.inv_tau = (1.0 / p.tau);
+    P.inv_tau_phi = (1.0 / p.tau_phi);
+    P.inv_tau_psi = (1.0 / p.tau_psi);
+    P.gphi = p.gamma_phi;
+    P.gpsi = p.gamma_psi;
+    P.k1 = p.kappa[0];
+    P.k2 = p.kappa[1];
+    P.k3 = p.kappa[2];
+    P.a2 = p.alpha * p.alpha;
+    P.kc = p.kappa_c;
+    P.nx = p.nx;
+    P.ny = p.ny;
+    P.nz = 1;
+    P.wall_y = p.wall_y;
+    P.wall_z = 0;
+    P.N = N;
+    P.ntx = L.ntx;
+    P.nty = L.nty;
+    P.tile = L.tile;
+    P.seg = seg;
+  }
+
+  CoupArgs coup_args(int want_force) const {
+    CoupArgs c;
+    c.nx = p.nx;
+    c.ny = p.ny;
+    c.wall_y = p.wall_y;
+    c.alpha = p.alpha;
+    c.kappa_c = p.kappa_c;
+    c.r_cut = r_cut;
+    c.want_force = want_force;
+    return c;
+  }
+
+  int coupling(int want_force) override {
+    if (K == 0) return LBIB_OK;
+    MemDev md = memdev();
+    TileMap tm = tilemap();
+    hipLaunchKernelGGL(k_tiles<1024>, dim3(1), dim3(1024), 0, stream, md, tm, p.nx, p.ny, 1,
+                       p.wall_y, 0, 2, r_cut + 3.0);
+    const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 2048);
+    hipLaunchKernelGGL((k_coupling2d<St, R, COUP_THREADS>), dim3(grid), dim3(COUP_THREADS), 0, stream,
+                       md, tm, coup_args(want_force), at<double>(L.Ifield), store(cur));
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  void launch_lb(St src, St dst) {
+    P.seg = seg;
+    const int W = bx - 4;
+    dim3 grid((p.nx + W - 1) / W, (p.ny + seg - 1) / seg);
+    const int* tf = at<int>(L.tflag);
+    const double* If = at<double>(L.Ifield);
+    long long* fib = at<long long>(L.fib);
+    double* frc = at<double>(L.force);
+    switch (bx) {
+      case 128:
+        hipLaunchKernelGGL((k_lb2d<St, R, 128>), grid, dim3(128), 0, stream, src, dst, P, tf, If, fib, frc);
+        break;
+      case 256:
+        hipLaunchKernelGGL((k_lb2d<St, R, 256>), grid, dim3(256), 0, stream, src, dst, P, tf, If, fib, frc);
+        break;
+      default:
+        hipLaunchKernelGGL((k_lb2d<St, R, 64>), grid, dim3(64), 0, stream, src, dst, P, tf, If, fib, frc);
+    }
+  }
+
+  int step() override {
+    MemDev md = memdev();
+    const int mb = (M + 255) / 256;
+    if (K > 0) {
+      hipEvent_t t0 = tbeg(1);
+      int rc = coupling(1);
+      if (rc) return rc;
+      tend(1, t0);
+      t0 = tbeg(2);
+      hipLaunchKernelGGL(k_memforce2d, dim3(mb), dim3(256), 0, stream, md);
+      hipLaunchKernelGGL(k_spread2d, dim3(mb), dim3(256), 0, stream, md, at<long long>(L.fib), p.nx,
+                         p.ny, p.wall_y);
+      tend(2, t0);
+    }
+    hipEvent_t t1 = tbeg(0);
+    launch_lb(store(cur), store(1 - cur));
+    tend(0, t1);
+    if (K > 0) {
+      hipEvent_t t2 = tbeg(3);
+      hipLaunchKernelGGL((k_interp2d<St, R>), dim3(mb), dim3(256), 0, stream, md, store(1 - cur), P,
+                         (const double*)at<double>(L.force));
+      tend(3, t2);
+    }
+    cur = 1 - cur;
+    if (timing) {
+      timed_steps++;
+      if (ev_used > 4096) {
+        int rc = timing_flush();
+        if (rc) return rc;
+      }
+    }
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int init(const double* st) override {
+    int rc = coupling(0);
+    if (rc) return rc;
+    const int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL((k_init2d<St, R>), dim3(nb), dim3(256), 0, stream, store(cur), P, st, st + N,
+                       st + 2 * N, st + 3 * N, st + 4 * N, (const int*)at<int>(L.tflag),
+                       (const double*)at<double>(L.Ifield));
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int moments(double* out) override {
+    const int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL((k_moments2d<St, R>), dim3(nb), dim3(256), 0, stream, store(cur), P, out);
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int energy_nodes(double* part, long long* nblk) override {
+    const long long nb = (N + 255) / 256;
+    hipLaunchKernelGGL((k_energy_nodes2d<256>), dim3((unsigned)nb), dim3(256), 0, stream, P,
+                       (const double*)at<double>(L.stage), (const int*)at<int>(L.tflag),
+                       (const double*)at<double>(L.Ifield), part);
+    *nblk = nb;
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int check(int* bad) override {
+    const int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL((k_check<St, R, 256>), dim3(nb), dim3(256), 0, stream, store(cur), N, 9, bad);
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+};
+
+lbib_sim* make_engine(const lbib_params* p) {
+  if (p->lattice == LBIB_D2Q9) {
+    switch (p->storage) {
+      case LBIB_FP32: return new (std::nothrow) Engine2D<MixStore<9>, float>();
+      case LBIB_FP64: return new (std::nothrow) Engine2D<PlainStore<double, 9>, double>();
+      case LBIB_FP16: return new (std::nothrow) Engine2D<Split16Store<__half, 9>, float>();
+      case LBIB_BF16: return new (std::nothrow) Engine2D<Split16Store<__hip_bfloat16, 9>, float>();
+    }
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+extern "C" {
+
+int lbib_workspace_bytes(const lbib_params* p, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) return LBIB_EINVAL;
+  *bytes = make_layout(p).total;
+  return LBIB_OK;
+}
+
+int lbib_create(const lbib_params* p, void* ws, size_t ws_bytes, void* stream, lbib_sim** out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!ws || !out || ((uintptr_t)ws % kAlign) != 0) return LBIB_EINVAL;
+  Layout L = make_layout(p);
+  if (ws_bytes < L.total) return LBIB_ENOMEM;
+  lbib_sim* s = make_engine(p);
+  if (!s) return LBIB_ENOMEM;
+  s->p = *p;
+  s->L = L;
+  s->ws = (char*)ws;
+  s->stream = (hipStream_t)stream;
+  s->Q = p->lattice == LBIB_D2Q9 ? 9 : 19;
+  s->D = p->lattice == LBIB_D2Q9 ? 2 : 3;
+  s->N = (long long)p->nx * p->ny * p->nz;
+  s->r_cut = p->r_cut > 0 ? p->r_cut : 17.0 * p->alpha;
+  s->bx = 64;
+  s->seg = std::max(4, std::min(p->ny, 64));
+  s->setup();
+  // zero the maps, accumulators and counters (fill kernels would do as well;
+  // memset is only used here, outside any step)
+  hipStream_t st = s->stream;
+  if (hipMemsetAsync(s->ws + L.fib, 0, (size_t)s->N * s->D * 8, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.tflag, 0, (size_t)L.ntiles * 4, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.tcount, 0, 64, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.Facc, 0, (size_t)std::max(p->max_markers, 1) * 3 * 8, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.status, 0, 64, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.force, 0, (size_t)s->N * s->D * 8, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.moff, 0, 4, st) != hipSuccess) {
+    delete s;
+    return LBIB_EHIP;
+  }
+  *out = s;
+  return LBIB_OK;
+}
+
+int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const int* conn, double ks,
+                      double kb, int* id) {
+  if (!s || !X || n < 3) return LBIB_EINVAL;
+  if (s->ready) return LBIB_ESTATE;
+  if (s->D == 2 && (n_elems != 0 || conn)) return LBIB_EINVAL;
+  if (!(ks >= 0) || !(kb >= 0)) return LBIB_EINVAL;
+  if (s->K + 1 > s->p.max_membranes || s->M + n > s->p.max_markers) return LBIB_ENOMEM;
+  for (int i = 0; i < n * s->D; i++)
+    if (!std::isfinite(X[i])) return LBIB_EINVAL;
+  std::vector<double> X3((size_t)3 * n, 0.0), rest(n);
+  for (int l = 0; l < n; l++)
+    for (int a = 0; a < s->D; a++) X3[3 * l + a] = X[(size_t)l * s->D + a];
+  for (int l = 0; l < n; l++) {
+    const int m = (l + 1) % n;
+    rest[l] = std::hypot(X3[3 * m] - X3[3 * l], X3[3 * m + 1] - X3[3 * l + 1]);
+    if (!(rest[l] > 0)) return LBIB_EINVAL;
+  }
+  std::vector<int> mid(n, s->K);
+  const int off = s->M;
+  hipStream_t st = s->stream;
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.X + (size_t)off * 24, X3.data(), (size_t)n * 24, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(s->ws + s->L.U + (size_t)off * 24, 0, (size_t)n * 24, st));
+  HIPCHK(hipMemsetAsync(s->ws + s->L.F + (size_t)off * 24, 0, (size_t)n * 24, st));
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.rest + (size_t)off * 8, rest.data(), (size_t)n * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.mid + (size_t)off * 4, mid.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.ks + (size_t)s->K * 8, &ks, 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.kb + (size_t)s->K * 8, &kb, 8, hipMemcpyHostToDevice, st));
+  s->moff.push_back(off + n);
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.moff, s->moff.data(), s->moff.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // host vectors go out of scope
+  if (id) *id = s->K;
+  s->K += 1;
+  s->M += n;
+  return LBIB_OK;
+}
+
+int lbib_set_fields(lbib_sim* s, const double* rho, const double* phi, const double* psi,
+                    const double* ux, const double* uy, const double* uz) {
+  if (!s || !rho || !phi || !psi) return LBIB_EINVAL;
+  (void)uz;
+  const long long N = s->N;
+  for (long long n = 0; n < N; n++)
+    if (!(rho[n] > 0) || !std::isfinite(phi[n]) || !std::isfinite(psi[n])) return LBIB_EINVAL;
+  double* stage = s->at<double>(s->L.stage);
+  hipStream_t st = s->stream;
+  HIPCHK(hipMemcpyAsync(stage, rho, N * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(stage + N, phi, N * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(stage + 2 * N, psi, N * 8, hipMemcpyHostToDevice, st));
+  if (ux)
+    HIPCHK(hipMemcpyAsync(stage + 3 * N, ux, N * 8, hipMemcpyHostToDevice, st));
+  else
+    HIPCHK(hipMemsetAsync(stage + 3 * N, 0, N * 8, st));
+  if (uy)
+    HIPCHK(hipMemcpyAsync(stage + 4 * N, uy, N * 8, hipMemcpyHostToDevice, st));
+  else
+    HIPCHK(hipMemsetAsync(stage + 4 * N, 0, N * 8, st));
+  s->cur = 0;
+  int rc = s->init(stage);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  s->ready = true;
+  s->steps = 0;
+  return LBIB_OK;
+}
+
+int lbib_step(lbib_sim* s, int n) {
+  if (!s || n < 0) return LBIB_EINVAL;
+  if (!s->ready) return LBIB_ESTATE;
+  for (int k = 0; k < n; k++) {
+    int rc = s->step();
+    if (rc) return rc;
+    s->steps++;
+  }
+  return LBIB_OK;
+}
+
+long long lbib_steps_done(const lbib_sim* s) { return s ? s->steps : -1; }
+
+int lbib_timing_enable(lbib_sim* s, int on) {
+  if (!s) return LBIB_EINVAL;
+  int rc = s->timing_flush();
+  if (rc) return rc;
+  s->timing = on & 15;
+  s->timed_steps = 0;
+  for (double& v : s->timed_ms) v = 0;
+  return LBIB_OK;
+}
+
+int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps) {
+  if (!s || n < 0 || n > 4 || (n > 0 && !ms)) return LBIB_EINVAL;
+  int rc = s->timing_flush();
+  if (rc) return rc;
+  for (int k = 0; k < n; k++) ms[k] = s->timed_ms[k];
+  if (steps) *steps = s->timed_steps;
+  return LBIB_OK;
+}
+
+int lbib_get_fields(lbib_sim* s, double* rho, double* c1, double* c2, double* c3, double* ux,
+                    double* uy, double* uz) {
+  if (!s) return LBIB_EINVAL;
+  if (!s->ready) return LBIB_ESTATE;
+  (void)uz;
+  double* stage = s->at<double>(s->L.stage);
+  int rc = s->moments(stage);
+  if (rc) return rc;
+  const long long N = s->N;
+  double* outs[6] = {rho, c1, c2, c3, ux, uy};
+  for (int k = 0; k < 6; k++)
+    if (outs[k]) HIPCHK(hipMemcpyAsync(outs[k], stage + k * N, N * 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return LBIB_OK;
+}
+
+int lbib_get_membrane(lbib_sim* s, int id, double* X, double* U, double* F) {
+  if (!s || id < 0 || id >= s->K) return LBIB_EINVAL;
+  const int b = s->moff[id], n = s->moff[id + 1] - b;
+  std::vector<double> buf((size_t)3 * n);
+  const size_t offs[3] = {s->L.X, s->L.U, s->L.F};
+  double* outs[3] = {X, U, F};
+  for (int k = 0; k < 3; k++) {
+    if (!outs[k]) continue;
+    HIPCHK(hipMemcpyAsync(buf.data(), s->ws + offs[k] + (size_t)b * 24, (size_t)n * 24, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int l = 0; l < n; l++)
+      for (int a = 0; a < s->D; a++) outs[k][(size_t)l * s->D + a] = buf[3 * l + a];
+  }
+  return LBIB_OK;
+}
+
+int lbib_energy(lbib_sim* s, lbib_energies* out) {
+  if (!s || !out) return LBIB_EINVAL;
+  if (!s->ready) return LBIB_ESTATE;
+  double* stage = s->at<double>(s->L.stage);
+  double* part = s->at<double>(s->L.part);
+  int rc = s->coupling(0);  // profile I at the current markers
+  if (rc) return rc;
+  rc = s->moments(stage);
+  if (rc) return rc;
+  long long nblk = 0;
+  rc = s->energy_nodes(part, &nblk);
+  if (rc) return rc;
+  double* sums = s->at<double>(s->L.memE);
+  hipLaunchKernelGGL(k_sum_rows<256>, dim3(1), dim3(256), 0, s->stream, (const double*)part, nblk, 8, sums);
+  double host[8];
+  HIPCHK(hipMemcpyAsync(host, sums, 64, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < 3; k++) out->mass[k] = host[k];
+  out->F_bulk = host[3];
+  out->F_grad = host[4];
+  out->E_c = host[5];
+  out->E_kin = host[6];
+  out->p_ideal = host[7];
+  out->E_s = out->E_b = 0.0;
+  if (s->K > 0) {
+    double* me = part + ((s->N + 255) / 256 + 1) * 8;
+    MemDev md = s->memdev();
+    hipLaunchKernelGGL(k_memenergy2d, dim3((s->M + 255) / 256), dim3(256), 0, s->stream, md, me);
+    hipLaunchKernelGGL(k_sum_rows<256>, dim3(1), dim3(256), 0, s->stream, (const double*)me,
+                       (long long)s->M, 2, sums);
+    double h2[2];
+    HIPCHK(hipMemcpyAsync(h2, sums, 16, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    out->E_s = h2[0];
+    out->E_b = h2[1];
+  }
+  return LBIB_OK;
+}
+
+int lbib_check(lbib_sim* s) {
+  if (!s) return LBIB_EINVAL;
+  if (!s->ready) return LBIB_ESTATE;
+  int* st = s->at<int>(s->L.status);
+  HIPCHK(hipMemsetAsync(st + 8, 0, 4, s->stream));
+  int rc = s->check(st + 8);
+  if (rc) return rc;
+  int host[9];
+  HIPCHK(hipMemcpyAsync(host, st, 36, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  if (host[8]) return LBIB_ENONFINITE;
+  if (host[0] || host[1]) return LBIB_EUNSTABLE;
+  return LBIB_OK;
+}
+
+int lbib_device_view(lbib_sim* s, int field, void** ptr, size_t* elems) {
+  if (!s || !ptr || !elems) return LBIB_EINVAL;
+  switch (field) {
+    case 0:
+      *ptr = s->ws + s->L.pops[s->cur];
+      *elems = s->L.pop_bytes;
+      return LBIB_OK;
+    case 1:
+      *ptr = s->ws + s->L.Ifield;
+      *elems = (size_t)s->N;
+      return LBIB_OK;
+    case 2:
+      *ptr = s->ws + s->L.X;
+      *elems = (size_t)s->M * 3;
+      return LBIB_OK;
+  }
+  return LBIB_EINVAL;
+}
+
+int lbib_save(lbib_sim* s, void* buf, size_t* bytes) {
+  if (!s || !bytes) return LBIB_EINVAL;
+  if (!s->ready) return LBIB_ESTATE;
+  const size_t need = 16 + s->L.pop_bytes + (size_t)s->M * 24 * 3;
+  if (!buf) {
+    *bytes = need;
+    return LBIB_OK;
+  }
+  if (*bytes < need) return LBIB_ENOMEM;
+  char* o = (char*)buf;
+  long long hdr[2] = {s->steps, (long long)s->M};
+  memcpy(o, hdr, 16);
+  HIPCHK(hipMemcpyAsync(o + 16, s->ws + s->L.pops[s->cur], s->L.pop_bytes, hipMemcpyDeviceToHost, s->stream));
+  const size_t offs[3] = {s->L.X, s->L.U, s->L.F};
+  for (int k = 0; k < 3; k++)
+    HIPCHK(hipMemcpyAsync(o + 16 + s->L.pop_bytes + (size_t)k * s->M * 24, s->ws + offs[k],
+                          (size_t)s->M * 24, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  *bytes = need;
+  return LBIB_OK;
+}
+
+int lbib_load(lbib_sim* s, const void* buf, size_t bytes) {
+  if (!s || !buf) return LBIB_EINVAL;
+  const size_t need = 16 + s->L.pop_bytes + (size_t)s->M * 24 * 3;
+  if (bytes < need) return LBIB_EINVAL;
+  const char* o = (const char*)buf;
+  long long hdr[2];
+  memcpy(hdr, o, 16);
+  if (hdr[1] != s->M) return LBIB_EINVAL;
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.pops[s->cur], o + 16, s->L.pop_bytes, hipMemcpyHostToDevice, s->stream));
+  const size_t offs[3] = {s->L.X, s->L.U, s->L.F};
+  for (int k = 0; k < 3; k++)
+    HIPCHK(hipMemcpyAsync(s->ws + offs[k], o + 16 + s->L.pop_bytes + (size_t)k * s->M * 24,
+                          (size_t)s->M * 24, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->steps = hdr[0];
+  s->ready = true;
+  return LBIB_OK;
+}
+
+int lbib_debug_poke(lbib_sim* s, int field, long long idx, double value) {
+  if (!s) return LBIB_EINVAL;
+  if (field == 2) {
+    if (idx < 0 || idx >= (long long)s->M * 3) return LBIB_EINVAL;
+    HIPCHK(hipMemcpyAsync(s->ws + s->L.X + idx * 8, &value, 8, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LBIB_OK;
+  }
+  if (field == 0) {
+    // entry idx of the current buffer: FP32 planes (FP32 / 16-bit rest planes)
+    // or FP64 planes (FP64 storage), in the storage's plane order
+    char* base = s->ws + s->L.pops[s->cur];
+    if (s->p.storage == LBIB_FP64) {
+      if (idx < 0 || idx >= 3LL * s->Q * s->N) return LBIB_EINVAL;
+      HIPCHK(hipMemcpyAsync(base + idx * 8, &value, 8, hipMemcpyHostToDevice, s->stream));
+    } else {
+      size_t off = 0;
+      long long lim = (3LL * s->Q - 2) * s->N;
+      if (s->p.storage == LBIB_FP16 || s->p.storage == LBIB_BF16) {
+        off = align_up((size_t)(3LL * (s->Q - 1) * s->N * 2));  // FP32 rest planes
+        lim = 3 * s->N;
+      }
+      if (idx < 0 || idx >= lim) return LBIB_EINVAL;
+      float v = (float)value;
+      HIPCHK(hipMemcpyAsync(base + off + idx * 4, &v, 4, hipMemcpyHostToDevice, s->stream));
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LBIB_OK;
+  }
+  return LBIB_EINVAL;
+}
+
+const char* lbib_strerror(int status) {
+  switch (status) {
+    case LBIB_OK: return "ok";
+    case LBIB_EINVAL: return "invalid argument";
+    case LBIB_ENOMEM: return "workspace or capacity too small";
+    case LBIB_EHIP: return "HIP runtime error";
+    case LBIB_ENONFINITE: return "non-finite population";
+    case LBIB_EUNSTABLE: return "force out of range or membrane too large for the lattice";
+    case LBIB_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+void lbib_destroy(lbib_sim* s) { delete s; }
+
+}  // extern "C"

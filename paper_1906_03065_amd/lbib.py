@@ -1,0 +1,256 @@
+"""ctypes binding of the HIP library ``liblbib.so`` (C ABI in include/lbib.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch supplies the device workspace (one uint8 tensor) and
+the stream.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbib.so")
+
+D2Q9, D3Q19 = 0, 1
+FP32, FP16, BF16, FP64 = 0, 1, 2, 3
+STORAGE = {"fp32": FP32, "fp16": FP16, "bf16": BF16, "fp64": FP64}
+
+STATUS = {0: "LBIB_OK", -1: "LBIB_EINVAL", -2: "LBIB_ENOMEM", -3: "LBIB_EHIP",
+          -4: "LBIB_ENONFINITE", -5: "LBIB_EUNSTABLE", -6: "LBIB_ESTATE"}
+
+
+class LbibError(RuntimeError):
+    def __init__(self, fn, code):
+        self.code = code
+        super().__init__(f"{fn} failed: {STATUS.get(code, code)}")
+
+
+class Params(C.Structure):
+    _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("wall_y", C.c_int), ("wall_z", C.c_int),
+                ("tau", C.c_double), ("tau_phi", C.c_double), ("tau_psi", C.c_double),
+                ("gamma_phi", C.c_double), ("gamma_psi", C.c_double),
+                ("kappa", C.c_double * 3), ("alpha", C.c_double), ("kappa_c", C.c_double),
+                ("r_cut", C.c_double), ("storage", C.c_int), ("max_markers", C.c_int),
+                ("max_elems", C.c_int), ("max_membranes", C.c_int)]
+
+
+class Energies(C.Structure):
+    _fields_ = [("mass", C.c_double * 3), ("F_bulk", C.c_double), ("F_grad", C.c_double),
+                ("E_c", C.c_double), ("E_s", C.c_double), ("E_b", C.c_double),
+                ("E_kin", C.c_double), ("p_ideal", C.c_double)]
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_vp = C.c_void_p
+
+# (name, restype, argtypes) of every entry point declared in include/lbib.h
+SIGNATURES = [
+    ("lbib_workspace_bytes", C.c_int, [C.POINTER(Params), C.POINTER(C.c_size_t)]),
+    ("lbib_create", C.c_int, [C.POINTER(Params), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    ("lbib_add_membrane", C.c_int, [_vp, C.c_int, _dp, C.c_int, _ip, C.c_double, C.c_double, _ip]),
+    ("lbib_set_fields", C.c_int, [_vp, _dp, _dp, _dp, _dp, _dp, _dp]),
+    ("lbib_step", C.c_int, [_vp, C.c_int]),
+    ("lbib_get_fields", C.c_int, [_vp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+    ("lbib_get_membrane", C.c_int, [_vp, C.c_int, _dp, _dp, _dp]),
+    ("lbib_energy", C.c_int, [_vp, C.POINTER(Energies)]),
+    ("lbib_check", C.c_int, [_vp]),
+    ("lbib_device_view", C.c_int, [_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_size_t)]),
+    ("lbib_save", C.c_int, [_vp, _vp, C.POINTER(C.c_size_t)]),
+    ("lbib_load", C.c_int, [_vp, _vp, C.c_size_t]),
+    ("lbib_timing_enable", C.c_int, [_vp, C.c_int]),
+    ("lbib_timing_read", C.c_int, [_vp, _dp, C.c_int, _ip]),
+    ("lbib_steps_done", C.c_longlong, [_vp]),
+    ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
+    ("lbib_strerror", C.c_char_p, [C.c_int]),
+    ("lbib_destroy", None, [_vp]),
+]
+
+
+def lib():
+    """Load liblbib.so (built by paper_1906_03065_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import "
+                               "__graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _chk(fn, code):
+    if code != 0:
+        raise LbibError(fn, code)
+
+
+def _d(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def make_params(p: dict, storage="fp32", max_markers=None, max_membranes=None, max_elems=0,
+                membranes=()) -> Params:
+    if isinstance(storage, str):
+        storage = STORAGE[storage]
+    if max_markers is None:
+        max_markers = sum(len(m["X"]) for m in membranes)
+    if max_membranes is None:
+        max_membranes = len(membranes)
+    k = p["kappa"]
+    return Params(int(p.get("lattice", 0)), int(p["nx"]), int(p["ny"]), int(p.get("nz", 1)),
+                  int(p.get("wall_y", 0)), int(p.get("wall_z", 0)),
+                  float(p.get("tau", 1.0)), float(p.get("tau_phi", 1.0)), float(p.get("tau_psi", 1.0)),
+                  float(p.get("gamma_phi", 1.0)), float(p.get("gamma_psi", 1.0)),
+                  (C.c_double * 3)(float(k[0]), float(k[1]), float(k[2])),
+                  float(p.get("alpha", 1.0)), float(p.get("kappa_c", 0.0)), float(p.get("r_cut", 0.0)),
+                  int(storage), int(max_markers), int(max_elems), int(max_membranes))
+
+
+def workspace_bytes(prm: Params) -> int:
+    n = C.c_size_t(0)
+    _chk("lbib_workspace_bytes", lib().lbib_workspace_bytes(C.byref(prm), C.byref(n)))
+    return n.value
+
+
+class Sim:
+    """One GPU simulation.  ``p`` is the project's parameter dict (see
+    workloads.base_params); ``membranes`` sizes the marker capacity."""
+
+    def __init__(self, p: dict, storage="fp32", membranes=(), device="cuda:0", stream=None,
+                 max_markers=None, max_membranes=None):
+        import torch
+
+        self.torch = torch
+        self.p = dict(p)
+        self.prm = make_params(p, storage, max_markers, max_membranes, membranes=membranes)
+        self.D = 3 if self.prm.lattice == D3Q19 else 2
+        self.shape = ((self.prm.nz, self.prm.ny, self.prm.nx) if self.D == 3
+                      else (self.prm.ny, self.prm.nx))
+        self.N = int(np.prod(self.shape))
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(self.prm)
+        # torch's caching allocator returns blocks aligned to at least 512 bytes
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        _chk("lbib_create", lib().lbib_create(C.byref(self.prm), _vp(self.ws.data_ptr()), nbytes,
+                                              _vp(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.mem_sizes = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbib_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_membrane(self, X, tris=None, kappa_s=0.0, kappa_b=0.0) -> int:
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, self.D)
+        mid = C.c_int(-1)
+        if tris is None:
+            rc = lib().lbib_add_membrane(self.h, X.shape[0], _d(X), 0, None, kappa_s, kappa_b,
+                                         C.byref(mid))
+        else:
+            t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+            rc = lib().lbib_add_membrane(self.h, X.shape[0], _d(X), t.shape[0],
+                                         t.ctypes.data_as(_ip), kappa_s, kappa_b, C.byref(mid))
+        _chk("lbib_add_membrane", rc)
+        self.mem_sizes.append(X.shape[0])
+        return mid.value
+
+    def set_fields(self, rho, phi, psi, u=None):
+        arr = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, phi, psi)]
+        uu = [None, None, None]
+        if u is not None:
+            for a in range(self.D):
+                uu[a] = np.ascontiguousarray(u[a], dtype=np.float64).reshape(-1)
+        _chk("lbib_set_fields", lib().lbib_set_fields(self.h, *(_d(a) for a in arr),
+                                                      *(_d(a) for a in uu)))
+
+    def step(self, n=1):
+        _chk("lbib_step", lib().lbib_step(self.h, int(n)))
+
+    @property
+    def steps_done(self) -> int:
+        return lib().lbib_steps_done(self.h)
+
+    def fields(self) -> dict:
+        keys = ("rho", "c1", "c2", "c3", "ux", "uy", "uz")
+        out = {k: np.empty(self.N) for k in keys}
+        if self.D == 2:
+            out["uz"] = None
+        _chk("lbib_get_fields", lib().lbib_get_fields(self.h, *(_d(out[k]) for k in keys)))
+        return {k: v.reshape(self.shape) for k, v in out.items() if v is not None}
+
+    def membrane(self, i: int) -> dict:
+        n = self.mem_sizes[i]
+        X, U, F = (np.empty((n, self.D)) for _ in range(3))
+        _chk("lbib_get_membrane", lib().lbib_get_membrane(self.h, i, _d(X), _d(U), _d(F)))
+        return {"X": X, "U": U, "F": F}
+
+    def energy(self) -> dict:
+        e = Energies()
+        _chk("lbib_energy", lib().lbib_energy(self.h, C.byref(e)))
+        d = {k: getattr(e, k) for k, _ in Energies._fields_ if k != "mass"}
+        d["mass"] = list(e.mass)
+        return d
+
+    def check(self) -> int:
+        return lib().lbib_check(self.h)
+
+    def save(self) -> bytes:
+        n = C.c_size_t(0)
+        _chk("lbib_save", lib().lbib_save(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _chk("lbib_save", lib().lbib_save(self.h, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _chk("lbib_load", lib().lbib_load(self.h, buf, len(blob)))
+
+    def poke(self, field: int, idx: int, value: float):
+        _chk("lbib_debug_poke", lib().lbib_debug_poke(self.h, field, int(idx), float(value)))
+
+    def timing(self, mask: int = 15):
+        """Time the phases in ``mask`` (bit 0 lattice kernel, 1 coupling,
+        2 membrane forces + spreading, 3 interpolation); 0 switches off."""
+        _chk("lbib_timing_enable", lib().lbib_timing_enable(self.h, int(mask)))
+
+    def timing_read(self):
+        """Summed milliseconds per phase: lattice kernel, coupling, membrane
+        forces + spreading, interpolation; and the number of steps timed."""
+        ms = np.zeros(4)
+        n = C.c_int(0)
+        _chk("lbib_timing_read", lib().lbib_timing_read(self.h, _d(ms), 4, C.byref(n)))
+        return {"lb": ms[0], "coupling": ms[1], "membrane": ms[2], "interp": ms[3],
+                "steps": n.value}
+
+    def device_view(self, field: int):
+        ptr, n = _vp(), C.c_size_t(0)
+        _chk("lbib_device_view", lib().lbib_device_view(self.h, field, C.byref(ptr), C.byref(n)))
+        return ptr.value, n.value
+
+
+def from_workload(w: dict, storage="fp32", device="cuda:0", **kw) -> Sim:
+    """Create a GPU simulation from a workloads.* dictionary."""
+    s = Sim(w["params"], storage=storage, membranes=w["membranes"], device=device, **kw)
+    for m in w["membranes"]:
+        s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"])
+    f = w["fields"]
+    s.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
+    return s

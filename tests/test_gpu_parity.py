@@ -1,0 +1,157 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs, element by element over whole fields (D2Q9)."""
+import numpy as np
+import pytest
+
+from helpers import compare, marker_err, normwise, run_gpu, run_oracle
+from paper_1906_03065_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _report(tag, errs):
+    print(tag, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+
+
+def test_fp64_parity_c1(orc):
+    """128x128 capsule at an interface (periodic x, walls y): FP64 kernels
+    match the oracle to round-off at steps 0, 1, 10 and 200."""
+    w = W.c1()
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    for n in (0, 1, 10, 200):
+        o.step(n - o.steps_done)
+        g.step(n - g.steps_done)
+        errs = compare(g, o)
+        _report(f"fp64 c1 step {n}", errs)
+        for k, v in errs.items():
+            assert v < 1e-9, (n, k, v)
+        assert marker_err(g, o, 1) < 1e-9
+
+
+def test_fp32_parity_c1_1000_steps(orc):
+    """FP32 storage and arithmetic: max relative error <= 1e-5 on rho, u and
+    C_m after 1000 steps (normwise: max |a-b| / max |b|)."""
+    w = W.c1()
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp32")
+    o.step(1000)
+    g.step(1000)
+    errs = compare(g, o)
+    _report("fp32 c1 step 1000", errs)
+    for k, v in errs.items():
+        assert v <= 1e-5, (k, v)
+    assert marker_err(g, o, 1) < 1e-4
+
+
+@pytest.mark.parametrize("wall_y", [0, 1])
+def test_fp64_parity_ragged_two_capsules_taus(orc, wall_y):
+    """Ragged lattice (several 60-column strips plus a tail, segments plus a
+    tail), two capsules, tau != 1 (tau = 1 hides BGK errors)."""
+    nx, ny = 150, 83
+    w = W.capsule_at_interface(nx=nx, ny=ny, R=12.0, n_markers=72, centre=(40.3, 41.2),
+                               wall_y=wall_y, tau=0.8, tau_phi=1.3, tau_psi=0.9,
+                               kappa=(0.02, 0.03, 0.015), seed=5)
+    w["membranes"].append(dict(X=W.circle_markers(110.6, 40.1, 10.0, 60), tris=None,
+                               kappa_s=0.05, kappa_b=1e-3))
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    for n in (1, 60):
+        o.step(n - o.steps_done)
+        g.step(n - g.steps_done)
+        errs = compare(g, o)
+        _report(f"fp64 ragged wall={wall_y} step {n}", errs)
+        for k, v in errs.items():
+            assert v < 1e-9, (n, k, v)
+        assert marker_err(g, o, 2) < 1e-9
+
+
+def test_fp64_parity_no_membrane(orc):
+    """Pure ternary fluid (a drop, no markers): the lattice path alone."""
+    w = W.drop(n=70, R=14.0)
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    o.step(100)
+    g.step(100)
+    errs = compare(g, o)
+    _report("fp64 drop", errs)
+    for k, v in errs.items():
+        assert v < 1e-10, (k, v)
+
+
+def test_energy_parity(orc):
+    """FP64 reductions: energies and masses against the oracle's."""
+    w = W.c1()
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    o.step(20)
+    g.step(20)
+    eo, eg = o.energy(), g.energy()
+    print("energies", eg, eo, flush=True)
+    for k in ("F_bulk", "F_grad", "E_c", "E_s", "E_b", "E_kin"):
+        assert abs(eg[k] - eo[k]) <= 1e-9 * max(abs(eo[k]), 1e-12), k
+    # sum rho ln rho / 3 moves by ~1/3 per unit of total mass, which the two
+    # sides carry to ~1e-15 relative: bound it by the mass round-off
+    assert abs(eg["p_ideal"] - eo["p_ideal"]) <= 1e-14 * 128 * 128
+    np.testing.assert_allclose(eg["mass"], eo["mass"], rtol=1e-12)
+
+
+def test_fp32_mass_conservation():
+    """Masses stay constant on the GPU in FP32 (moving populations shifted)."""
+    w = W.c1()
+    g = run_gpu(w, "fp32")
+    m0 = np.array(g.energy()["mass"])
+    g.step(500)
+    m1 = np.array(g.energy()["mass"])
+    print("mass drift", (m1 - m0) / m0, flush=True)
+    assert np.abs((m1 - m0) / m0).max() < 1e-6
+
+
+def test_determinism_and_checkpoint():
+    """Bitwise reproducible runs; save/load resumes bitwise."""
+    w = W.c1()
+    a = run_gpu(w, "fp32")
+    a.step(40)
+    blob = a.save()
+    a.step(40)
+    fa = a.fields()
+    b = run_gpu(w, "fp32")
+    b.step(80)
+    fb = b.fields()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    c = run_gpu(w, "fp32")
+    c.load(blob)
+    c.step(40)
+    fc = c.fields()
+    for k in fa:
+        assert np.array_equal(fa[k], fc[k]), k
+    assert np.array_equal(a.membrane(0)["X"], c.membrane(0)["X"])
+
+
+def test_failure_injection_nonfinite():
+    """A NaN forced into a population from the host is reported by lbib_check."""
+    from paper_1906_03065_amd import lbib
+
+    w = W.c1()
+    g = run_gpu(w, "fp32")
+    g.step(2)
+    assert g.check() == 0
+    g.poke(0, 12345, float("nan"))
+    g.step(1)
+    assert g.check() == -4
+
+
+def test_c2_fullsize_fp32_vs_oracle(orc):
+    """2048x2048 with 16 capsules (the throughput workload, same launch
+    shape as the benchmark): two steps, every node against the oracle."""
+    w = W.c2()
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp32")
+    o.step(2)
+    g.step(2)
+    errs = compare(g, o)
+    _report("fp32 c2 step 2", errs)
+    for k, v in errs.items():
+        assert v <= 1e-5, (k, v)
+    assert marker_err(g, o, 16) < 1e-6
