@@ -22,13 +22,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb2d_d2q9_2048_traffic.json")
+
+
+def measured_traffic(storage: str, size: int):
+    """HBM bytes per fused-kernel launch from the committed rocprofv3 counter
+    runs (FETCH_SIZE, WRITE_SIZE scaled by a plain copy), or None when the
+    kernel sources changed since they were taken or the workload differs."""
+    import hashlib
+
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_1906_03065_amd", "csrc", f), "rb").read()
+                   for f in ("k_lb.h", "store.h"))
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    if storage != "fp32" or size != 2048:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def bytes_per_lup(storage: str, Q: int = 9) -> int:
     """Algorithmic bytes per lattice update: the three population sets read
     once and written once."""
     if storage == "fp32":
-        return 2 * 3 * Q * 4
+        return 2 * ((3 * Q - 2) * 4 + 2 * 8)  # FP32 planes, FP64 g_0 and h_0
     if storage == "fp64":
         return 2 * 3 * Q * 8
     return 2 * (3 * (Q - 1) * 2 + 3 * 4)  # 16-bit moving + FP32 rest populations
@@ -68,7 +88,25 @@ def main():
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--block-x", type=int, default=0, help="fused kernel lanes per workgroup")
+    ap.add_argument("--seg", type=int, default=0, help="fused kernel rows per workgroup")
+    ap.add_argument("--nxcd", type=int, default=0, help="L2 domains workgroups are dealt to")
+    ap.add_argument("--ring", type=int, default=0, help="register ring depth (3 or 4)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (source + destination "
+                         "traffic 2*MIB MiB per launch), --steps times, to scale counters")
     args = ap.parse_args()
+    if args.calib_copy:
+        import torch
+
+        a = torch.empty(args.calib_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_mib": args.calib_copy, "launches": args.steps}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "domain decomposition is a design, not part of this build", file=sys.stderr)
@@ -81,6 +119,7 @@ def main():
 
     w = W.c2(n=args.size)
     g = lbib.from_workload(w, storage=args.storage, device="cuda:0")
+    g.set_launch(args.block_x, args.seg, args.nxcd, args.ring)
     N = g.N
     g.step(args.warmup)
     torch.cuda.synchronize()
@@ -120,9 +159,11 @@ def main():
                    "nodes": N, "capsules": len(w["membranes"]),
                    "markers": sum(len(m["X"]) for m in w["membranes"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.storage, args.size),
                      "kernel": "k_lb2d", "kernel_ms": round(lb_ms, 5), "bytes_per_lup": bpl,
-                     "kernel_share_of_step": round(lb_ms / (el * 1e3 / args.steps), 4)},
+                     "kernel_share_of_step": round(lb_ms / (el * 1e3 / args.steps), 4),
+                     "launch": g.get_launch()},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -154,6 +154,16 @@ int lbib_load(lbib_sim* s, const void* host_buf, size_t bytes);
 int lbib_timing_enable(lbib_sim* s, int on);
 int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps);
 
+/* Launch shape of the fused lattice kernel (a tuning knob; results do not
+   depend on it): block_x lanes per workgroup (64, 128 or 256; block_x - 4
+   interior columns), seg rows per workgroup, nxcd the number of L2 domains
+   workgroups are dealt to in turn, ring the rows held in registers (3, or 4
+   to load the next row while the current ones are computed).  0 keeps the
+   current value; seg = -1 returns to the automatic choice (as many
+   workgroups as fit on the GPU at once, so none waits for a second round). */
+int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring);
+int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* ring);
+
 /* Number of completed steps. */
 long long lbib_steps_done(const lbib_sim* s);
 

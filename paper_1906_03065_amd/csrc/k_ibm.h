@@ -7,21 +7,26 @@
 // Active tiles: every lattice tile (TILE x TILE nodes) that meets a
 // membrane's bounding box grown by r_cut + 3.  Only these tiles carry a
 // profile I different from 0, a spread force, or a stored total force; the
-// fused lattice kernel reads the maps there and nowhere else.
+// fused lattice kernel reads the maps there and nowhere else.  A tile is
+// active in a step when its flag equals that step's stamp, so no pass is
+// needed to clear the previous step's map.
 //
 // Signed distance d(x): distance to the closest segment of the marker
-// polygon, positive inside.  Inside/outside is the even-odd rule: the parity
-// of the tile centre from a ray towards +x over all segments, then flipped
-// once per segment crossing the short path from the tile centre to the node
-// (such segments lie within reach of the tile and are among its candidates).
+// polygon, positive inside.  Every node of a tile is compared with all
+// segments within reach of the tile (enough to contain each node's closest
+// segment); the sign comes from the closest feature: the side of the closest
+// segment, or at a closest vertex the sum of its two edge normals (exact for
+// a simple polygon, whichever way it is oriented).
 #pragma once
 #include "common.h"
 #include "k_lb.h"
 
 namespace lb {
 
-constexpr int TILE2 = 16;         // 2D tile edge
-constexpr int COUP_THREADS = 256; // one thread per node of a 16x16 tile
+constexpr int TILE2 = 16;          // 2D tile edge
+constexpr int COUP_THREADS = 256;  // one thread per node of a 16x16 tile
+constexpr int COUP_CHUNK = 512;    // segments examined per culling chunk
+constexpr int COUP_KEEP = 4;       // membranes per tile whose band data stays in LDS
 
 struct MemDev {
   double* X;          // 3 per marker
@@ -33,15 +38,15 @@ struct MemDev {
   int* mid;           // membrane id of every marker
   double* ks;         // K
   double* kb;         // K
-  double* mbox;       // 6 per membrane: lo xyz, hi xyz
-  int* status;        // [0] fixed-point overflow, [1] lattice too small for a membrane
+  double* mbox;       // 8 per membrane: lo xyz, hi xyz, orientation (+-1), spare
+  int* status;        // [0] force/marker out of range, [1] lattice too small / too many membranes
   int K, M;
 };
 
 struct TileMap {
-  int* tflag;         // per tile: 1 active
-  int* tlist;         // active tiles
-  int* tcount;        // number of active tiles
+  int* tflag;         // per tile: stamp of the last step it was active in
+  int* tlist;         // active tiles of this step
+  int* tstate;        // [0] active-tile count, [1] stamp of this step
   int ntx, nty, ntz, tile;
 };
 
@@ -56,30 +61,7 @@ __device__ double block_sum(double v, double* sh) {
   if (lane == 0) sh[wv] = v;
   __syncthreads();
   double t = 0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < NT / 64; i++) t += sh[i];
-  __syncthreads();
-  if (threadIdx.x == 0) sh[0] = t;
-  __syncthreads();
-  t = sh[0];
-  __syncthreads();
-  return t;
-}
-
-template <int NT>
-__device__ int block_sum_int(int v, int* sh) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wv] = v;
-  __syncthreads();
-  int t = 0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < NT / 64; i++) t += sh[i];
-  __syncthreads();
-  if (threadIdx.x == 0) sh[0] = t;
-  __syncthreads();
-  t = sh[0];
+  for (int i = 0; i < NT / 64; i++) t += sh[i];
   __syncthreads();
   return t;
 }
@@ -91,87 +73,94 @@ __device__ double block_min(double v, double* sh) {
   __syncthreads();
   if (lane == 0) sh[wv] = v;
   __syncthreads();
-  if (threadIdx.x == 0)
-    for (int i = 1; i < NT / 64; i++) sh[0] = fmin(sh[0], sh[i]);
-  __syncthreads();
   double t = sh[0];
+  for (int i = 1; i < NT / 64; i++) t = fmin(t, sh[i]);
   __syncthreads();
   return t;
 }
 
 // ---------------------------------------------------------------------------
-// bounding boxes and the active-tile map; one workgroup per simulation
+// start of a step: new stamp, empty active-tile list (one thread)
+__global__ void k_begin(int* tstate) {
+  if (threadIdx.x == 0) {
+    tstate[0] = 0;
+    tstate[1] = tstate[1] + 1;
+  }
+}
+
+// bounding box, orientation and active tiles of membrane blockIdx.x
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int ny, int nz,
                                               int wall_y, int wall_z, int D, double reach) {
-  __shared__ double sh[NT / 64 + 1];
-  __shared__ int cnt;
+  __shared__ double sh[NT / 64];
+  const int m = blockIdx.x;
   const int tid = threadIdx.x;
-  // clear the previous map
-  const int nprev = *tm.tcount;
-  for (int i = tid; i < nprev; i += NT) tm.tflag[tm.tlist[i]] = 0;
-  if (tid == 0) cnt = 0;
-  __syncthreads();
-  for (int m = 0; m < md.K; m++) {
-    const int b = md.moff[m], e = md.moff[m + 1];
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; a++) {
-      double mn = 1e300, mx = -1e300;
-      if (a < D)
-        for (int l = b + tid; l < e; l += NT) {
-          const double v = md.X[3 * l + a];
-          mn = fmin(mn, v);
-          mx = fmax(mx, v);
-        }
-      lo[a] = block_min<NT>(mn, sh);
-      hi[a] = -block_min<NT>(-mx, sh);
-    }
-    if (tid == 0)
-      for (int a = 0; a < 3; a++) {
-        md.mbox[6 * m + a] = lo[a];
-        md.mbox[6 * m + 3 + a] = hi[a];
+  const int b = md.moff[m], e = md.moff[m + 1], n = e - b;
+  const int stamp = tm.tstate[1];
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; a++) {
+    double mn = 1e300, mx = -1e300;
+    if (a < D)
+      for (int l = b + tid; l < e; l += NT) {
+        const double v = md.X[3 * l + a];
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
       }
-    // non-finite or runaway markers: flag and leave this membrane off the map
-    bool sane = true;
-    for (int a = 0; a < D; a++)
-      if (!(fabs(lo[a]) < 1e9) || !(fabs(hi[a]) < 1e9)) sane = false;
-    if (!sane) {
-      if (tid == 0) md.status[0] = 1;
-      __syncthreads();
-      continue;
-    }
-    // the periodic image of a node must be unique within the grown box
-    const int dims[3] = {nx, ny, nz};
-    const int per[3] = {1, !wall_y, !wall_z};
-    for (int a = 0; a < D; a++)
-      if (per[a] && hi[a] - lo[a] + 2.0 * reach + 2.0 * tm.tile >= dims[a] && tid == 0)
-        md.status[1] = 1;
-    // tile ranges of the grown box
-    int t0[3] = {0, 0, 0}, t1[3] = {0, 0, 0}, nt[3] = {tm.ntx, tm.nty, tm.ntz};
-    for (int a = 0; a < D; a++) {
-      t0[a] = (int)floor((lo[a] - reach) / tm.tile);
-      t1[a] = (int)floor((hi[a] + reach) / tm.tile);
-      if (!per[a]) {
-        t0[a] = max(t0[a], 0);
-        t1[a] = min(t1[a], nt[a] - 1);
-      } else if (t1[a] - t0[a] + 1 > nt[a]) {
-        t0[a] = 0;
-        t1[a] = nt[a] - 1;
-      }
-    }
-    const int sx = t1[0] - t0[0] + 1, sy = t1[1] - t0[1] + 1, sz = (D == 3) ? t1[2] - t0[2] + 1 : 1;
-    const long long total = (long long)sx * sy * sz;
-    for (long long q = tid; q < total; q += NT) {
-      const int ix = (int)(q % sx), iy = (int)((q / sx) % sy), iz = (int)(q / ((long long)sx * sy));
-      const int tx = wrap(t0[0] + ix, nt[0]), ty = wrap(t0[1] + iy, nt[1]);
-      const int tz = (D == 3) ? wrap(t0[2] + iz, nt[2]) : 0;
-      const int t = (tz * tm.nty + ty) * tm.ntx + tx;
-      if (atomicCAS(&tm.tflag[t], 0, 1) == 0) tm.tlist[atomicAdd(&cnt, 1)] = t;
-    }
-    __syncthreads();
+    lo[a] = block_min<NT>(mn, sh);
+    hi[a] = -block_min<NT>(-mx, sh);
   }
-  __syncthreads();
-  if (tid == 0) *tm.tcount = cnt;
+  // orientation of a 2D ring from its signed area (shoelace sum)
+  double area = 0.0;
+  if (D == 2) {
+    double acc = 0.0;
+    for (int l = tid; l < n; l += NT) {
+      const int l1 = (l + 1 == n) ? 0 : l + 1;
+      acc += md.X[3 * (b + l)] * md.X[3 * (b + l1) + 1] - md.X[3 * (b + l1)] * md.X[3 * (b + l) + 1];
+    }
+    area = block_sum<NT>(acc, sh);
+  }
+  if (tid == 0) {
+    for (int a = 0; a < 3; a++) {
+      md.mbox[8 * m + a] = lo[a];
+      md.mbox[8 * m + 3 + a] = hi[a];
+    }
+    md.mbox[8 * m + 6] = area >= 0.0 ? 1.0 : -1.0;
+  }
+  // non-finite or runaway markers: flag and leave this membrane off the map
+  for (int a = 0; a < D; a++)
+    if (!(fabs(lo[a]) < 1e9) || !(fabs(hi[a]) < 1e9)) {
+      if (tid == 0) md.status[0] = 1;
+      return;
+    }
+  const int dims[3] = {nx, ny, nz};
+  const int per[3] = {1, !wall_y, !wall_z};
+  // the periodic image of a node must be unique within the grown box
+  for (int a = 0; a < D; a++)
+    if (per[a] && hi[a] - lo[a] + 2.0 * reach + 2.0 * tm.tile >= dims[a] && tid == 0)
+      md.status[1] = 1;
+  int t0[3] = {0, 0, 0}, t1[3] = {0, 0, 0};
+  const int nt[3] = {tm.ntx, tm.nty, tm.ntz};
+  for (int a = 0; a < D; a++) {
+    t0[a] = (int)floor((lo[a] - reach) / tm.tile);
+    t1[a] = (int)floor((hi[a] + reach) / tm.tile);
+    if (!per[a]) {
+      t0[a] = max(t0[a], 0);
+      t1[a] = min(t1[a], nt[a] - 1);
+    } else if (t1[a] - t0[a] + 1 > nt[a]) {
+      t0[a] = 0;
+      t1[a] = nt[a] - 1;
+    }
+  }
+  const int sx = t1[0] - t0[0] + 1, sy = t1[1] - t0[1] + 1, sz = (D == 3) ? t1[2] - t0[2] + 1 : 1;
+  if (sx <= 0 || sy <= 0 || sz <= 0) return;
+  const long long total = (long long)sx * sy * sz;
+  for (long long q = tid; q < total; q += NT) {
+    const int ix = (int)(q % sx), iy = (int)((q / sx) % sy), iz = (int)(q / ((long long)sx * sy));
+    const int tx = wrap(t0[0] + ix, nt[0]), ty = wrap(t0[1] + iy, nt[1]);
+    const int tz = (D == 3) ? wrap(t0[2] + iz, nt[2]) : 0;
+    const int t = (tz * tm.nty + ty) * tm.ntx + tx;
+    if (atomicMax(&tm.tflag[t], stamp) < stamp) tm.tlist[atomicAdd(&tm.tstate[0], 1)] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -200,21 +189,6 @@ __device__ __forceinline__ int ray_cross(double px, double py, double ax, double
   return 0;
 }
 
-__device__ __forceinline__ double orient(double ax, double ay, double bx, double by, double cx,
-                                         double cy) {
-  return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
-}
-
-// does the path P->Q cross segment A-B?  Half-open on both (a vertex on the
-// path is counted by exactly one of its two segments)
-__device__ __forceinline__ int path_cross(double px, double py, double qx, double qy, double ax,
-                                          double ay, double bx, double by) {
-  const double o1 = orient(px, py, qx, qy, ax, ay), o2 = orient(px, py, qx, qy, bx, by);
-  if ((o1 >= 0.0) == (o2 >= 0.0)) return 0;
-  const double o3 = orient(ax, ay, bx, by, px, py), o4 = orient(ax, ay, bx, by, qx, qy);
-  return (o3 >= 0.0) != (o4 >= 0.0);
-}
-
 __device__ __forceinline__ double near_image(double v, double c, int n) {
   return v + n * floor((c - v) / n + 0.5);
 }
@@ -225,71 +199,55 @@ struct CoupArgs {
   int want_force;
 };
 
-// per node: signed distance to membrane m, closest segment and its t; the
-// caller's block cooperates on candidate culling.  Returns via refs; d2 =
-// +inf when the node lies outside the membrane's grown box.
-template <int NT>
-__device__ void ring_geometry(const MemDev& md, const CoupArgs& ca, int m, double px_tile,
-                              double py_tile, double px, double py, bool valid_node, double& d2_best,
-                              int& seg_best, double& t_best, int& inside, int* s_cand, int* s_int,
-                              double* s_dbl) {
-  const int b = md.moff[m], n = md.moff[m + 1] - b;
-  const double* X = md.X + 3 * b;
-  const double reach = ca.r_cut + 1.0;
-  const double hd = 0.5 * TILE2 * 1.41421356237309515 + 1e-9;
-  const double cull = ca.r_cut + hd + 1.0;
-  // parity of the tile centre: ray towards +x over all segments
-  int cr = 0;
-  for (int l = threadIdx.x; l < n; l += NT) {
-    const int l1 = (l + 1 == n) ? 0 : l + 1;
-    cr += ray_cross(px_tile, py_tile, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1]);
+// inside test at the closest feature of a ring (markers X, n of them,
+// orientation o = +1 counter-clockwise): the side of segment s at parameter
+// t, or at an end vertex the side of the sum of the two edge normals
+__device__ __forceinline__ bool ring_side(const double* X, int n, double o, int s, double t,
+                                          double px, double py) {
+  const int s1 = (s + 1 == n) ? 0 : s + 1;
+  const double ax = X[3 * s], ay = X[3 * s + 1], bx = X[3 * s1], by = X[3 * s1 + 1];
+  if (t > 0.0 && t < 1.0) return o * ((bx - ax) * (py - ay) - (by - ay) * (px - ax)) > 0.0;
+  int v, u, w;  // vertex, previous, next
+  if (t <= 0.0) {
+    v = s;
+    u = (s == 0) ? n - 1 : s - 1;
+    w = s1;
+  } else {
+    v = s1;
+    u = s;
+    w = (s1 + 1 == n) ? 0 : s1 + 1;
   }
-  const int parity = block_sum_int<NT>(cr, s_int) & 1;
-  d2_best = 1e300;
-  seg_best = -1;
-  t_best = 0.0;
-  int flips = 0;
-  for (int c0 = 0; c0 < n; c0 += NT) {
-    if (threadIdx.x == 0) s_int[NT / 64] = 0;
-    __syncthreads();
-    const int l = c0 + threadIdx.x;
-    if (l < n) {
-      const int l1 = (l + 1 == n) ? 0 : l + 1;
-      double t;
-      const double d2 = seg_d2(px_tile, py_tile, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1], t);
-      if (d2 <= cull * cull) s_cand[atomicAdd(&s_int[NT / 64], 1)] = l;
-    }
-    __syncthreads();
-    const int nc = s_int[NT / 64];
-    if (valid_node)
-      for (int q = 0; q < nc; q++) {
-        const int s = s_cand[q];
-        const int s1 = (s + 1 == n) ? 0 : s + 1;
-        const double ax = X[3 * s], ay = X[3 * s + 1], bx = X[3 * s1], by = X[3 * s1 + 1];
-        double t;
-        const double d2 = seg_d2(px, py, ax, ay, bx, by, t);
-        if (d2 < d2_best || (d2 == d2_best && s < seg_best)) {
-          d2_best = d2;
-          seg_best = s;
-          t_best = t;
-        }
-        flips += path_cross(px_tile, py_tile, px, py, ax, ay, bx, by);
-      }
-    __syncthreads();
-  }
-  inside = parity ^ (flips & 1);
-  (void)reach;
-  (void)s_dbl;
+  const double vx = X[3 * v], vy = X[3 * v + 1];
+  const double e1x = vx - X[3 * u], e1y = vy - X[3 * u + 1];
+  const double e2x = X[3 * w] - vx, e2y = X[3 * w + 1] - vy;
+  const double l1 = sqrt(e1x * e1x + e1y * e1y), l2 = sqrt(e2x * e2x + e2y * e2y);
+  // left normals (-ey, ex) of both edges, summed
+  const double nx_ = -e1y / l1 - e2y / l2, ny_ = e1x / l1 + e2x / l2;
+  return o * (nx_ * (px - vx) + ny_ * (py - vy)) > 0.0;
 }
 
+// whole tile outside membrane m's grown box?  (uniform over the block)
+__device__ __forceinline__ bool tile_misses(const double* bx, double pxt, double pyt, double hd,
+                                            double reach) {
+  return pxt + hd < bx[0] - reach || pxt - hd > bx[3] + reach || pyt + hd < bx[1] - reach ||
+         pyt - hd > bx[4] + reach;
+}
+
+// one tile per workgroup (grid-stride over the active-tile list)
 template <class St, typename R, int NT>
 __global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupArgs ca,
                                                    double* __restrict__ Ifield, St cur) {
-  __shared__ int s_cand[NT];
-  __shared__ int s_int[NT / 64 + 2];
-  __shared__ double s_dbl[NT / 64 + 1];
-  const int ntl = *tm.tcount;
+  __shared__ int s_cand[COUP_CHUNK];
+  __shared__ float4 s_geo[COUP_CHUNK];  // candidate start point and edge, relative to the tile centre
+  __shared__ float s_inv[COUP_CHUNK];   // 1 / |edge|^2
+  __shared__ int s_cnt;
+  __shared__ double s_red[NT / 64];
+  __shared__ int b_seg[COUP_KEEP][NT];
+  __shared__ double b_t[COUP_KEEP][NT];
+  __shared__ double b_sd[COUP_KEEP][NT];
+  const int ntl = tm.tstate[0];
   const double reach = ca.r_cut + 1.0;
+  const double hd = 0.5 * TILE2 * 1.41421356237309515;
   for (int li = blockIdx.x; li < ntl; li += gridDim.x) {
     const int t = tm.tlist[li];
     const int tx = t % tm.ntx, ty = t / tm.ntx;
@@ -297,95 +255,171 @@ __global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupAr
     const bool valid = (x < ca.nx) && (y < ca.ny);
     const double xt = tx * TILE2 + 0.5 * (TILE2 - 1), yt = ty * TILE2 + 0.5 * (TILE2 - 1);
     double Itot = 0.0;
-    // pass 1: the profile, summed over membranes
+    int kept = 0;  // membranes met by this tile (uniform)
     for (int m = 0; m < md.K; m++) {
-      const double* bx = md.mbox + 6 * m;
+      const double* bx = md.mbox + 8 * m;
       const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
       const double pxt = near_image(xt, cx, ca.nx);
       const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
-      const double hd = 0.5 * TILE2 * 1.41421356237309515;
-      // whole tile outside the grown box: nothing to add (uniform branch)
-      if (pxt + hd < bx[0] - reach || pxt - hd > bx[3] + reach || pyt + hd < bx[1] - reach ||
-          pyt - hd > bx[4] + reach)
-        continue;
+      if (tile_misses(bx, pxt, pyt, hd, reach)) continue;
+      const int b = md.moff[m], n = md.moff[m + 1] - b;
+      const double* X = md.X + 3 * b;
+      const double o = bx[6];
       const double px = near_image((double)x, cx, ca.nx);
       const double py = ca.wall_y ? (double)y : near_image((double)y, cy, ca.ny);
-      const bool inbox = px >= bx[0] - reach && px <= bx[3] + reach && py >= bx[1] - reach &&
-                         py <= bx[4] + reach;
-      double d2;
-      int seg, inside;
-      double tt;
-      ring_geometry<NT>(md, ca, m, pxt, pyt, px, py, valid && inbox, d2, seg, tt, inside, s_cand,
-                        s_int, s_dbl);
-      if (valid && inbox) {
-        const double d = sqrt(d2);
-        if (d > ca.r_cut)
-          Itot += inside ? 1.0 : 0.0;
+      const bool inbox = valid && px >= bx[0] - reach && px <= bx[3] + reach &&
+                         py >= bx[1] - reach && py <= bx[4] + reach;
+      // distance of the tile centre to the ring, and its ray parity
+      double dmin = 1e300;
+      int cr = 0;
+      for (int l = threadIdx.x; l < n; l += NT) {
+        const int l1 = (l + 1 == n) ? 0 : l + 1;
+        double tt;
+        dmin = fmin(dmin, seg_d2(pxt, pyt, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1], tt));
+        cr += ray_cross(pxt, pyt, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1]);
+      }
+      dmin = sqrt(block_min<NT>(dmin, s_red));
+      const int par = ((int)block_sum<NT>((double)cr, s_red)) & 1;
+      const int slot = kept++;
+      if (dmin > ca.r_cut + hd) {
+        // no node of the tile is within the band: all on the centre's side
+        if (inbox) Itot += par ? 1.0 : 0.0;
+        if (slot < COUP_KEEP) b_seg[slot][threadIdx.x] = -1;
+        continue;
+      }
+      // every node's closest segment lies within dmin + 2 hd of the centre.
+      // Candidates go to LDS with their geometry relative to the tile centre
+      // in FP32 (one reciprocal per segment, none per node); each node finds
+      // the FP32 minimum, then re-evaluates in FP64 every candidate within a
+      // margin that covers the FP32 rounding, so the FP64 closest segment
+      // (lowest index on ties) is the one chosen.
+      const double cull = dmin + 2.0 * hd + 1e-6;
+      const float fx = (float)(px - pxt), fy = (float)(py - pyt);
+      double d2b = 1e300, tb = 0.0;
+      int sb = -1;
+      for (int c0 = 0; c0 < n; c0 += COUP_CHUNK) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        for (int l = c0 + threadIdx.x; l < min(n, c0 + COUP_CHUNK); l += NT) {
+          const int l1 = (l + 1 == n) ? 0 : l + 1;
+          double tt;
+          const double ax = X[3 * l], ay = X[3 * l + 1], ex = X[3 * l1] - ax, ey = X[3 * l1 + 1] - ay;
+          if (seg_d2(pxt, pyt, ax, ay, X[3 * l1], X[3 * l1 + 1], tt) <= cull * cull) {
+            const int q = atomicAdd(&s_cnt, 1);
+            s_cand[q] = l;
+            const double ee = ex * ex + ey * ey;
+            s_geo[q] = make_float4((float)(ax - pxt), (float)(ay - pyt), (float)ex, (float)ey);
+            s_inv[q] = ee > 0.0 ? (float)(1.0 / ee) : 0.0f;
+          }
+        }
+        __syncthreads();
+        const int nc = s_cnt;
+        if (inbox && nc > 0) {
+          float bf = 3.0e38f;
+          for (int q = 0; q < nc; q++) {
+            const float4 g4 = s_geo[q];
+            const float qx = fx - g4.x, qy = fy - g4.y;
+            const float sp = fminf(fmaxf((qx * g4.z + qy * g4.w) * s_inv[q], 0.0f), 1.0f);
+            const float dx = qx - sp * g4.z, dy = qy - sp * g4.w;
+            bf = fminf(bf, dx * dx + dy * dy);
+          }
+          const float tol = 1e-3f + 1e-5f * bf;
+          for (int q = 0; q < nc; q++) {
+            const float4 g4 = s_geo[q];
+            const float qx = fx - g4.x, qy = fy - g4.y;
+            const float sp = fminf(fmaxf((qx * g4.z + qy * g4.w) * s_inv[q], 0.0f), 1.0f);
+            const float dx = qx - sp * g4.z, dy = qy - sp * g4.w;
+            if (dx * dx + dy * dy > bf + tol) continue;
+            const int s = s_cand[q];
+            const int s1 = (s + 1 == n) ? 0 : s + 1;
+            double tt;
+            const double d2 = seg_d2(px, py, X[3 * s], X[3 * s + 1], X[3 * s1], X[3 * s1 + 1], tt);
+            if (d2 < d2b || (d2 == d2b && s < sb)) {
+              d2b = d2;
+              sb = s;
+              tb = tt;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      double sd = 0.0;
+      bool band = false;
+      if (inbox && sb >= 0) {
+        const double d = sqrt(d2b);
+        const bool in = ring_side(X, n, o, sb, tb, px, py);
+        sd = in ? d : -d;
+        band = d <= ca.r_cut;
+        if (!band)
+          Itot += in ? 1.0 : 0.0;
         else
-          Itot += 0.5 * (1.0 + tanh((inside ? d : -d) / (2.0 * ca.alpha)));
+          Itot += 0.5 * (1.0 + tanh(sd / (2.0 * ca.alpha)));
+      }
+      if (slot < COUP_KEEP) {
+        b_seg[slot][threadIdx.x] = band ? sb : -1;
+        b_t[slot][threadIdx.x] = tb;
+        b_sd[slot][threadIdx.x] = sd;
       }
     }
     const long long node = (long long)y * ca.nx + x;
     if (valid) Ifield[node] = Itot;
-    if (!ca.want_force) continue;
-    // pass 2: coupling force on the markers, -dE_c/dX (eq. DiscreteCF)
-    double psi = 0.0;
-    if (valid) {
-      // psi(t) = sum_i h_i(x, t) by pull streaming of the current buffer
-      using L = Lattice<9>;
-      psi = cur.rest(2, node);
-      for (int i = 1; i < 9; i++) {
-        const int sy = y - L::cy[i];
-        long long sn;
-        int dir = i;
-        if (ca.wall_y && (sy < 0 || sy >= ca.ny)) {
-          sn = node;
-          dir = L::opp[i];
-        } else {
-          sn = (long long)wrap(sy, ca.ny) * ca.nx + wrap(x - L::cx[i], ca.nx);
+    if (ca.want_force) {
+      // coupling force on the markers, -dE_c/dX (eq. DiscreteCF): from every
+      // band node, kappa_c/(4 alpha) (psi - I) sech^2(d/2 alpha) dd/dX_v with
+      // dd/dX_v = -sign(d) nhat w_v (nhat from the closest point to the
+      // node, w_v the closest point's weight on vertex v)
+      if (kept > COUP_KEEP && threadIdx.x == 0) md.status[1] = 1;
+      double psi = 0.0;
+      if (valid) {
+        using L = Lattice<9>;
+        psi = cur.rest(2, node);
+        for (int i = 1; i < 9; i++) {
+          const int sy = y - L::cy[i];
+          long long sn;
+          int dir = i;
+          if (ca.wall_y && (sy < 0 || sy >= ca.ny)) {
+            sn = node;
+            dir = L::opp[i];
+          } else {
+            sn = (long long)wrap(sy, ca.ny) * ca.nx + wrap(x - L::cx[i], ca.nx);
+          }
+          psi += (double)cur.template load<R>(2, dir, sn);
         }
-        psi += (double)cur.template load<R>(2, dir, sn);
+      }
+      int slot = 0;
+      for (int m = 0; m < md.K && slot < COUP_KEEP; m++) {
+        const double* bx = md.mbox + 8 * m;
+        const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
+        const double pxt = near_image(xt, cx, ca.nx);
+        const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
+        if (tile_misses(bx, pxt, pyt, hd, reach)) continue;
+        const int myslot = slot++;
+        const int sb = b_seg[myslot][threadIdx.x];
+        if (sb < 0) continue;
+        const double sd = b_sd[myslot][threadIdx.x], tb = b_t[myslot][threadIdx.x];
+        const double d = fabs(sd);
+        if (d == 0.0) continue;
+        const int b = md.moff[m], n = md.moff[m + 1] - b;
+        const double* X = md.X + 3 * b;
+        const int s1 = (sb + 1 == n) ? 0 : sb + 1;
+        const double px = near_image((double)x, cx, ca.nx);
+        const double py = ca.wall_y ? (double)y : near_image((double)y, cy, ca.ny);
+        const double fx = X[3 * sb] + tb * (X[3 * s1] - X[3 * sb]);
+        const double fy = X[3 * sb + 1] + tb * (X[3 * s1 + 1] - X[3 * sb + 1]);
+        const double nxh = (px - fx) / d, nyh = (py - fy) / d;
+        const double sg = sd > 0.0 ? 1.0 : -1.0;
+        const double ch = cosh(sd / (2.0 * ca.alpha));
+        const double wgt = ca.kappa_c / (4.0 * ca.alpha) * (psi - Itot) / (ch * ch);
+        const double gx = -sg * nxh * wgt, gy = -sg * nyh * wgt;
+        long long* A = md.Facc + 3 * (b + sb);
+        long long* B = md.Facc + 3 * (b + s1);
+        atomicAdd((unsigned long long*)&A[0], (unsigned long long)to_fix(gx * (1.0 - tb)));
+        atomicAdd((unsigned long long*)&A[1], (unsigned long long)to_fix(gy * (1.0 - tb)));
+        atomicAdd((unsigned long long*)&B[0], (unsigned long long)to_fix(gx * tb));
+        atomicAdd((unsigned long long*)&B[1], (unsigned long long)to_fix(gy * tb));
       }
     }
-    for (int m = 0; m < md.K; m++) {
-      const double* bx = md.mbox + 6 * m;
-      const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
-      const double pxt = near_image(xt, cx, ca.nx);
-      const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
-      const double hd = 0.5 * TILE2 * 1.41421356237309515;
-      if (pxt + hd < bx[0] - reach || pxt - hd > bx[3] + reach || pyt + hd < bx[1] - reach ||
-          pyt - hd > bx[4] + reach)
-        continue;
-      const double px = near_image((double)x, cx, ca.nx);
-      const double py = ca.wall_y ? (double)y : near_image((double)y, cy, ca.ny);
-      const bool inbox = px >= bx[0] - reach && px <= bx[3] + reach && py >= bx[1] - reach &&
-                         py <= bx[4] + reach;
-      double d2;
-      int seg, inside;
-      double tt;
-      ring_geometry<NT>(md, ca, m, pxt, pyt, px, py, valid && inbox, d2, seg, tt, inside, s_cand,
-                        s_int, s_dbl);
-      if (!(valid && inbox) || seg < 0) continue;
-      const double d = sqrt(d2);
-      if (d > ca.r_cut || d == 0.0) continue;
-      const int b = md.moff[m], n = md.moff[m + 1] - b;
-      const int s1 = (seg + 1 == n) ? 0 : seg + 1;
-      const double* X = md.X + 3 * b;
-      const double fx = X[3 * seg] + tt * (X[3 * s1] - X[3 * seg]);
-      const double fy = X[3 * seg + 1] + tt * (X[3 * s1 + 1] - X[3 * seg + 1]);
-      const double nxh = (px - fx) / d, nyh = (py - fy) / d;
-      const double sg = inside ? 1.0 : -1.0;
-      const double ch = cosh((inside ? d : -d) / (2.0 * ca.alpha));
-      const double wgt = ca.kappa_c / (4.0 * ca.alpha) * (psi - Itot) / (ch * ch);
-      // dd/dX_vertex = -sign(d) nhat * barycentric weight
-      const double gx = -sg * nxh * wgt, gy = -sg * nyh * wgt;
-      long long* A = md.Facc + 3 * (b + seg);
-      long long* B = md.Facc + 3 * (b + s1);
-      atomicAdd((unsigned long long*)&A[0], (unsigned long long)to_fix(gx * (1.0 - tt)));
-      atomicAdd((unsigned long long*)&A[1], (unsigned long long)to_fix(gy * (1.0 - tt)));
-      atomicAdd((unsigned long long*)&B[0], (unsigned long long)to_fix(gx * tt));
-      atomicAdd((unsigned long long*)&B[1], (unsigned long long)to_fix(gy * tt));
-    }
+    __syncthreads();  // LDS band data is rewritten by the next tile
   }
 }
 
@@ -471,56 +505,44 @@ __global__ void k_memforce2d(MemDev md) {
   md.F[3 * g + 2] = 0.0;
 }
 
-// spreading, eq. Spreading with delta x = 1 (READING: no extra Delta s): each
-// marker adds F delta_h(x - X) to its 16 stencil nodes in fixed point
+// spreading, eq. Spreading with delta x = 1 (READING: no extra Delta s):
+// sixteen lanes per marker, each adds F delta_h(x - X) to one stencil node in
+// fixed point (integer sums are order independent)
 __global__ void k_spread2d(MemDev md, long long* __restrict__ fib, int nx, int ny, int wall_y) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = tid >> 4, k = tid & 15;
   if (g >= md.M) return;
   const double X = md.X[3 * g], Y = md.X[3 * g + 1];
   const double Fx = md.F[3 * g], Fy = md.F[3 * g + 1];
-  const int bx = (int)floor(X) - 1, by = (int)floor(Y) - 1;
-  double wx[4], wy[4];
-  for (int k = 0; k < 4; k++) {
-    wx[k] = peskin((bx + k) - X);
-    wy[k] = peskin((by + k) - Y);
-  }
-  for (int ky = 0; ky < 4; ky++) {
-    const int yy = by + ky;
-    if (wall_y && (yy < 0 || yy >= ny)) continue;
-    const int yw = wrap(yy, ny);
-    for (int kx = 0; kx < 4; kx++) {
-      const double w = wx[kx] * wy[ky];
-      const long long node = (long long)yw * nx + wrap(bx + kx, nx);
-      atomicAdd((unsigned long long*)&fib[2 * node], (unsigned long long)to_fix(Fx * w));
-      atomicAdd((unsigned long long*)&fib[2 * node + 1], (unsigned long long)to_fix(Fy * w));
-    }
-  }
+  const int cx = (int)floor(X) - 1 + (k & 3), cy = (int)floor(Y) - 1 + (k >> 2);
+  if (wall_y && (cy < 0 || cy >= ny)) return;
+  const double w = peskin(cx - X) * peskin(cy - Y);
+  const long long node = (long long)wrap(cy, ny) * nx + wrap(cx, nx);
+  atomicAdd((unsigned long long*)&fib[2 * node], (unsigned long long)to_fix(Fx * w));
+  atomicAdd((unsigned long long*)&fib[2 * node + 1], (unsigned long long)to_fix(Fy * w));
 }
 
 // interpolation of v* = u(t+1) + f(t) / (2 rho(t+1)) at the stencil of X(t)
 // (eq. Interpolation, READING: the force of step t stands in for the unknown
-// force at t+1), then X(t+1) = X(t) + U (eq. UpdatedXl)
+// force at t+1), then X(t+1) = X(t) + U (eq. UpdatedXl).  Sixteen lanes per
+// marker (one stencil node each), summed in a fixed butterfly order.
 template <class St, typename R>
 __global__ void k_interp2d(MemDev md, St cur, LBParams P, const double* __restrict__ force) {
   using L = Lattice<9>;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= md.M) return;
-  const double X = md.X[3 * g], Y = md.X[3 * g + 1];
-  const int bx = (int)floor(X) - 1, by = (int)floor(Y) - 1;
-  double wx[4], wy[4];
-  for (int k = 0; k < 4; k++) {
-    wx[k] = peskin((bx + k) - X);
-    wy[k] = peskin((by + k) - Y);
-  }
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = tid >> 4, k = tid & 15;
+  const bool live = g < md.M;
   double Ux = 0, Uy = 0;
-  for (int ky = 0; ky < 4; ky++) {
-    const int yy = by + ky;
-    if (P.wall_y && (yy < 0 || yy >= P.ny)) continue;
-    const int yw = wrap(yy, P.ny);
-    for (int kx = 0; kx < 4; kx++) {
-      const int xw = wrap(bx + kx, P.nx);
+  double X = 0, Y = 0;
+  if (live) {
+    X = md.X[3 * g];
+    Y = md.X[3 * g + 1];
+    const int cx = (int)floor(X) - 1 + (k & 3), cy = (int)floor(Y) - 1 + (k >> 2);
+    if (!(P.wall_y && (cy < 0 || cy >= P.ny))) {
+      const int yw = wrap(cy, P.ny), xw = wrap(cx, P.nx);
       const long long node = (long long)yw * P.nx + xw;
       double d = 0, jx = 0, jy = 0;
+#pragma unroll
       for (int i = 0; i < 9; i++) {
         const int sy = yw - L::cy[i];
         long long sn;
@@ -537,18 +559,22 @@ __global__ void k_interp2d(MemDev md, St cur, LBParams P, const double* __restri
         jy += L::cy[i] * v;
       }
       const double rho = 1.0 + d;
-      const double vx = (jx + 0.5 * force[2 * node]) / rho;
-      const double vy = (jy + 0.5 * force[2 * node + 1]) / rho;
-      const double w = wx[kx] * wy[ky];
-      Ux += vx * w;
-      Uy += vy * w;
+      const double w = peskin(cx - X) * peskin(cy - Y);
+      Ux = w * (jx + 0.5 * force[2 * node]) / rho;
+      Uy = w * (jy + 0.5 * force[2 * node + 1]) / rho;
     }
   }
-  md.U[3 * g] = Ux;
-  md.U[3 * g + 1] = Uy;
-  md.U[3 * g + 2] = 0.0;
-  md.X[3 * g] = X + Ux;
-  md.X[3 * g + 1] = Y + Uy;
+  for (int o = 8; o > 0; o >>= 1) {
+    Ux += __shfl_xor(Ux, o, 16);
+    Uy += __shfl_xor(Uy, o, 16);
+  }
+  if (live && k == 0) {
+    md.U[3 * g] = Ux;
+    md.U[3 * g + 1] = Uy;
+    md.U[3 * g + 2] = 0.0;
+    md.X[3 * g] = X + Ux;
+    md.X[3 * g + 1] = Y + Uy;
+  }
 }
 
 }  // namespace lb

@@ -10,12 +10,12 @@
 //
 // Dependency chain: the collision at row c needs grad mu at c, i.e. mu on
 // rows c-1..c+1, i.e. moments on rows c-2..c+2.  A workgroup owns a strip of
-// BX-4 interior columns (BX lanes, two halo columns each side) and marches up
-// a segment of rows with a three-stage software pipeline:
-//   iteration k:  M  pull row r = y0-2+k into registers, moments -> LDS ring
-//                 U  mu on row r-1 from the moment ring -> LDS ring
-//                 C  collide row r-2 with the populations pulled two
-//                    iterations earlier (still in registers) and store.
+// BX-4 interior columns (BX lanes, two halo columns each side) and marches
+// along a segment of rows (up or down) with a three-stage software pipeline:
+//   iteration k:  M  pull row r into registers, moments -> LDS ring
+//                 U  mu on the previous row from the moment ring -> LDS ring
+//                 C  collide the row before that with the populations pulled
+//                    two iterations earlier (still in registers) and store.
 // Halo columns are recomputed by the neighbouring strip; halo rows only at
 // segment ends.  Registers hold three rows of populations; the loop is
 // unrolled by three so every register index is a compile-time constant.
@@ -41,7 +41,24 @@ struct LBParams {
   long long N;
   int ntx, nty, tile;                        // tile grid of the membrane maps
   int seg;                                   // rows (2D) or planes (3D) per workgroup
+  int nstrip, nseg;                          // workgroup grid: strips x segments
+  int nxcd;                                  // XCDs the dispatcher deals workgroups to
 };
+
+// Workgroup -> (strip, segment).  The dispatcher deals consecutive
+// workgroups to the XCDs in turn, and each XCD has its own L2.  Give every
+// XCD a contiguous run of the logical order (strips fastest), so the strips
+// that share halo columns run side by side on one XCD and meet in its L2.
+__device__ __forceinline__ void strip_segment(int b, int nstrip, int nseg, int nxcd, int& s, int& g) {
+  const int total = nstrip * nseg;
+  const int c = b % nxcd, j = b / nxcd;
+  // blocks dealt to XCDs before c: sum over c' < c of ceil((total - c') / nxcd)
+  const int q = total / nxcd, rem = total % nxcd;
+  const int off = c * q + min(c, rem);
+  const int L = off + j;
+  s = L % nstrip;
+  g = L / nstrip;
+}
 
 // mu_rho (without the ideal-gas part), mu_phi, mu_psi' from local values and
 // Laplacians.  Written through the concentrations: with
@@ -138,69 +155,99 @@ __device__ __forceinline__ void pull9(const St& src, const LBParams& P, int x, i
   }
 }
 
+// moments of eq. MomentsDFs: the sums over the small values (f_i - w_i and
+// the moving g_i, h_i) run in R, the rest populations g_0, h_0 join in FP64
 template <typename R>
 __device__ __forceinline__ void moments9(const R* pf, const R* pg, const R* ph, double g0, double h0,
                                          double& d, double& jx, double& jy, double& phi,
                                          double& psi) {
   using L = Lattice<9>;
-  d = 0.0;
-  jx = 0.0;
-  jy = 0.0;
-  phi = g0;
-  psi = h0;
+  R sd = 0, sx = 0, sy = 0, sg = 0, sh = 0;
 #pragma unroll
   for (int i = 0; i < 9; i++) {
-    const double f = (double)pf[i];
-    d += f;
-    jx += L::cx[i] * f;
-    jy += L::cy[i] * f;
+    sd += pf[i];
+    if (L::cx[i] != 0) sx += R(L::cx[i]) * pf[i];
+    if (L::cy[i] != 0) sy += R(L::cy[i]) * pf[i];
     if (i > 0) {
-      phi += (double)pg[i];
-      psi += (double)ph[i];
+      sg += pg[i];
+      sh += ph[i];
     }
   }
+  d = (double)sd;
+  jx = (double)sx;
+  jy = (double)sy;
+  phi = g0 + (double)sg;
+  psi = h0 + (double)sh;
 }
 
-template <class St, typename R, int BX>
-__global__ __launch_bounds__(BX) void k_lb2d(St src, St dst, LBParams P,
-                                             const int* __restrict__ tflag,
-                                             const double* __restrict__ Ifield,
-                                             long long* __restrict__ fib,
-                                             double* __restrict__ force) {
+// NS = 3: each iteration pulls its row and then waits for it.  NS = 4: the
+// row of the next iteration is pulled at the start of this one (a register
+// ring of four rows), so the loads of one row are in flight while the
+// previous rows are computed.  WPE: waves per SIMD the register budget is
+// sized for.
+template <class St, typename R, int BX, int NS, int WPE>
+__global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
+                                                  const int* __restrict__ tflag,
+                                                  const int* __restrict__ tstate,
+                                                  const double* __restrict__ Ifield,
+                                                  long long* __restrict__ fib,
+                                                  double* __restrict__ force) {
+  static_assert(NS == 3 || NS == 4, "ring of three or four rows");
   constexpr int W = BX - 4;
   __shared__ double s_m[3][3][BX];  // moment ring [slot][drho, phi, psi][lane]
+  __shared__ double s_j[3][2][BX];  // momentum ring [slot][jx, jy][lane]
   __shared__ double s_u[3][3][BX];  // chemical-potential ring [slot][mu_rho, mu_phi, mu_psi'][lane]
 
   const int j = threadIdx.x;
-  const int xc = (int)blockIdx.x * W - 2 + j;
+  int strip, sgm;
+  strip_segment((int)blockIdx.x, P.nstrip, P.nseg, P.nxcd, strip, sgm);
+  const int xc = strip * W - 2 + j;
   const int x = wrap(xc, P.nx);
   const bool interior = (j >= 2) && (j < BX - 2) && (xc < P.nx);
-  const int y0 = (int)blockIdx.y * P.seg;
+  const int y0 = sgm * P.seg;
   const int y1 = min(y0 + P.seg, P.ny);
   const int K = (y1 - y0) + 4;
+  // even segments march up, odd ones down: neighbouring segments then read
+  // the rows they share at the same time (both at their start or both at
+  // their end)
+  const int dir = (sgm & 1) ? -1 : 1;
+  const int rbase = dir > 0 ? y0 - 2 : y1 + 1;
 
-  R pf[3][9], pg[3][9], ph[3][9];
-  double g0[3], h0[3];
+  const int stamp = tstate[1];  // tiles flagged with this step's stamp are active
+  R pf[NS][9], pg[NS][9], ph[NS][9];
+  double g0[NS], h0[NS];
+
+  auto load_row = [&](auto slot_c, int k) {
+    constexpr int S = decltype(slot_c)::value;
+    const int ry = fd_row(rbase + dir * k, P.ny, P.wall_y);
+    pull9(src, P, x, ry, pf[S], pg[S], ph[S], g0[S], h0[S]);
+  };
 
   auto body = [&](auto slot_c, int k) {
-    constexpr int S = decltype(slot_c)::value;
-    constexpr int SC = (S + 1) % 3;
-    const int r = y0 - 2 + k;
-    // ---- M: pull row r, moments -> ring slot k%3
+    constexpr int S = decltype(slot_c)::value;   // slot of row k
+    constexpr int SN = (S + 1) % NS;             // slot of row k+1
+    constexpr int SC = (S + NS - 2) % NS;        // slot of row k-2 (collided now)
+    const int r = rbase + dir * k;               // row whose moments are formed now
+    if constexpr (NS == 4) {
+      if (k + 1 < K) load_row(std::integral_constant<int, SN>{}, k + 1);
+    } else {
+      load_row(std::integral_constant<int, S>{}, k);
+    }
+    // ---- M: moments of row r -> ring slot k%3
     {
-      const int ry = fd_row(r, P.ny, P.wall_y);
-      pull9(src, P, x, ry, pf[S], pg[S], ph[S], g0[S], h0[S]);
       double d, jx, jy, phi, psi;
       moments9(pf[S], pg[S], ph[S], g0[S], h0[S], d, jx, jy, phi, psi);
       const int sl = k % 3;
       s_m[sl][0][j] = d;
       s_m[sl][1][j] = phi;
       s_m[sl][2][j] = psi;
+      s_j[sl][0][j] = jx;
+      s_j[sl][1][j] = jy;
     }
     __syncthreads();
-    // ---- U: chemical potentials on row r-1 -> ring slot k%3
+    // ---- U: chemical potentials on the previous row -> ring slot k%3
     if (k >= 2 && j >= 1 && j < BX - 1) {
-      const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // rows r-2, r-1, r
+      const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // rows r-2dir, r-dir, r
       double lap[3], ctr[3];
 #pragma unroll
       for (int f = 0; f < 3; f++) {
@@ -213,9 +260,9 @@ __global__ __launch_bounds__(BX) void k_lb2d(St src, St dst, LBParams P,
         lap[f] = (2.0 / 3.0) * n4 + (1.0 / 6.0) * n8;
         ctr[f] = q;
       }
-      const int qy = fd_row(r - 1, P.ny, P.wall_y);
+      const int qy = fd_row(r - dir, P.ny, P.wall_y);
       double I = 0.0;
-      if (tflag[(qy / P.tile) * P.ntx + x / P.tile]) I = Ifield[(long long)qy * P.nx + x];
+      if (tflag[(qy / P.tile) * P.ntx + x / P.tile] == stamp) I = Ifield[(long long)qy * P.nx + x];
       double mr, mp, ms;
       chem_pot(P, ctr[0], ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
       const int sl = k % 3;
@@ -224,29 +271,31 @@ __global__ __launch_bounds__(BX) void k_lb2d(St src, St dst, LBParams P,
       s_u[sl][2][j] = ms;
     }
     __syncthreads();
-    // ---- C: collide row r-2 with the registers of slot SC
+    // ---- C: collide row r - 2 dir with the registers of slot SC
     if (k >= 4 && interior) {
-      const int cy = r - 2;
-      const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // mu rows cy-1, cy, cy+1
-      double d, jx, jy, phi, psi;
-      moments9(pf[SC], pg[SC], ph[SC], g0[SC], h0[SC], d, jx, jy, phi, psi);
+      const int cy = r - 2 * dir;
+      const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // mu rows cy-dir, cy, cy+dir
+      const int sn = dir > 0 ? c : a, ss = dir > 0 ? a : c;   // north (cy+1) and south (cy-1)
+      // moments of row cy were stored two iterations ago (slot (k-2)%3 = a)
+      const double d = s_m[a][0][j], phi = s_m[a][1][j], psi = s_m[a][2][j];
+      const double jx = s_j[a][0][j], jy = s_j[a][1][j];
       // grad mu = 3 sum_i w_i c_i mu(x + c_i)
       double gx[3], gy[3];
 #pragma unroll
       for (int f = 0; f < 3; f++) {
         const double e = s_u[b][f][j + 1], wv = s_u[b][f][j - 1];
-        const double nn = s_u[c][f][j], ss = s_u[a][f][j];
-        const double ne = s_u[c][f][j + 1], nw = s_u[c][f][j - 1];
-        const double se = s_u[a][f][j + 1], sw = s_u[a][f][j - 1];
+        const double nn = s_u[sn][f][j], so = s_u[ss][f][j];
+        const double ne = s_u[sn][f][j + 1], nw = s_u[sn][f][j - 1];
+        const double se = s_u[ss][f][j + 1], sw = s_u[ss][f][j - 1];
         gx[f] = (1.0 / 3.0) * (e - wv) + (1.0 / 12.0) * ((ne - nw) + (se - sw));
-        gy[f] = (1.0 / 3.0) * (nn - ss) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
+        gy[f] = (1.0 / 3.0) * (nn - so) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
       }
       const double rho = 1.0 + d;
       // thermodynamic force, eq. ForceFE with eq. GradPT (potential form)
       double Fx = -(rho * gx[0] + phi * gx[1] + psi * gx[2]);
       double Fy = -(rho * gy[0] + phi * gy[1] + psi * gy[2]);
       const long long node = (long long)cy * P.nx + x;
-      if (tflag[(cy / P.tile) * P.ntx + x / P.tile]) {
+      if (tflag[(cy / P.tile) * P.ntx + x / P.tile] == stamp) {
         long long* fp = fib + 2 * node;
         Fx += from_fix(fp[0]);
         Fy += from_fix(fp[1]);
@@ -269,10 +318,13 @@ __global__ __launch_bounds__(BX) void k_lb2d(St src, St dst, LBParams P,
     }
   };
 
-  for (int kb = 0; kb < K; kb += 3) {
+  if constexpr (NS == 4) load_row(std::integral_constant<int, 0>{}, 0);
+  for (int kb = 0; kb < K; kb += NS) {
     body(std::integral_constant<int, 0>{}, kb);
     if (kb + 1 < K) body(std::integral_constant<int, 1>{}, kb + 1);
     if (kb + 2 < K) body(std::integral_constant<int, 2>{}, kb + 2);
+    if constexpr (NS == 4)
+      if (kb + 3 < K) body(std::integral_constant<int, 3>{}, kb + 3);
   }
 }
 

@@ -15,7 +15,8 @@ template <class St, typename R>
 __global__ void k_init2d(St dst, LBParams P, const double* __restrict__ rho,
                          const double* __restrict__ phi, const double* __restrict__ psi,
                          const double* __restrict__ ux, const double* __restrict__ uy,
-                         const int* __restrict__ tflag, const double* __restrict__ Ifield) {
+                         const int* __restrict__ tflag, const int* __restrict__ tstate,
+                         const double* __restrict__ Ifield) {
   using L = Lattice<9>;
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= P.N) return;
@@ -32,7 +33,7 @@ __global__ void k_init2d(St dst, LBParams P, const double* __restrict__ rho,
     lap[f] = 6.0 * acc;
   }
   double I = 0;
-  if (tflag[(y / P.tile) * P.ntx + x / P.tile]) I = Ifield[n];
+  if (tflag[(y / P.tile) * P.ntx + x / P.tile] == tstate[1]) I = Ifield[n];
   double mr, mp, ms;
   chem_pot(P, ctr[0] - 1.0, ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
   const double u0 = ux ? ux[n] : 0.0, u1 = uy ? uy[n] : 0.0;
@@ -97,6 +98,7 @@ __global__ void k_moments2d(St cur, LBParams P, double* __restrict__ out) {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_energy_nodes2d(LBParams P, const double* __restrict__ mom,
                                                        const int* __restrict__ tflag,
+                                                       const int* __restrict__ tstate,
                                                        const double* __restrict__ Ifield,
                                                        double* __restrict__ part) {
   using L = Lattice<9>;
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(NT) void k_energy_nodes2d(LBParams P, const double*
       v[4] += 0.5 * P.a2 * kap[m] * (gx * gx + gy * gy);
     }
     double I = 0;
-    if (tflag[(y / P.tile) * P.ntx + x / P.tile]) I = Ifield[n];
+    if (tflag[(y / P.tile) * P.ntx + x / P.tile] == tstate[1]) I = Ifield[n];
     const double psi = mom[3 * P.N + n];
     v[5] = 0.5 * P.kc * (psi - I) * (psi - I);
     const double rho = mom[n], ux = mom[4 * P.N + n], uy = mom[5 * P.N + n];

@@ -51,7 +51,7 @@ struct Carver {
 struct Layout {
   size_t pops[2];       // population buffers A, B
   size_t pop_bytes;     // bytes of one buffer
-  size_t Ifield, fib, force, tflag, tlist, tcount, stage, part;
+  size_t Ifield, fib, force, tflag, tlist, tstate, stage, part;
   size_t X, U, F, Facc, rest, moff, mid, ks, kb, mbox, status, memE;
   size_t total;
   long long ntiles;
@@ -103,7 +103,7 @@ Layout make_layout(const lbib_params* p) {
   L.force = c.take((size_t)N * D * 8);
   L.tflag = c.take((size_t)L.ntiles * 4);
   L.tlist = c.take((size_t)L.ntiles * 4);
-  L.tcount = c.take(64);
+  L.tstate = c.take(64);
   L.stage = c.take((size_t)N * 8 * 8);
   L.part = c.take((size_t)((N + 255) / 256 + 1) * 8 * 8 + (size_t)M * 2 * 8);
   L.X = c.take((size_t)M * 3 * 8);
@@ -115,7 +115,7 @@ Layout make_layout(const lbib_params* p) {
   L.mid = c.take((size_t)M * 4);
   L.ks = c.take((size_t)K * 8);
   L.kb = c.take((size_t)K * 8);
-  L.mbox = c.take((size_t)K * 6 * 8);
+  L.mbox = c.take((size_t)K * 8 * 8);
   L.status = c.take(64);
   L.memE = c.take(64);
   L.total = c.off;
@@ -138,7 +138,9 @@ struct lbib_sim {
   int K = 0, M = 0;
   std::vector<int> moff{0};
   double r_cut = 0;
-  int bx = 64, seg = 64;  // fused-kernel launch shape
+  int bx = 256, seg = 0;  // fused-kernel launch shape (seg 0: automatic)
+  int nxcd = 1;           // L2 domains workgroups are dealt to (1: plain strip order)
+  int ring = 3;           // rows in the fused kernel's register ring (4: prefetch)
   // optional per-phase timing with HIP events on the stream
   int timing = 0;  // bit mask of timed phases
   std::vector<hipEvent_t> ev_pool;
@@ -213,7 +215,7 @@ struct lbib_sim {
     TileMap t;
     t.tflag = at<int>(L.tflag);
     t.tlist = at<int>(L.tlist);
-    t.tcount = at<int>(L.tcount);
+    t.tstate = at<int>(L.tstate);
     t.ntx = L.ntx;
     t.nty = L.nty;
     t.ntz = L.ntz;
@@ -295,37 +297,77 @@ struct Engine2D final : lbib_sim {
     if (K == 0) return LBIB_OK;
     MemDev md = memdev();
     TileMap tm = tilemap();
-    hipLaunchKernelGGL(k_tiles<1024>, dim3(1), dim3(1024), 0, stream, md, tm, p.nx, p.ny, 1,
-                       p.wall_y, 0, 2, r_cut + 3.0);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
+    hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, 1, p.wall_y,
+                       0, 2, r_cut + 3.0);
     const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 2048);
     hipLaunchKernelGGL((k_coupling2d<St, R, COUP_THREADS>), dim3(grid), dim3(COUP_THREADS), 0, stream,
                        md, tm, coup_args(want_force), at<double>(L.Ifield), store(cur));
     return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
   }
 
-  void launch_lb(St src, St dst) {
-    P.seg = seg;
+  // kernel variant for the current (bx, ring)
+  const void* lb_kernel() const {
+    if (ring == 4) {
+      if (bx == 128) return (const void*)&k_lb2d<St, R, 128, 4, 2>;
+      if (bx == 256) return (const void*)&k_lb2d<St, R, 256, 4, 2>;
+      return (const void*)&k_lb2d<St, R, 64, 4, 2>;
+    }
+    if (bx == 128) return (const void*)&k_lb2d<St, R, 128, 3, 3>;
+    if (bx == 256) return (const void*)&k_lb2d<St, R, 256, 3, 3>;
+    return (const void*)&k_lb2d<St, R, 64, 3, 3>;
+  }
+
+  // rows per workgroup: with seg = 0 (automatic), the whole lattice is cut
+  // into exactly as many (strip, segment) workgroups as can be resident at
+  // once, so no partial last round of workgroups stretches the launch
+  int pick_seg() const {
+    if (seg > 0) return seg;
     const int W = bx - 4;
-    dim3 grid((p.nx + W - 1) / W, (p.ny + seg - 1) / seg);
+    const long long nstrip = (p.nx + W - 1) / W;
+    int per_cu = 0, ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lb_kernel(), bx, 0) != hipSuccess ||
+        per_cu <= 0 || ncu <= 0)
+      return std::max(4, std::min(p.ny, 16));
+    const long long slots = (long long)per_cu * ncu;
+    const long long rows = (p.ny * nstrip + slots - 1) / slots;
+    return (int)std::max(4LL, std::min<long long>(p.ny, rows));
+  }
+
+  void launch_lb(St src, St dst) {
+    P.seg = pick_seg();
+    const int W = bx - 4;
+    P.nstrip = (p.nx + W - 1) / W;
+    P.nseg = (p.ny + P.seg - 1) / P.seg;
+    P.nxcd = nxcd;
+    dim3 grid(P.nstrip * P.nseg);
     const int* tf = at<int>(L.tflag);
+    const int* ts = at<int>(L.tstate);
     const double* If = at<double>(L.Ifield);
     long long* fib = at<long long>(L.fib);
     double* frc = at<double>(L.force);
-    switch (bx) {
-      case 128:
-        hipLaunchKernelGGL((k_lb2d<St, R, 128>), grid, dim3(128), 0, stream, src, dst, P, tf, If, fib, frc);
-        break;
-      case 256:
-        hipLaunchKernelGGL((k_lb2d<St, R, 256>), grid, dim3(256), 0, stream, src, dst, P, tf, If, fib, frc);
-        break;
-      default:
-        hipLaunchKernelGGL((k_lb2d<St, R, 64>), grid, dim3(64), 0, stream, src, dst, P, tf, If, fib, frc);
+    // (lanes, ring depth, waves per SIMD) variants of the fused kernel
+#define LB_LAUNCH(BXV, NSV, WPEV)                                                                  \
+  hipLaunchKernelGGL((k_lb2d<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, stream, src, dst, P, tf, ts, \
+                     If, fib, frc)
+    if (ring == 4) {
+      if (bx == 128) LB_LAUNCH(128, 4, 2);
+      else if (bx == 256) LB_LAUNCH(256, 4, 2);
+      else LB_LAUNCH(64, 4, 2);
+    } else {
+      if (bx == 128) LB_LAUNCH(128, 3, 3);
+      else if (bx == 256) LB_LAUNCH(256, 3, 3);
+      else LB_LAUNCH(64, 3, 3);
     }
+#undef LB_LAUNCH
   }
 
   int step() override {
     MemDev md = memdev();
     const int mb = (M + 255) / 256;
+    const int mb16 = (16 * M + 255) / 256;  // sixteen lanes per marker
     if (K > 0) {
       hipEvent_t t0 = tbeg(1);
       int rc = coupling(1);
@@ -333,7 +375,7 @@ struct Engine2D final : lbib_sim {
       tend(1, t0);
       t0 = tbeg(2);
       hipLaunchKernelGGL(k_memforce2d, dim3(mb), dim3(256), 0, stream, md);
-      hipLaunchKernelGGL(k_spread2d, dim3(mb), dim3(256), 0, stream, md, at<long long>(L.fib), p.nx,
+      hipLaunchKernelGGL(k_spread2d, dim3(mb16), dim3(256), 0, stream, md, at<long long>(L.fib), p.nx,
                          p.ny, p.wall_y);
       tend(2, t0);
     }
@@ -342,7 +384,7 @@ struct Engine2D final : lbib_sim {
     tend(0, t1);
     if (K > 0) {
       hipEvent_t t2 = tbeg(3);
-      hipLaunchKernelGGL((k_interp2d<St, R>), dim3(mb), dim3(256), 0, stream, md, store(1 - cur), P,
+      hipLaunchKernelGGL((k_interp2d<St, R>), dim3(mb16), dim3(256), 0, stream, md, store(1 - cur), P,
                          (const double*)at<double>(L.force));
       tend(3, t2);
     }
@@ -363,7 +405,7 @@ struct Engine2D final : lbib_sim {
     const int nb = (int)((N + 255) / 256);
     hipLaunchKernelGGL((k_init2d<St, R>), dim3(nb), dim3(256), 0, stream, store(cur), P, st, st + N,
                        st + 2 * N, st + 3 * N, st + 4 * N, (const int*)at<int>(L.tflag),
-                       (const double*)at<double>(L.Ifield));
+                       (const int*)at<int>(L.tstate), (const double*)at<double>(L.Ifield));
     return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
   }
 
@@ -377,7 +419,7 @@ struct Engine2D final : lbib_sim {
     const long long nb = (N + 255) / 256;
     hipLaunchKernelGGL((k_energy_nodes2d<256>), dim3((unsigned)nb), dim3(256), 0, stream, P,
                        (const double*)at<double>(L.stage), (const int*)at<int>(L.tflag),
-                       (const double*)at<double>(L.Ifield), part);
+                       (const int*)at<int>(L.tstate), (const double*)at<double>(L.Ifield), part);
     *nblk = nb;
     return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
   }
@@ -431,15 +473,14 @@ int lbib_create(const lbib_params* p, void* ws, size_t ws_bytes, void* stream, l
   s->D = p->lattice == LBIB_D2Q9 ? 2 : 3;
   s->N = (long long)p->nx * p->ny * p->nz;
   s->r_cut = p->r_cut > 0 ? p->r_cut : 17.0 * p->alpha;
-  s->bx = 64;
-  s->seg = std::max(4, std::min(p->ny, 64));
+  s->seg = 0;  // automatic: one resident round of workgroups
   s->setup();
   // zero the maps, accumulators and counters (fill kernels would do as well;
   // memset is only used here, outside any step)
   hipStream_t st = s->stream;
   if (hipMemsetAsync(s->ws + L.fib, 0, (size_t)s->N * s->D * 8, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.tflag, 0, (size_t)L.ntiles * 4, st) != hipSuccess ||
-      hipMemsetAsync(s->ws + L.tcount, 0, 64, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.tstate, 0, 64, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.Facc, 0, (size_t)std::max(p->max_markers, 1) * 3 * 8, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.status, 0, 64, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.force, 0, (size_t)s->N * s->D * 8, st) != hipSuccess ||
@@ -528,6 +569,28 @@ int lbib_step(lbib_sim* s, int n) {
 }
 
 long long lbib_steps_done(const lbib_sim* s) { return s ? s->steps : -1; }
+
+int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
+  if (!s) return LBIB_EINVAL;
+  if (ring != 0 && ring != 3 && ring != 4) return LBIB_EINVAL;
+  if (ring) s->ring = ring;
+  if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 256) return LBIB_EINVAL;
+  if (seg < -1 || nxcd < 0 || nxcd > 64) return LBIB_EINVAL;
+  if (block_x) s->bx = block_x;
+  if (seg > 0) s->seg = std::max(1, std::min(seg, s->p.ny));
+  if (seg < 0) s->seg = 0;  // back to automatic
+  if (nxcd) s->nxcd = nxcd;
+  return LBIB_OK;
+}
+
+int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* ring) {
+  if (!s) return LBIB_EINVAL;
+  if (ring) *ring = s->ring;
+  if (block_x) *block_x = s->bx;
+  if (seg) *seg = s->seg;
+  if (nxcd) *nxcd = s->nxcd;
+  return LBIB_OK;
+}
 
 int lbib_timing_enable(lbib_sim* s, int on) {
   if (!s) return LBIB_EINVAL;

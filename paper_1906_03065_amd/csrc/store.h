@@ -28,6 +28,8 @@
 
 namespace lb {
 
+typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+
 // all planes in one type T (FP32 or FP64): p[(set * Q + i) * N + node]
 template <typename T, int Q>
 struct PlainStore {
@@ -55,6 +57,11 @@ struct PlainStore {
 //   g_i:   p[(Q + i - 1) * N + node]          i >= 1
 //   h_i:   p[(2Q - 1 + i - 1) * N + node]     i >= 1
 //   g_0:   r[node], h_0: r[N + node]
+// (The buffer builtins move raw 32/64-bit words; values are bit-cast.)
+// Accesses go through buffer resources: the plane offset is a uniform
+// (scalar) byte offset and the node a 32-bit per-lane offset, so one address
+// register serves the three populations that travel along the same link.
+// The FP32 planes of one buffer must stay below 4 GiB (checked on the host).
 template <int Q>
 struct MixStore {
   float* p;
@@ -63,27 +70,41 @@ struct MixStore {
   __device__ __forceinline__ static long long plane(int set, int i) {
     return set == 0 ? i : (set == 1 ? Q + i - 1 : 2 * Q - 1 + i - 1);
   }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rp() const {
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)0xffffffffu, 0x00020000);
+  }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rr() const {
+    return __builtin_amdgcn_make_buffer_rsrc(r, 0, (int)0xffffffffu, 0x00020000);
+  }
   template <typename R>
   __device__ __forceinline__ R load(int set, int i, long long node) const {
-    if (set > 0 && i == 0) return (R)r[(long long)(set - 1) * N + node];
-    return (R)p[plane(set, i) * N + node];
+    if (set > 0 && i == 0) return (R)rest(set, node);
+    return (R)__builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(rp(), (int)(node * 4), (int)(plane(set, i) * N * 4), 0));
   }
   __device__ __forceinline__ double rest(int set, long long node) const {
-    if (set == 0) return (double)p[node];
-    return r[(long long)(set - 1) * N + node];
+    if (set == 0)
+      return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp(), (int)(node * 4), 0, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                          rr(), (int)(node * 8), (int)((long long)(set - 1) * N * 8), 0));
   }
   template <typename R>
   __device__ __forceinline__ void store(int set, int i, long long node, R v) const {
-    if (set > 0 && i == 0)
-      r[(long long)(set - 1) * N + node] = (double)v;
-    else
-      p[plane(set, i) * N + node] = (float)v;
+    if (set > 0 && i == 0) {
+      store_rest(set, node, (double)v);
+      return;
+    }
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), rp(), (int)(node * 4),
+                                          (int)(plane(set, i) * N * 4), 0);
   }
   __device__ __forceinline__ void store_rest(int set, long long node, double v) const {
-    if (set == 0)
-      p[node] = (float)v;
-    else
-      r[(long long)(set - 1) * N + node] = v;
+    if (set == 0) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)v), rp(), (int)(node * 4), 0,
+                                            0);
+      return;
+    }
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rr(), (int)(node * 8),
+                                          (int)((long long)(set - 1) * N * 8), 0);
   }
   static constexpr long long float_planes() { return 3LL * Q - 2; }
   static constexpr long long bytes_per_node() { return float_planes() * 4 + 2 * 8; }

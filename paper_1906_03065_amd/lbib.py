@@ -65,6 +65,8 @@ SIGNATURES = [
     ("lbib_load", C.c_int, [_vp, _vp, C.c_size_t]),
     ("lbib_timing_enable", C.c_int, [_vp, C.c_int]),
     ("lbib_timing_read", C.c_int, [_vp, _dp, C.c_int, _ip]),
+    ("lbib_set_launch", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("lbib_get_launch", C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     ("lbib_steps_done", C.c_longlong, [_vp]),
     ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
     ("lbib_strerror", C.c_char_p, [C.c_int]),
@@ -225,6 +227,16 @@ class Sim:
 
     def poke(self, field: int, idx: int, value: float):
         _chk("lbib_debug_poke", lib().lbib_debug_poke(self.h, field, int(idx), float(value)))
+
+    def set_launch(self, block_x=0, seg=0, nxcd=0, ring=0):
+        _chk("lbib_set_launch", lib().lbib_set_launch(self.h, int(block_x), int(seg), int(nxcd),
+                                                      int(ring)))
+
+    def get_launch(self):
+        a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        _chk("lbib_get_launch", lib().lbib_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c),
+                                                      C.byref(d)))
+        return {"block_x": a.value, "seg": b.value, "nxcd": c.value, "ring": d.value}
 
     def timing(self, mask: int = 15):
         """Time the phases in ``mask`` (bit 0 lattice kernel, 1 coupling,
