@@ -306,6 +306,24 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
       }
       collide9(P, pf[SC], pg[SC], ph[SC], g0[SC], h0[SC], d, jx, jy, phi, psi, s_u[b][1][j],
                s_u[b][2][j], Fx, Fy);
+      if constexpr (St::kQuantized) {
+        // moving populations are stored rounded; the rest population of the
+        // same set takes the rounding so the node's mass per set is exact
+        R ef = 0, eg = 0, eh = 0;
+#pragma unroll
+        for (int i = 1; i < 9; i++) {
+          const R qf = dst.quantize(pf[SC][i]), qg = dst.quantize(pg[SC][i]), qh = dst.quantize(ph[SC][i]);
+          ef += pf[SC][i] - qf;
+          eg += pg[SC][i] - qg;
+          eh += ph[SC][i] - qh;
+          pf[SC][i] = qf;
+          pg[SC][i] = qg;
+          ph[SC][i] = qh;
+        }
+        pf[SC][0] += ef;
+        g0[SC] += (double)eg;
+        h0[SC] += (double)eh;
+      }
       dst.template store<R>(0, 0, node, pf[SC][0]);
       dst.store_rest(1, node, g0[SC]);
       dst.store_rest(2, node, h0[SC]);

@@ -52,6 +52,14 @@ __global__ void k_init2d(St dst, LBParams P, const double* __restrict__ rho,
   }
   E[1][0] = ctr[1] - gs;
   E[2][0] = ctr[2] - hs;
+  if constexpr (St::kQuantized) {
+    for (int s = 0; s < 3; s++)
+      for (int i = 1; i < 9; i++) {
+        const double q = (double)dst.quantize((R)E[s][i]);
+        E[s][0] += E[s][i] - q;
+        E[s][i] = q;
+      }
+  }
   for (int i = 0; i < 9; i++) {
     const int sy = y - L::cy[i];
     long long tn;

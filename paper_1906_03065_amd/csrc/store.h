@@ -49,6 +49,9 @@ struct PlainStore {
   __device__ __forceinline__ void store_rest(int set, long long node, double v) const {
     p[((long long)(set * Q)) * N + node] = (T)v;
   }
+  static constexpr bool kQuantized = false;
+  template <typename R>
+  __device__ __forceinline__ R quantize(R v) const { return v; }
   static constexpr long long bytes_per_node() { return 3LL * Q * (long long)sizeof(T); }
 };
 
@@ -106,6 +109,9 @@ struct MixStore {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rr(), (int)(node * 8),
                                           (int)((long long)(set - 1) * N * 8), 0);
   }
+  static constexpr bool kQuantized = false;
+  template <typename R>
+  __device__ __forceinline__ R quantize(R v) const { return v; }
   static constexpr long long float_planes() { return 3LL * Q - 2; }
   static constexpr long long bytes_per_node() { return float_planes() * 4 + 2 * 8; }
 };
@@ -141,9 +147,13 @@ struct Split16Store {
   __device__ __forceinline__ void store_rest(int set, long long node, double v) const {
     rst[(long long)set * N + node] = (float)v;
   }
-  // the value a moving population reads back as after a store
-  __device__ __forceinline__ float quantize(float v) const {
-    return to_float(from_float(v * kScale)) * kInv;
+  // the value a moving population reads back as after a store; the collision
+  // adds the difference to the rest population of the same node and set, so
+  // every set's mass survives the rounding exactly (up to FP32)
+  static constexpr bool kQuantized = true;
+  template <typename R>
+  __device__ __forceinline__ R quantize(R v) const {
+    return (R)(to_float(from_float((float)v * kScale)) * kInv);
   }
   __device__ static __forceinline__ float to_float(__half h) { return __half2float(h); }
   __device__ static __forceinline__ float to_float(__hip_bfloat16 h) { return __bfloat162float(h); }

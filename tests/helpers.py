@@ -37,3 +37,43 @@ def marker_err(g, o, n_mem):
     for i in range(n_mem):
         e = max(e, float(np.abs(g.membrane(i)["X"] - o.membrane(i)["X"]).max()))
     return e
+
+
+def pressure(f, kap):
+    """p = sum_m C_m dF/dC_m - f + c_s^2 rho with the Landau energy (the
+    bulk pressure definition), evaluated from concentration fields."""
+    C = [f["c1"], f["c2"], f["c3"]]
+    p = f["rho"] / 3.0
+    for k, c in zip(kap, C):
+        p = p + c * k * c * (1 - c) * (1 - 2 * c) - 0.5 * k * c * c * (1 - c) ** 2
+    return p
+
+
+def contour(c3, level=0.5):
+    """Points where a 2D field crosses level, from row and column scans."""
+    pts = []
+    a = c3 - level
+    for y in range(a.shape[0]):
+        r = a[y]
+        for i in np.where(np.sign(r[:-1]) != np.sign(r[1:]))[0]:
+            pts.append((i + r[i] / (r[i] - r[i + 1]), y))
+    for x in range(a.shape[1]):
+        c = a[:, x]
+        for i in np.where(np.sign(c[:-1]) != np.sign(c[1:]))[0]:
+            pts.append((x, i + c[i] / (c[i] - c[i + 1])))
+    return np.array(pts)
+
+
+def lens_angles(c3, y0, margin=4.0):
+    """Cap angles of a lens at y = y0 from circle fits to the C3 = 1/2 contour
+    above and below the interface."""
+    P = contour(c3)
+
+    def circ(Q):
+        A = np.c_[2 * Q[:, 0], 2 * Q[:, 1], np.ones(len(Q))]
+        s = np.linalg.lstsq(A, (Q ** 2).sum(1), rcond=None)[0]
+        return s[0], s[1], np.sqrt(s[2] + s[0] ** 2 + s[1] ** 2)
+
+    _, yu, ru = circ(P[P[:, 1] > y0 + margin])
+    _, yd, rd = circ(P[P[:, 1] < y0 - margin])
+    return np.degrees(np.arccos((y0 - yu) / ru)), np.degrees(np.arccos((yd - y0) / rd))
