@@ -134,9 +134,12 @@ __global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int
     }
   const int dims[3] = {nx, ny, nz};
   const int per[3] = {1, !wall_y, !wall_z};
-  // the periodic image of a node must be unique within the grown box
+  // the periodic image of a node must be unique within the grown box; the 2D
+  // coupling kernel also needs every node of a tile in the tile centre's
+  // image (the 3D kernel searches such tiles node by node)
+  const double slack = D == 2 ? 2.0 * tm.tile : 0.0;
   for (int a = 0; a < D; a++)
-    if (per[a] && hi[a] - lo[a] + 2.0 * reach + 2.0 * tm.tile >= dims[a] && tid == 0)
+    if (per[a] && hi[a] - lo[a] + 2.0 * reach + slack >= dims[a] && tid == 0)
       md.status[1] = 1;
   int t0[3] = {0, 0, 0}, t1[3] = {0, 0, 0};
   const int nt[3] = {tm.ntx, tm.nty, tm.ntz};

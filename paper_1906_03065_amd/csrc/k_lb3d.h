@@ -1,0 +1,300 @@
+// k_lb3d.h -- the lattice-Boltzmann step (Sec. 3.1) on D3Q19.
+//
+// Two kernels per step:
+//   k_mom3d   pull-streams every node and writes its moments drho, phi and
+//             psi (FP64) to a moment field (24 B per node);
+//   k_lb3d    a workgroup owns a 16 x 16 column of nodes and marches along
+//             z.  Per plane it stages the moments of a 20 x 20 region in an
+//             LDS ring, forms mu on the inner 18 x 18 region (Appendix A),
+//             then for its 16 x 16 nodes pulls the populations, forms grad mu,
+//             the force (eqs. ForcingTermLBE, ForceFE + the spread membrane
+//             force) and collides (eq. LBE).
+// In 3D the two-node halo of the mu chain would make a single-pass kernel
+// re-read the 55 populations of (T+4)^2/T^2 as many nodes; staging 24 B of
+// moments instead costs one extra read of the populations per step.
+// Precision follows the 2D kernel: moments, mu and grad mu in FP64.
+#pragma once
+#include "common.h"
+#include "k_lb.h"
+#include "store.h"
+
+namespace lb {
+
+constexpr int T3 = 16;       // interior tile edge (x and y)
+constexpr int T3H = T3 + 4;  // with the two-node halo
+constexpr int T3U = T3 + 2;  // region where mu is formed
+
+struct Moments3 {
+  double* d;     // drho = rho - 1
+  double* phi;
+  double* psi;
+};
+
+// pull the populations of node (x, y, z); bounce-back across walls in y, z
+template <class St, typename R>
+__device__ __forceinline__ void pull19(const St& src, const LBParams& P, int x, int y, int z, R* pf,
+                                       R* pg, R* ph, double& g0, double& h0) {
+  using L = Lattice<19>;
+  const long long here = ((long long)z * P.ny + y) * P.nx + x;
+  pf[0] = src.template load<R>(0, 0, here);
+  g0 = src.rest(1, here);
+  h0 = src.rest(2, here);
+#pragma unroll
+  for (int i = 1; i < 19; i++) {
+    const int sy = y - L::cy[i], sz = z - L::cz[i];
+    long long node;
+    int dir = i;
+    if ((P.wall_y && (sy < 0 || sy >= P.ny)) || (P.wall_z && (sz < 0 || sz >= P.nz))) {
+      node = here;
+      dir = L::opp[i];
+    } else {
+      node = ((long long)wrap(sz, P.nz) * P.ny + wrap(sy, P.ny)) * P.nx + wrap(x - L::cx[i], P.nx);
+    }
+    pf[i] = src.template load<R>(0, dir, node);
+    pg[i] = src.template load<R>(1, dir, node);
+    ph[i] = src.template load<R>(2, dir, node);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void moments19(const R* pf, const R* pg, const R* ph, double g0, double h0,
+                                          double& d, double& jx, double& jy, double& jz, double& phi,
+                                          double& psi) {
+  using L = Lattice<19>;
+  R sd = 0, sx = 0, sy = 0, sz = 0, sg = 0, sh = 0;
+#pragma unroll
+  for (int i = 0; i < 19; i++) {
+    sd += pf[i];
+    if (L::cx[i] != 0) sx += R(L::cx[i]) * pf[i];
+    if (L::cy[i] != 0) sy += R(L::cy[i]) * pf[i];
+    if (L::cz[i] != 0) sz += R(L::cz[i]) * pf[i];
+    if (i > 0) {
+      sg += pg[i];
+      sh += ph[i];
+    }
+  }
+  d = (double)sd;
+  jx = (double)sx;
+  jy = (double)sy;
+  jz = (double)sz;
+  phi = g0 + (double)sg;
+  psi = h0 + (double)sh;
+}
+
+template <class St, typename R>
+__global__ __launch_bounds__(256) void k_mom3d(St src, LBParams P, Moments3 M) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= P.N) return;
+  const int x = (int)(n % P.nx), y = (int)((n / P.nx) % P.ny), z = (int)(n / ((long long)P.nx * P.ny));
+  R pf[19], pg[19], ph[19];
+  double g0, h0, d, jx, jy, jz, phi, psi;
+  pull19(src, P, x, y, z, pf, pg, ph, g0, h0);
+  moments19(pf, pg, ph, g0, h0, d, jx, jy, jz, phi, psi);
+  M.d[n] = d;
+  M.phi[n] = phi;
+  M.psi[n] = psi;
+}
+
+// BGK + exact-difference collision of one D3Q19 node, in place
+template <typename R>
+__device__ __forceinline__ void collide19(const LBParams& P, R* pf, R* pg, R* ph, double& g0,
+                                          double& h0, double drho, double jx, double jy, double jz,
+                                          double phi, double psi, double mphi, double mpsi,
+                                          double Fx, double Fy, double Fz) {
+  using L = Lattice<19>;
+  const double rho = 1.0 + drho;
+  const double irho = 1.0 / rho;
+  const double uxd = jx * irho, uyd = jy * irho, uzd = jz * irho;
+  const double dxd = Fx * irho, dyd = Fy * irho, dzd = Fz * irho;  // eq. VelCorrection
+  const R ux = (R)uxd, uy = (R)uyd, uz = (R)uzd;
+  const R vx = (R)(uxd + 0.5 * dxd), vy = (R)(uyd + 0.5 * dyd), vz = (R)(uzd + 0.5 * dzd);
+  const R wx = (R)(uxd + dxd), wy = (R)(uyd + dyd), wz = (R)(uzd + dzd);
+  const R uu = ux * ux + uy * uy + uz * uz, ww = wx * wx + wy * wy + wz * wz;
+  const R vv = vx * vx + vy * vy + vz * vz;
+  const R rr = (R)rho, dr = (R)drho, ph_ = (R)phi, ps_ = (R)psi;
+  const R gm = (R)(3.0 * P.gphi * mphi), hm = (R)(3.0 * P.gpsi * mpsi);
+  const R itf = (R)P.inv_tau, itg = (R)P.inv_tau_phi, ith = (R)P.inv_tau_psi;
+  double gsum = 0.0, hsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 19; i++) {
+    const R w = R(L::w(i));
+    const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
+    const R cw = R(L::cx[i]) * wx + R(L::cy[i]) * wy + R(L::cz[i]) * wz;
+    const R pu = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+    const R pw = R(3) * cw + R(4.5) * cw * cw - R(1.5) * ww;
+    const R feq = w * (dr + rr * pu);
+    const R edm = w * rr * (pw - pu);
+    pf[i] = pf[i] - (pf[i] - feq) * itf + edm;
+    if (i > 0) {
+      const R cv = R(L::cx[i]) * vx + R(L::cy[i]) * vy + R(L::cz[i]) * vz;
+      const R pv = R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv;
+      const R geq = w * (gm + ph_ * pv);
+      const R heq = w * (hm + ps_ * pv);
+      gsum += (double)geq;
+      hsum += (double)heq;
+      pg[i] = pg[i] - (pg[i] - geq) * itg;
+      ph[i] = ph[i] - (ph[i] - heq) * ith;
+    }
+  }
+  g0 = g0 - (g0 - (phi - gsum)) * P.inv_tau_phi;
+  h0 = h0 - (h0 - (psi - hsum)) * P.inv_tau_psi;
+}
+
+// row of a staged halo node: rows beyond the two-node ghost band of a wall
+// are never used (they only occur in a ragged last tile of a lattice thinner
+// than the tile), so they are clamped into the band to stay in bounds
+__device__ __forceinline__ int halo_row(int v, int n, int wall) {
+  if (wall) v = min(max(v, -2), n + 1);
+  return fd_row(v, n, wall);
+}
+
+__device__ __forceinline__ int tile3(const LBParams& P, int x, int y, int z) {
+  return ((z / P.tile) * P.nty + y / P.tile) * P.ntx + x / P.tile;
+}
+
+template <class St, typename R>
+__global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Moments3 M,
+                                                 const int* __restrict__ tflag,
+                                                 const int* __restrict__ tstate,
+                                                 const double* __restrict__ Ifield,
+                                                 long long* __restrict__ fib,
+                                                 double* __restrict__ force, int ntilex) {
+  using L = Lattice<19>;
+  __shared__ double s_m[3][3][T3H * T3H];  // moments ring: drho, phi, psi
+  __shared__ double s_u[3][3][T3U * T3U];  // chemical-potential ring
+  const int tid = threadIdx.x;
+  const int tx = blockIdx.x % ntilex, ty = blockIdx.x / ntilex;
+  const int x0 = tx * T3, y0t = ty * T3;
+  const int z0 = (int)blockIdx.y * P.seg;
+  const int z1 = min(z0 + P.seg, P.nz);
+  const int K = (z1 - z0) + 4;
+  const int dir = (blockIdx.y & 1) ? -1 : 1;
+  const int zbase = dir > 0 ? z0 - 2 : z1 + 1;
+  const int stamp = tstate[1];
+  // this thread's interior node
+  const int ix = tid % T3, iy = tid / T3;
+  const int gx = x0 + ix, gy = y0t + iy;
+  const bool own = gx < P.nx && gy < P.ny;
+  const int xw = wrap(gx, P.nx);
+
+  for (int k = 0; k < K; k++) {
+    const int zk = zbase + dir * k;
+    const int slot = k % 3;
+    // ---- L: stage the moments of plane zk on the 20 x 20 region
+    {
+      const int zr = halo_row(zk, P.nz, P.wall_z);
+      for (int q = tid; q < T3H * T3H; q += 256) {
+        const int hx = q % T3H, hy = q / T3H;
+        const int xx = wrap(x0 - 2 + hx, P.nx);
+        const int yy = halo_row(y0t - 2 + hy, P.ny, P.wall_y);
+        const long long nd = ((long long)zr * P.ny + yy) * P.nx + xx;
+        s_m[slot][0][q] = M.d[nd];
+        s_m[slot][1][q] = M.phi[nd];
+        s_m[slot][2][q] = M.psi[nd];
+      }
+    }
+    __syncthreads();
+    // ---- U: mu on plane z_{k-1} over the 18 x 18 region
+    if (k >= 2) {
+      const int a = (k + 1) % 3, b = (k + 2) % 3, c = slot;  // planes z_{k-2}, z_{k-1}, z_k
+      const int pa = dir > 0 ? a : c, pc = dir > 0 ? c : a;   // planes below / above in z
+      const int zq = halo_row(zk - dir, P.nz, P.wall_z);
+      for (int q = tid; q < T3U * T3U; q += 256) {
+        const int ux_ = q % T3U, uy_ = q / T3U;
+        const int hq = (uy_ + 1) * T3H + (ux_ + 1);  // centre in the 20 x 20 region
+        double lap[3], ctr[3];
+#pragma unroll
+        for (int f = 0; f < 3; f++) {
+          const double qc = s_m[b][f][hq];
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 1; i < 19; i++) {
+            const int pl = L::cz[i] > 0 ? pc : (L::cz[i] < 0 ? pa : b);
+            acc += L::w(i) * (s_m[pl][f][hq + L::cy[i] * T3H + L::cx[i]] - qc);
+          }
+          lap[f] = 6.0 * acc;
+          ctr[f] = qc;
+        }
+        const int xx = wrap(x0 - 1 + ux_, P.nx);
+        const int yy = halo_row(y0t - 1 + uy_, P.ny, P.wall_y);
+        double I = 0.0;
+        if (tflag[tile3(P, xx, yy, zq)] == stamp) I = Ifield[((long long)zq * P.ny + yy) * P.nx + xx];
+        double mr, mp, ms;
+        chem_pot(P, ctr[0], ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
+        s_u[slot][0][q] = mr;
+        s_u[slot][1][q] = mp;
+        s_u[slot][2][q] = ms;
+      }
+    }
+    __syncthreads();
+    // ---- C: collide plane z_{k-2}
+    if (k >= 4 && own) {
+      const int cz = zk - 2 * dir;
+      const int a = (k + 1) % 3, b = (k + 2) % 3, c = slot;  // mu planes z_{k-3}, z_{k-2}, z_{k-1}
+      const int pa = dir > 0 ? a : c, pc = dir > 0 ? c : a;
+      R pf[19], pg[19], ph[19];
+      double g0, h0, d, jx, jy, jz, phi, psi;
+      pull19(src, P, xw, gy, cz, pf, pg, ph, g0, h0);
+      moments19(pf, pg, ph, g0, h0, d, jx, jy, jz, phi, psi);
+      const int uq = (iy + 1) * T3U + (ix + 1);
+      double gr[3][3];
+#pragma unroll
+      for (int f = 0; f < 3; f++) {
+        double sx = 0, sy = 0, sz = 0;
+#pragma unroll
+        for (int i = 1; i < 19; i++) {
+          const int pl = L::cz[i] > 0 ? pc : (L::cz[i] < 0 ? pa : b);
+          const double v = L::w(i) * s_u[pl][f][uq + L::cy[i] * T3U + L::cx[i]];
+          sx += L::cx[i] * v;
+          sy += L::cy[i] * v;
+          sz += L::cz[i] * v;
+        }
+        gr[f][0] = 3.0 * sx;
+        gr[f][1] = 3.0 * sy;
+        gr[f][2] = 3.0 * sz;
+      }
+      const double rho = 1.0 + d;
+      double F[3];
+      for (int a3 = 0; a3 < 3; a3++) F[a3] = -(rho * gr[0][a3] + phi * gr[1][a3] + psi * gr[2][a3]);
+      const long long node = ((long long)cz * P.ny + gy) * P.nx + xw;
+      if (tflag[tile3(P, xw, gy, cz)] == stamp) {
+        long long* fp = fib + 3 * node;
+        for (int a3 = 0; a3 < 3; a3++) {
+          F[a3] += from_fix(fp[a3]);
+          fp[a3] = 0;
+          force[3 * node + a3] = F[a3];
+        }
+      }
+      collide19(P, pf, pg, ph, g0, h0, d, jx, jy, jz, phi, psi, s_u[b][1][uq], s_u[b][2][uq], F[0], F[1],
+                F[2]);
+      if constexpr (St::kQuantized) {
+        R ef = 0, eg = 0, eh = 0;
+#pragma unroll
+        for (int i = 1; i < 19; i++) {
+          const R qf = dst.quantize(pf[i]), qg = dst.quantize(pg[i]), qh = dst.quantize(ph[i]);
+          ef += pf[i] - qf;
+          eg += pg[i] - qg;
+          eh += ph[i] - qh;
+          pf[i] = qf;
+          pg[i] = qg;
+          ph[i] = qh;
+        }
+        pf[0] += ef;
+        g0 += (double)eg;
+        h0 += (double)eh;
+      }
+      dst.template store<R>(0, 0, node, pf[0]);
+      dst.store_rest(1, node, g0);
+      dst.store_rest(2, node, h0);
+#pragma unroll
+      for (int i = 1; i < 19; i++) {
+        dst.template store<R>(0, i, node, pf[i]);
+        dst.template store<R>(1, i, node, pg[i]);
+        dst.template store<R>(2, i, node, ph[i]);
+      }
+    }
+    __syncthreads();  // the rings are rewritten by the next plane
+  }
+}
+
+}  // namespace lb

@@ -10,6 +10,9 @@
 //   k_spread      marker forces onto the lattice (fixed-point atomics)
 //   k_lb          fused pull-stream / moments / mu / force / collide
 //   k_interp      v at t+1 interpolated at X(t), Euler update X(t+1)
+// D3Q19 runs the same sequence with triangle meshes (face and vertex normals
+// before the coupling, per-edge membrane forces) and a two-kernel lattice
+// update (moment field, then the z-marching collide kernel).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +24,9 @@
 #include "../../include/lbib.h"
 #include "common.h"
 #include "k_ibm.h"
+#include "k_ibm3d.h"
 #include "k_lb.h"
+#include "k_lb3d.h"
 #include "k_misc.h"
 #include "store.h"
 
@@ -53,6 +58,9 @@ struct Layout {
   size_t pop_bytes;     // bytes of one buffer
   size_t Ifield, fib, force, tflag, tlist, tstate, stage, part;
   size_t X, U, F, Facc, rest, moff, mid, ks, kb, mbox, status, memE;
+  // 3D: moment field and triangle meshes
+  size_t mom, tri, toff, edge, erest, eoff, emem, tadj, vtoff, vt, fn, vn;
+  int maxT, maxE;
   size_t total;
   long long ntiles;
   int ntx, nty, ntz, tile;
@@ -77,8 +85,14 @@ int validate(const lbib_params* p) {
   if (!(p->alpha > 0.0) || !(p->kappa_c >= 0.0)) return LBIB_EINVAL;
   if (p->storage < 0 || p->storage > 3) return LBIB_EINVAL;
   if (p->max_markers < 0 || p->max_elems < 0 || p->max_membranes < 0) return LBIB_EINVAL;
-  if ((long long)p->nx * p->ny * p->nz > (1LL << 40)) return LBIB_EINVAL;
-  if (p->lattice == LBIB_D3Q19) return LBIB_EINVAL;  // D3Q19 engine not built in this library
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  if (N > (1LL << 40)) return LBIB_EINVAL;
+  if (p->lattice == LBIB_D3Q19 && p->nz > 65535) return LBIB_EINVAL;
+  // the FP32 format addresses its planes through 32-bit buffer offsets
+  const int Q = p->lattice == LBIB_D2Q9 ? 9 : 19;
+  if (p->storage == LBIB_FP32 && ((3LL * Q - 2) * N * 4 > 0xffffffffLL || 2 * N * 8 > 0xffffffffLL))
+    return LBIB_EINVAL;
+  if (p->max_elems > (1 << 28) || p->max_markers > (1 << 28)) return LBIB_EINVAL;
   return LBIB_OK;
 }
 
@@ -105,7 +119,9 @@ Layout make_layout(const lbib_params* p) {
   L.tlist = c.take((size_t)L.ntiles * 4);
   L.tstate = c.take(64);
   L.stage = c.take((size_t)N * 8 * 8);
-  L.part = c.take((size_t)((N + 255) / 256 + 1) * 8 * 8 + (size_t)M * 2 * 8);
+  L.maxT = D == 3 ? std::max(p->max_elems, 1) : 0;
+  L.maxE = 2 * L.maxT;  // a closed mesh has 3T/2 edges
+  L.part = c.take((size_t)((N + 255) / 256 + 1) * 8 * 8 + (size_t)std::max(M, L.maxE) * 2 * 8);
   L.X = c.take((size_t)M * 3 * 8);
   L.U = c.take((size_t)M * 3 * 8);
   L.F = c.take((size_t)M * 3 * 8);
@@ -118,6 +134,19 @@ Layout make_layout(const lbib_params* p) {
   L.mbox = c.take((size_t)K * 8 * 8);
   L.status = c.take(64);
   L.memE = c.take(64);
+  const bool d3 = D == 3;
+  L.mom = c.take(d3 ? (size_t)N * 3 * 8 : 0);
+  L.tri = c.take((size_t)L.maxT * 3 * 4);
+  L.toff = c.take(d3 ? (size_t)(K + 1) * 4 : 0);
+  L.edge = c.take((size_t)L.maxE * 4 * 4);
+  L.erest = c.take((size_t)L.maxE * 8);
+  L.eoff = c.take(d3 ? (size_t)(K + 1) * 4 : 0);
+  L.emem = c.take((size_t)L.maxE * 4);
+  L.tadj = c.take((size_t)L.maxT * 3 * 4);
+  L.vtoff = c.take(d3 ? (size_t)(M + 1) * 4 : 0);
+  L.vt = c.take((size_t)L.maxT * 3 * 4);
+  L.fn = c.take((size_t)L.maxT * 3 * 8);
+  L.vn = c.take(d3 ? (size_t)M * 3 * 8 : 0);
   L.total = c.off;
   return L;
 }
@@ -137,6 +166,8 @@ struct lbib_sim {
   long long steps = 0;
   int K = 0, M = 0;
   std::vector<int> moff{0};
+  int ntri = 0, nedge = 0;                 // triangles and edges of all meshes (3D)
+  std::vector<int> toff{0}, eoff{0}, vtoff{0};
   double r_cut = 0;
   int bx = 256, seg = 0;  // fused-kernel launch shape (seg 0: automatic)
   int nxcd = 1;           // L2 domains workgroups are dealt to (1: plain strip order)
@@ -192,6 +223,8 @@ struct lbib_sim {
   virtual int energy_nodes(double* part, long long* nblk) = 0;
   virtual int coupling(int want_force) = 0;
   virtual int check(int* bad_dev) = 0;
+  // per-element membrane energies (strain, bending) into out[2 * rows]
+  virtual int mem_energy(double* out, long long* rows) = 0;
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   MemDev memdev() const {
@@ -210,6 +243,22 @@ struct lbib_sim {
     m.K = K;
     m.M = M;
     return m;
+  }
+  MeshDev meshdev() const {
+    MeshDev h;
+    h.tri = at<int>(L.tri);
+    h.toff = at<int>(L.toff);
+    h.edge = at<int>(L.edge);
+    h.erest = at<double>(L.erest);
+    h.eoff = at<int>(L.eoff);
+    h.tadj = at<int>(L.tadj);
+    h.vtoff = at<int>(L.vtoff);
+    h.vt = at<int>(L.vt);
+    h.fn = at<double>(L.fn);
+    h.vn = at<double>(L.vn);
+    h.T = ntri;
+    h.E = nedge;
+    return h;
   }
   TileMap tilemap() const {
     TileMap t;
@@ -253,33 +302,57 @@ Split16Store<__hip_bfloat16, 9> make_store<Split16Store<__hip_bfloat16, 9>>(char
                                          reinterpret_cast<float*>(base + mov), N};
 }
 
+template <>
+MixStore<19> make_store<MixStore<19>>(char* base, long long N) {
+  size_t fl = align_up((size_t)(MixStore<19>::float_planes() * N * 4));
+  return MixStore<19>{reinterpret_cast<float*>(base), reinterpret_cast<double*>(base + fl), N};
+}
+template <>
+PlainStore<double, 19> make_store<PlainStore<double, 19>>(char* base, long long N) {
+  return PlainStore<double, 19>{reinterpret_cast<double*>(base), N};
+}
+template <>
+Split16Store<__half, 19> make_store<Split16Store<__half, 19>>(char* base, long long N) {
+  size_t mov = align_up((size_t)(3LL * 18 * N * 2));
+  return Split16Store<__half, 19>{reinterpret_cast<__half*>(base), reinterpret_cast<float*>(base + mov), N};
+}
+template <>
+Split16Store<__hip_bfloat16, 19> make_store<Split16Store<__hip_bfloat16, 19>>(char* base, long long N) {
+  size_t mov = align_up((size_t)(3LL * 18 * N * 2));
+  return Split16Store<__hip_bfloat16, 19>{reinterpret_cast<__hip_bfloat16*>(base),
+                                          reinterpret_cast<float*>(base + mov), N};
+}
+
+// lattice parameters shared by both engines
+void fill_params(LBParams& P, const lbib_params& p, const Layout& L, long long N, int seg) {
+  P.inv_tau = (1.0 / p.tau);
+  P.inv_tau_phi = (1.0 / p.tau_phi);
+  P.inv_tau_psi = (1.0 / p.tau_psi);
+  P.gphi = p.gamma_phi;
+  P.gpsi = p.gamma_psi;
+  P.k1 = p.kappa[0];
+  P.k2 = p.kappa[1];
+  P.k3 = p.kappa[2];
+  P.a2 = p.alpha * p.alpha;
+  P.kc = p.kappa_c;
+  P.nx = p.nx;
+  P.ny = p.ny;
+  P.nz = p.lattice == LBIB_D3Q19 ? p.nz : 1;
+  P.wall_y = p.wall_y;
+  P.wall_z = p.lattice == LBIB_D3Q19 ? p.wall_z : 0;
+  P.N = N;
+  P.ntx = L.ntx;
+  P.nty = L.nty;
+  P.tile = L.tile;
+  P.seg = seg;
+}
+
 template <class St, typename R>
 struct Engine2D final : lbib_sim {
   LBParams P{};
   St store(int which) const { return make_store<St>(ws + L.pops[which], N); }
 
-  void setup() override {
-    P.inv_tau = (1.0 / p.tau);
-    P.inv_tau_phi = (1.0 / p.tau_phi);
-    P.inv_tau_psi = (1.0 / p.tau_psi);
-    P.gphi = p.gamma_phi;
-    P.gpsi = p.gamma_psi;
-    P.k1 = p.kappa[0];
-    P.k2 = p.kappa[1];
-    P.k3 = p.kappa[2];
-    P.a2 = p.alpha * p.alpha;
-    P.kc = p.kappa_c;
-    P.nx = p.nx;
-    P.ny = p.ny;
-    P.nz = 1;
-    P.wall_y = p.wall_y;
-    P.wall_z = 0;
-    P.N = N;
-    P.ntx = L.ntx;
-    P.nty = L.nty;
-    P.tile = L.tile;
-    P.seg = seg;
-  }
+  void setup() override { fill_params(P, p, L, N, seg); }
 
   CoupArgs coup_args(int want_force) const {
     CoupArgs c;
@@ -429,6 +502,172 @@ struct Engine2D final : lbib_sim {
     hipLaunchKernelGGL((k_check<St, R, 256>), dim3(nb), dim3(256), 0, stream, store(cur), N, 9, bad);
     return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
   }
+
+  int mem_energy(double* out, long long* rows) override {
+    hipLaunchKernelGGL(k_memenergy2d, dim3((M + 255) / 256), dim3(256), 0, stream, memdev(), out);
+    *rows = M;
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+};
+
+// D3Q19 with closed triangle meshes
+template <class St, typename R>
+struct Engine3D final : lbib_sim {
+  LBParams P{};
+  St store(int which) const { return make_store<St>(ws + L.pops[which], N); }
+  int ntilex() const { return (p.nx + T3 - 1) / T3; }
+  int ntiley() const { return (p.ny + T3 - 1) / T3; }
+
+  void setup() override { fill_params(P, p, L, N, seg); }
+
+  Moments3 mom3() const {
+    Moments3 m;
+    m.d = at<double>(L.mom);
+    m.phi = m.d + N;
+    m.psi = m.d + 2 * N;
+    return m;
+  }
+
+  Coup3Args coup_args(int want_force) const {
+    Coup3Args c;
+    c.nx = p.nx;
+    c.ny = p.ny;
+    c.nz = p.nz;
+    c.wall_y = p.wall_y;
+    c.wall_z = p.wall_z;
+    c.alpha = p.alpha;
+    c.kappa_c = p.kappa_c;
+    c.r_cut = r_cut;
+    c.want_force = want_force;
+    return c;
+  }
+
+  // mesh geometry at X(t): boxes and the active-tile map, face normals,
+  // orientation, vertex normals; then the profile and coupling forces
+  int coupling(int want_force) override {
+    if (K == 0) return LBIB_OK;
+    MemDev md = memdev();
+    MeshDev mh = meshdev();
+    TileMap tm = tilemap();
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
+    hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, p.nz, p.wall_y,
+                       p.wall_z, 3, r_cut + 3.0);
+    hipLaunchKernelGGL(k_facenormals, dim3((ntri + 255) / 256), dim3(256), 0, stream, md, mh);
+    hipLaunchKernelGGL(k_meshvolume<256>, dim3(K), dim3(256), 0, stream, md, mh);
+    hipLaunchKernelGGL(k_vertexnormals, dim3((M + 255) / 256), dim3(256), 0, stream, md, mh);
+    const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 4096);
+    hipLaunchKernelGGL((k_coupling3d<St, R, COUP3_THREADS>), dim3(grid), dim3(COUP3_THREADS), 0, stream,
+                       md, mh, tm, coup_args(want_force), at<double>(L.Ifield), store(cur));
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  // planes per workgroup: with seg = 0, one resident round of workgroups
+  int pick_seg() const {
+    if (seg > 0) return std::min(seg, p.nz);
+    const long long tiles = (long long)ntilex() * ntiley();
+    int per_cu = 0, ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_lb3d<St, R>, 256, 0) !=
+            hipSuccess ||
+        per_cu <= 0 || ncu <= 0)
+      return std::min(p.nz, 16);
+    const long long slots = (long long)per_cu * ncu;
+    const long long planes = (p.nz * tiles + slots - 1) / slots;
+    return (int)std::max<long long>(std::min<long long>(4, p.nz), std::min<long long>(p.nz, planes));
+  }
+
+  void launch_lb(St src, St dst) {
+    P.seg = pick_seg();
+    P.nseg = (p.nz + P.seg - 1) / P.seg;
+    Moments3 m3 = mom3();
+    const int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL((k_mom3d<St, R>), dim3(nb), dim3(256), 0, stream, src, P, m3);
+    dim3 grid(ntilex() * ntiley(), P.nseg);
+    hipLaunchKernelGGL((k_lb3d<St, R>), grid, dim3(256), 0, stream, src, dst, P, m3,
+                       (const int*)at<int>(L.tflag), (const int*)at<int>(L.tstate),
+                       (const double*)at<double>(L.Ifield), at<long long>(L.fib), at<double>(L.force),
+                       ntilex());
+  }
+
+  int step() override {
+    MemDev md = memdev();
+    MeshDev mh = meshdev();
+    const int mb = (M + 255) / 256;
+    const int mb64 = (int)((64LL * M + 255) / 256);  // one wave per marker
+    if (K > 0) {
+      hipEvent_t t0 = tbeg(1);
+      int rc = coupling(1);
+      if (rc) return rc;
+      tend(1, t0);
+      t0 = tbeg(2);
+      hipLaunchKernelGGL(k_memedge3d, dim3((nedge + 255) / 256), dim3(256), 0, stream, md, mh,
+                         (const int*)at<int>(L.emem));
+      hipLaunchKernelGGL(k_memforce3d, dim3(mb), dim3(256), 0, stream, md);
+      hipLaunchKernelGGL(k_spread3d, dim3(mb64), dim3(256), 0, stream, md, at<long long>(L.fib), p.nx,
+                         p.ny, p.nz, p.wall_y, p.wall_z);
+      tend(2, t0);
+    }
+    hipEvent_t t1 = tbeg(0);
+    launch_lb(store(cur), store(1 - cur));
+    tend(0, t1);
+    if (K > 0) {
+      hipEvent_t t2 = tbeg(3);
+      hipLaunchKernelGGL((k_interp3d<St, R>), dim3(mb64), dim3(256), 0, stream, md, store(1 - cur), P,
+                         (const double*)at<double>(L.force));
+      tend(3, t2);
+    }
+    cur = 1 - cur;
+    if (timing) {
+      timed_steps++;
+      if (ev_used > 4096) {
+        int rc = timing_flush();
+        if (rc) return rc;
+      }
+    }
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int init(const double* st) override {
+    int rc = coupling(0);
+    if (rc) return rc;
+    const int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL((k_init3d<St, R>), dim3(nb), dim3(256), 0, stream, store(cur), P, st,
+                       (const int*)at<int>(L.tflag), (const int*)at<int>(L.tstate),
+                       (const double*)at<double>(L.Ifield));
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int moments(double* out) override {
+    const int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL((k_moments3d<St, R>), dim3(nb), dim3(256), 0, stream, store(cur), P, out);
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int energy_nodes(double* part, long long* nblk) override {
+    const long long nb = (N + 255) / 256;
+    hipLaunchKernelGGL((k_energy_nodes3d<256>), dim3((unsigned)nb), dim3(256), 0, stream, P,
+                       (const double*)at<double>(L.stage), (const int*)at<int>(L.tflag),
+                       (const int*)at<int>(L.tstate), (const double*)at<double>(L.Ifield), part);
+    *nblk = nb;
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int check(int* bad) override {
+    const int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL((k_check<St, R, 256>), dim3(nb), dim3(256), 0, stream, store(cur), N, 19, bad);
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  int mem_energy(double* out, long long* rows) override {
+    MemDev md = memdev();
+    MeshDev mh = meshdev();
+    hipLaunchKernelGGL(k_facenormals, dim3((ntri + 255) / 256), dim3(256), 0, stream, md, mh);
+    hipLaunchKernelGGL(k_memenergy3d, dim3((nedge + 255) / 256), dim3(256), 0, stream, md, mh,
+                       (const int*)at<int>(L.emem), out);
+    *rows = nedge;
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
 };
 
 lbib_sim* make_engine(const lbib_params* p) {
@@ -439,6 +678,13 @@ lbib_sim* make_engine(const lbib_params* p) {
       case LBIB_FP16: return new (std::nothrow) Engine2D<Split16Store<__half, 9>, float>();
       case LBIB_BF16: return new (std::nothrow) Engine2D<Split16Store<__hip_bfloat16, 9>, float>();
     }
+  } else {
+    switch (p->storage) {
+      case LBIB_FP32: return new (std::nothrow) Engine3D<MixStore<19>, float>();
+      case LBIB_FP64: return new (std::nothrow) Engine3D<PlainStore<double, 19>, double>();
+      case LBIB_FP16: return new (std::nothrow) Engine3D<Split16Store<__half, 19>, float>();
+      case LBIB_BF16: return new (std::nothrow) Engine3D<Split16Store<__hip_bfloat16, 19>, float>();
+    }
   }
   return nullptr;
 }
@@ -446,6 +692,62 @@ lbib_sim* make_engine(const lbib_params* p) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+namespace {
+
+// closed-mesh topology on the host: edges with their two triangles, the
+// triangle across each edge, and the vertex -> triangle lists.  Returns
+// LBIB_EINVAL for an index out of range, a degenerate triangle, or an edge
+// that does not have exactly two triangles (open or non-manifold mesh).
+struct MeshTopo {
+  std::vector<int> edge;   // 4 per edge: a < b, t1, t2 (local ids)
+  std::vector<int> tadj;   // 3 per triangle
+  std::vector<int> vtoff;  // n + 1
+  std::vector<int> vt;
+};
+
+int mesh_topology(int n, int nt, const int* tri, MeshTopo& mt) {
+  std::vector<std::pair<long long, int>> keys;  // (edge key, 3 t + k)
+  keys.reserve((size_t)3 * nt);
+  for (int t = 0; t < nt; t++) {
+    const int* v = tri + 3 * t;
+    for (int k = 0; k < 3; k++) {
+      if (v[k] < 0 || v[k] >= n) return LBIB_EINVAL;
+    }
+    if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2]) return LBIB_EINVAL;
+    for (int k = 0; k < 3; k++) {
+      const int a = v[k], b = v[(k + 1) % 3];
+      keys.push_back({(long long)std::min(a, b) * n + std::max(a, b), 3 * t + k});
+    }
+  }
+  std::sort(keys.begin(), keys.end());
+  mt.tadj.assign((size_t)3 * nt, -1);
+  mt.edge.clear();
+  for (size_t i = 0; i < keys.size();) {
+    size_t j = i;
+    while (j < keys.size() && keys[j].first == keys[i].first) j++;
+    if (j - i != 2) return LBIB_EINVAL;
+    const int s0 = keys[i].second, s1 = keys[i + 1].second;
+    const int t1 = s0 / 3, t2 = s1 / 3;
+    mt.tadj[s0] = t2;
+    mt.tadj[s1] = t1;
+    mt.edge.push_back((int)(keys[i].first / n));
+    mt.edge.push_back((int)(keys[i].first % n));
+    mt.edge.push_back(t1);
+    mt.edge.push_back(t2);
+    i = j;
+  }
+  mt.vtoff.assign((size_t)n + 1, 0);
+  for (int q = 0; q < 3 * nt; q++) mt.vtoff[tri[q] + 1]++;
+  for (int v = 0; v < n; v++) mt.vtoff[v + 1] += mt.vtoff[v];
+  mt.vt.assign((size_t)3 * nt, 0);
+  std::vector<int> fill(mt.vtoff.begin(), mt.vtoff.end() - 1);
+  for (int t = 0; t < nt; t++)
+    for (int k = 0; k < 3; k++) mt.vt[fill[tri[3 * t + k]]++] = t;
+  return LBIB_OK;
+}
+
+}  // namespace
+
 // C ABI
 extern "C" {
 
@@ -497,21 +799,58 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
   if (!s || !X || n < 3) return LBIB_EINVAL;
   if (s->ready) return LBIB_ESTATE;
   if (s->D == 2 && (n_elems != 0 || conn)) return LBIB_EINVAL;
+  if (s->D == 3 && (n_elems < 4 || !conn)) return LBIB_EINVAL;
   if (!(ks >= 0) || !(kb >= 0)) return LBIB_EINVAL;
   if (s->K + 1 > s->p.max_membranes || s->M + n > s->p.max_markers) return LBIB_ENOMEM;
+  if (s->D == 3 && s->ntri + n_elems > s->p.max_elems) return LBIB_ENOMEM;
   for (int i = 0; i < n * s->D; i++)
     if (!std::isfinite(X[i])) return LBIB_EINVAL;
-  std::vector<double> X3((size_t)3 * n, 0.0), rest(n);
+  std::vector<double> X3((size_t)3 * n, 0.0), rest(n, 1.0);
   for (int l = 0; l < n; l++)
     for (int a = 0; a < s->D; a++) X3[3 * l + a] = X[(size_t)l * s->D + a];
-  for (int l = 0; l < n; l++) {
-    const int m = (l + 1) % n;
-    rest[l] = std::hypot(X3[3 * m] - X3[3 * l], X3[3 * m + 1] - X3[3 * l + 1]);
-    if (!(rest[l] > 0)) return LBIB_EINVAL;
+  if (s->D == 2) {
+    for (int l = 0; l < n; l++) {
+      const int m = (l + 1) % n;
+      rest[l] = std::hypot(X3[3 * m] - X3[3 * l], X3[3 * m + 1] - X3[3 * l + 1]);
+      if (!(rest[l] > 0)) return LBIB_EINVAL;
+    }
   }
-  std::vector<int> mid(n, s->K);
   const int off = s->M;
   hipStream_t st = s->stream;
+  MeshTopo mt;
+  std::vector<int> tri_g, edge_g, tadj_g, vtoff_g, vt_g, emem;
+  std::vector<double> erest;
+  if (s->D == 3) {
+    int rc = mesh_topology(n, n_elems, conn, mt);
+    if (rc) return rc;
+    const int ne = (int)mt.edge.size() / 4;
+    if (s->nedge + ne > s->L.maxE) return LBIB_ENOMEM;
+    // global ids: markers offset by M, triangles by T
+    tri_g.resize((size_t)3 * n_elems);
+    for (int q = 0; q < 3 * n_elems; q++) tri_g[q] = conn[q] + off;
+    tadj_g.resize(mt.tadj.size());
+    for (size_t q = 0; q < mt.tadj.size(); q++) tadj_g[q] = mt.tadj[q] + s->ntri;
+    edge_g.resize(mt.edge.size());
+    erest.resize(ne);
+    for (int e = 0; e < ne; e++) {
+      const int a = mt.edge[4 * e], b = mt.edge[4 * e + 1];
+      edge_g[4 * e] = a + off;
+      edge_g[4 * e + 1] = b + off;
+      edge_g[4 * e + 2] = mt.edge[4 * e + 2] + s->ntri;
+      edge_g[4 * e + 3] = mt.edge[4 * e + 3] + s->ntri;
+      erest[e] = std::sqrt((X3[3 * b] - X3[3 * a]) * (X3[3 * b] - X3[3 * a]) +
+                           (X3[3 * b + 1] - X3[3 * a + 1]) * (X3[3 * b + 1] - X3[3 * a + 1]) +
+                           (X3[3 * b + 2] - X3[3 * a + 2]) * (X3[3 * b + 2] - X3[3 * a + 2]));
+      if (!(erest[e] > 0)) return LBIB_EINVAL;
+    }
+    emem.assign(ne, s->K);
+    const int vbase = s->vtoff.back();
+    vtoff_g.resize(n);
+    for (int v = 0; v < n; v++) vtoff_g[v] = mt.vtoff[v + 1] + vbase;  // entries off + 1 .. off + n
+    vt_g.resize(mt.vt.size());
+    for (size_t q = 0; q < mt.vt.size(); q++) vt_g[q] = mt.vt[q] + s->ntri;
+  }
+  std::vector<int> mid(n, s->K);
   HIPCHK(hipMemcpyAsync(s->ws + s->L.X + (size_t)off * 24, X3.data(), (size_t)n * 24, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(s->ws + s->L.U + (size_t)off * 24, 0, (size_t)n * 24, st));
   HIPCHK(hipMemsetAsync(s->ws + s->L.F + (size_t)off * 24, 0, (size_t)n * 24, st));
@@ -521,7 +860,26 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
   HIPCHK(hipMemcpyAsync(s->ws + s->L.kb + (size_t)s->K * 8, &kb, 8, hipMemcpyHostToDevice, st));
   s->moff.push_back(off + n);
   HIPCHK(hipMemcpyAsync(s->ws + s->L.moff, s->moff.data(), s->moff.size() * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));  // host vectors go out of scope
+  if (s->D == 3) {
+    const int ne = (int)erest.size();
+    char* w = s->ws;
+    HIPCHK(hipMemcpyAsync(w + s->L.tri + (size_t)s->ntri * 12, tri_g.data(), tri_g.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.tadj + (size_t)s->ntri * 12, tadj_g.data(), tadj_g.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.edge + (size_t)s->nedge * 16, edge_g.data(), edge_g.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.erest + (size_t)s->nedge * 8, erest.data(), erest.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.emem + (size_t)s->nedge * 4, emem.data(), emem.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.vt + (size_t)s->vtoff.back() * 4, vt_g.data(), vt_g.size() * 4, hipMemcpyHostToDevice, st));
+    s->toff.push_back(s->ntri + n_elems);
+    s->eoff.push_back(s->nedge + ne);
+    for (int v = 0; v < n; v++) s->vtoff.push_back(vtoff_g[v]);
+    HIPCHK(hipMemcpyAsync(w + s->L.toff, s->toff.data(), s->toff.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.eoff, s->eoff.data(), s->eoff.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.vtoff, s->vtoff.data(), s->vtoff.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));  // host vectors go out of scope
+    s->ntri += n_elems;
+    s->nedge += ne;
+  }
+  HIPCHK(hipStreamSynchronize(st));
   if (id) *id = s->K;
   s->K += 1;
   s->M += n;
@@ -531,7 +889,6 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
 int lbib_set_fields(lbib_sim* s, const double* rho, const double* phi, const double* psi,
                     const double* ux, const double* uy, const double* uz) {
   if (!s || !rho || !phi || !psi) return LBIB_EINVAL;
-  (void)uz;
   const long long N = s->N;
   for (long long n = 0; n < N; n++)
     if (!(rho[n] > 0) || !std::isfinite(phi[n]) || !std::isfinite(psi[n])) return LBIB_EINVAL;
@@ -548,6 +905,12 @@ int lbib_set_fields(lbib_sim* s, const double* rho, const double* phi, const dou
     HIPCHK(hipMemcpyAsync(stage + 4 * N, uy, N * 8, hipMemcpyHostToDevice, st));
   else
     HIPCHK(hipMemsetAsync(stage + 4 * N, 0, N * 8, st));
+  if (s->D == 3) {
+    if (uz)
+      HIPCHK(hipMemcpyAsync(stage + 5 * N, uz, N * 8, hipMemcpyHostToDevice, st));
+    else
+      HIPCHK(hipMemsetAsync(stage + 5 * N, 0, N * 8, st));
+  }
   s->cur = 0;
   int rc = s->init(stage);
   if (rc) return rc;
@@ -577,7 +940,7 @@ int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
   if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 256) return LBIB_EINVAL;
   if (seg < -1 || nxcd < 0 || nxcd > 64) return LBIB_EINVAL;
   if (block_x) s->bx = block_x;
-  if (seg > 0) s->seg = std::max(1, std::min(seg, s->p.ny));
+  if (seg > 0) s->seg = std::max(1, std::min(seg, s->D == 3 ? s->p.nz : s->p.ny));
   if (seg < 0) s->seg = 0;  // back to automatic
   if (nxcd) s->nxcd = nxcd;
   return LBIB_OK;
@@ -615,13 +978,12 @@ int lbib_get_fields(lbib_sim* s, double* rho, double* c1, double* c2, double* c3
                     double* uy, double* uz) {
   if (!s) return LBIB_EINVAL;
   if (!s->ready) return LBIB_ESTATE;
-  (void)uz;
   double* stage = s->at<double>(s->L.stage);
   int rc = s->moments(stage);
   if (rc) return rc;
   const long long N = s->N;
-  double* outs[6] = {rho, c1, c2, c3, ux, uy};
-  for (int k = 0; k < 6; k++)
+  double* outs[7] = {rho, c1, c2, c3, ux, uy, s->D == 3 ? uz : nullptr};
+  for (int k = 0; k < 7; k++)
     if (outs[k]) HIPCHK(hipMemcpyAsync(outs[k], stage + k * N, N * 8, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   return LBIB_OK;
@@ -669,10 +1031,11 @@ int lbib_energy(lbib_sim* s, lbib_energies* out) {
   out->E_s = out->E_b = 0.0;
   if (s->K > 0) {
     double* me = part + ((s->N + 255) / 256 + 1) * 8;
-    MemDev md = s->memdev();
-    hipLaunchKernelGGL(k_memenergy2d, dim3((s->M + 255) / 256), dim3(256), 0, s->stream, md, me);
-    hipLaunchKernelGGL(k_sum_rows<256>, dim3(1), dim3(256), 0, s->stream, (const double*)me,
-                       (long long)s->M, 2, sums);
+    long long rows = 0;
+    rc = s->mem_energy(me, &rows);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sum_rows<256>, dim3(1), dim3(256), 0, s->stream, (const double*)me, rows, 2,
+                       sums);
     double h2[2];
     HIPCHK(hipMemcpyAsync(h2, sums, 16, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));

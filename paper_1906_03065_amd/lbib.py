@@ -99,12 +99,14 @@ def _d(a):
     return None if a is None else a.ctypes.data_as(_dp)
 
 
-def make_params(p: dict, storage="fp32", max_markers=None, max_membranes=None, max_elems=0,
+def make_params(p: dict, storage="fp32", max_markers=None, max_membranes=None, max_elems=None,
                 membranes=()) -> Params:
     if isinstance(storage, str):
         storage = STORAGE[storage]
     if max_markers is None:
         max_markers = sum(len(m["X"]) for m in membranes)
+    if max_elems is None:
+        max_elems = sum(len(m["tris"]) for m in membranes if m.get("tris") is not None)
     if max_membranes is None:
         max_membranes = len(membranes)
     k = p["kappa"]
@@ -128,12 +130,12 @@ class Sim:
     workloads.base_params); ``membranes`` sizes the marker capacity."""
 
     def __init__(self, p: dict, storage="fp32", membranes=(), device="cuda:0", stream=None,
-                 max_markers=None, max_membranes=None):
+                 max_markers=None, max_membranes=None, max_elems=None):
         import torch
 
         self.torch = torch
         self.p = dict(p)
-        self.prm = make_params(p, storage, max_markers, max_membranes, membranes=membranes)
+        self.prm = make_params(p, storage, max_markers, max_membranes, max_elems, membranes=membranes)
         self.D = 3 if self.prm.lattice == D3Q19 else 2
         self.shape = ((self.prm.nz, self.prm.ny, self.prm.nx) if self.D == 3
                       else (self.prm.ny, self.prm.nx))

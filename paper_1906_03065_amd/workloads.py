@@ -242,14 +242,14 @@ def icosphere(subdiv: int):
 
 def capsule3d(n=64, R=10.0, subdiv=3, kappa=(0.02, 0.02, 0.02), alpha=1.0, kappa_c=0.01,
               kappa_s=0.01, kappa_b=1e-3, mobility=0.1, two=True, bridge=True, perturb=1e-4,
-              seed=SEED_BASE + 2, wall_z=1):
+              seed=SEED_BASE + 2, wall_z=1, r_cut=0.0, tau=1.0):
     """D3Q19 box n^3 (periodic x, y; walls in z when wall_z): C2 below
     z0 = (n-1)/2, C1 above; two icosphere capsules of fluid 3 (radius R) side
     by side on the interface with a C2 bridge between them.  READING of the
     bridge: component 3 is reserved for capsule interiors by the coupling
     energy, so the bridge is component 2."""
     p = base_params(n, n, n, lattice=1, wall_y=0, wall_z=wall_z, kappa=kappa, alpha=alpha,
-                    kappa_c=kappa_c, mobility=mobility)
+                    kappa_c=kappa_c, mobility=mobility, r_cut=r_cut, tau=tau)
     z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64),) * 3, indexing="ij")
     z0 = (n - 1) / 2.0
     yc = (n - 1) / 2.0 + 0.25
@@ -277,6 +277,37 @@ def capsule3d(n=64, R=10.0, subdiv=3, kappa=(0.02, 0.02, 0.02), alpha=1.0, kappa
     C1 = 1.0 - C2 - C3
     return dict(params=p, fields=fields_from_C(C1, C2, C3, perturb, seed), membranes=mems,
                 name=f"capsule3d_{n}")
+
+
+def drop3d(nx=24, ny=22, nz=20, R=6.0, wall_y=0, wall_z=1, kappa=(0.02, 0.03, 0.025), alpha=1.0,
+           mobility=0.1, tau=1.0, tau_phi=1.0, tau_psi=1.0, u0=None, perturb=1e-4,
+           seed=SEED_BASE + 4):
+    """D3Q19 box: a C3 sphere of radius R in C1, above a C2 layer of a third
+    of the height (no membrane)."""
+    p = base_params(nx, ny, nz, lattice=1, wall_y=wall_y, wall_z=wall_z, kappa=kappa, alpha=alpha,
+                    kappa_c=0.0, mobility=mobility, tau=tau, tau_phi=tau_phi, tau_psi=tau_psi)
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    c = (nx / 2.0 + 0.2, ny / 2.0 - 0.3, 0.6 * nz)
+    C3 = tanh_profile(R - np.sqrt(_min_image(x - c[0], nx) ** 2 + _min_image(y - c[1], ny) ** 2 +
+                                  (z - c[2]) ** 2), alpha)
+    C2 = (1.0 - C3) * 0.5 * (1.0 - np.tanh((z - nz / 3.0) / (2.0 * alpha)))
+    C1 = 1.0 - C2 - C3
+    return dict(params=p, fields=fields_from_C(C1, C2, C3, perturb, seed, u=u0), membranes=[],
+                name=f"drop3d_{nx}x{ny}x{nz}")
+
+
+def lens3d(n=64, R=16.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_z=1):
+    """D3Q19 n^3: a C3 sphere centred on a flat C1/C2 interface at
+    z0 = (n-1)/2 (C1 below, C2 above), periodic in x and y."""
+    p = base_params(n, n, n, lattice=1, wall_y=0, wall_z=wall_z, kappa=kappa, alpha=alpha,
+                    kappa_c=0.0, mobility=mobility)
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64),) * 3, indexing="ij")
+    c = (n - 1) / 2.0
+    C3 = tanh_profile(R - np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2), alpha)
+    C1 = (1.0 - C3) * 0.5 * (1.0 - np.tanh((z - c) / (2.0 * alpha)))
+    C2 = 1.0 - C1 - C3
+    return dict(params=p, fields=fields_from_C(C1, C2, C3), membranes=[], name=f"lens3d_{n}")
 
 
 def c3(n=256, **kw):
