@@ -7,10 +7,14 @@ method: coupling profile and forces, membrane forces, spreading, the fused
 lattice kernel, interpolation and marker update.  Inputs are resident in HBM
 before the timed region.
 
-Prints one JSON line: whole-step MLUPS, the fused lattice kernel's HBM
-roofline fraction (algorithmic bytes / kernel time from HIP events on the
-library's stream over the timed region) and the CPU oracle's rate on a
-bounded sample of the same workload.
+With --workload c3: 256^3 D3Q19 in FP32 (or 16-bit storage), walls in z,
+two icosphere capsules of radius 40 (5120 triangles each) bridged by C2 on a
+flat C1/C2 interface.
+
+Prints one JSON line: whole-step MLUPS, the lattice update's HBM roofline
+fraction (algorithmic bytes / kernel time from HIP events on the library's
+stream over the timed region) and the CPU oracle's rate on a bounded sample
+of the same workload.
 """
 import argparse
 import json
@@ -54,8 +58,8 @@ def bytes_per_lup(storage: str, Q: int = 9) -> int:
     return 2 * (3 * (Q - 1) * 2 + 3 * 4)  # 16-bit moving + FP32 rest populations
 
 
-def cpu_baseline(w, budget_s: float):
-    """The oracle as it stands, on the same lattice, for about budget_s."""
+def cpu_baseline(w, budget_s: float, note: str = ""):
+    """The oracle as it stands, on the given lattice, for about budget_s."""
     import oracle
 
     oracle.build(force=False)
@@ -74,8 +78,10 @@ def cpu_baseline(w, budget_s: float):
         if el >= budget_s or n >= 200:
             break
     N = s.N
+    p = w["params"]
+    dims = f"{p['nx']}x{p['ny']}" + (f"x{p['nz']}" if p.get("lattice", 0) == 1 else "")
     return {"value": N * n / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} full steps of the same {w['params']['nx']}x{w['params']['ny']} workload "
+            "sample": f"{n} full steps of the {note or 'same'} {dims} workload "
                       f"({el:.1f} s, FP64, {threads} OpenMP threads)"}
 
 
@@ -85,7 +91,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp64"])
-    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
+                    help="c2: 2048^2 D2Q9 with 16 capsules; c3: 256^3 D3Q19 with two capsules")
+    ap.add_argument("--size", type=int, default=0, help="lattice side (default 2048 / 256)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--block-x", type=int, default=0, help="fused kernel lanes per workgroup")
@@ -117,7 +125,9 @@ def main():
     from paper_1906_03065_amd import lbib
     from paper_1906_03065_amd import workloads as W
 
-    w = W.c2(n=args.size)
+    d3 = args.workload == "c3"
+    size = args.size or (256 if d3 else 2048)
+    w = W.c3(n=size) if d3 else W.c2(n=size)
     g = lbib.from_workload(w, storage=args.storage, device="cuda:0")
     g.set_launch(args.block_x, args.seg, args.nxcd, args.ring)
     N = g.N
@@ -138,7 +148,7 @@ def main():
     el = t1 - t0
     mlups = N * args.steps / el / 1e6
     lb_ms = tm["lb"] / max(tm["steps"], 1)
-    bpl = bytes_per_lup(args.storage)
+    bpl = bytes_per_lup(args.storage, 19 if d3 else 9)
     achieved = bpl * N / (lb_ms * 1e-3) / 1e9
     out = {
         "metric": "MLUPS & % HBM roofline; wall time to equilibrium, warm-start vs plain",
@@ -153,20 +163,29 @@ def main():
         "vs_baseline": None,
         "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": f"D2Q9 {args.size}x{args.size}, walls in y, 16 capsules "
-                               f"(R 24-64, {sum(len(m['X']) for m in w['membranes'])} markers), "
-                               f"flat C1/C2 interface, {args.storage} populations",
+        "config": {"workload": (f"D3Q19 {size}^3, walls in z, two icosphere capsules (R {size / 6.4:g}, "
+                                f"{len(w['membranes'][0]['tris'])} triangles each) bridged by C2, "
+                                f"flat C1/C2 interface, {args.storage} populations" if d3 else
+                                f"D2Q9 {size}x{size}, walls in y, 16 capsules "
+                                f"(R 24-64, {sum(len(m['X']) for m in w['membranes'])} markers), "
+                                f"flat C1/C2 interface, {args.storage} populations"),
                    "nodes": N, "capsules": len(w["membranes"]),
                    "markers": sum(len(m["X"]) for m in w["membranes"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.storage, args.size),
-                     "kernel": "k_lb2d", "kernel_ms": round(lb_ms, 5), "bytes_per_lup": bpl,
+                     "traffic": None if d3 else measured_traffic(args.storage, size),
+                     "kernel": "k_mom3d + k_lb3d" if d3 else "k_lb2d", "kernel_ms": round(lb_ms, 5),
+                     "bytes_per_lup": bpl,
                      "kernel_share_of_step": round(lb_ms / (el * 1e3 / args.steps), 4),
                      "launch": g.get_launch()},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        if d3:
+            # the oracle's brute-force mesh distances make a 256^3 step take
+            # minutes: time it on the same workload generated at 64^3
+            out["cpu_baseline"] = cpu_baseline(W.c3(n=64), args.cpu_seconds, "same two-capsule")
+        else:
+            out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -20,7 +20,6 @@ namespace lb {
 
 constexpr int TILE3 = 8;
 constexpr int COUP3_THREADS = 512;  // one thread per node of an 8^3 tile
-constexpr int COUP3_CHUNK = 1024;
 constexpr int COUP3_KEEP = 2;
 
 struct MeshDev {
@@ -34,6 +33,7 @@ struct MeshDev {
   int* vt;
   double* fn;     // 3 per triangle: unit face normal (area vector direction)
   double* vn;     // 3 per vertex: angle-weighted normal
+  int* coff;      // K+1 offsets of the 64-triangle clusters of each mesh
   int T, E;
 };
 
@@ -157,20 +157,6 @@ __device__ __forceinline__ double tri_d2(const double* p, const double* a, const
   return best;
 }
 
-// does the ray from p towards +x cross triangle (a, b, c)?  (strict inside
-// of the triangle's projection onto the yz plane)
-__device__ __forceinline__ int ray_tri(const double* p, const double* a, const double* b,
-                                       const double* c) {
-  const double e0 = (b[1] - a[1]) * (p[2] - a[2]) - (b[2] - a[2]) * (p[1] - a[1]);
-  const double e1 = (c[1] - b[1]) * (p[2] - b[2]) - (c[2] - b[2]) * (p[1] - b[1]);
-  const double e2 = (a[1] - c[1]) * (p[2] - c[2]) - (a[2] - c[2]) * (p[1] - c[1]);
-  const bool pos = e0 > 0 && e1 > 0 && e2 > 0, neg = e0 < 0 && e1 < 0 && e2 < 0;
-  if (!pos && !neg) return 0;
-  const double s = e0 + e1 + e2;
-  const double xs = (e1 * a[0] + e2 * b[0] + e0 * c[0]) / s;
-  return xs > p[0];
-}
-
 struct Coup3Args {
   int nx, ny, nz, wall_y, wall_z;
   double alpha, kappa_c, r_cut;
@@ -214,26 +200,287 @@ __device__ __forceinline__ TileGeo tile_geo(const double* bx, const double* ct, 
   return g;
 }
 
+// ---------------------------------------------------------------------------
+// Closest-triangle search.  Distances are first compared in FP32 (with
+// margins far above the FP32 rounding), and every triangle whose FP32
+// distance is within a tolerance of a point's FP32 minimum is re-evaluated
+// in FP64, so the FP64 closest triangle (lowest index on exact ties) is the
+// one chosen.  Levels: the whole mesh against the 8^3 tile centre (from a
+// per-step FP32 table relative to the membrane's box centre), the tile's
+// candidate list against the centre of each 4^3 sub-tile (one wave), and
+// the sub-tile's list against each of its nodes.  At every level a bounding
+// sphere per triangle gives |p - c| - r <= d(p, T) <= |p - c| + r: the least
+// upper bound over the list caps the minimum, and only triangles whose lower
+// bound reaches below it get the exact distance.
+
+// per-step FP32 table: 4 float4 per triangle, relative to the box centre of
+// the triangle's membrane: the vertices, then (centroid, bounding radius)
+__global__ void k_tritable3d(MemDev md, MeshDev mh, float4* __restrict__ tab) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= mh.T) return;
+  int m = 0;
+  while (m + 1 < md.K && mh.toff[m + 1] <= t) m++;
+  const double* bx = md.mbox + 8 * m;
+  const double c[3] = {0.5 * (bx[0] + bx[3]), 0.5 * (bx[1] + bx[4]), 0.5 * (bx[2] + bx[5])};
+  const double* v[3];
+  for (int k = 0; k < 3; k++) v[k] = md.X + 3 * mh.tri[3 * t + k];
+  double g[3], r = 0.0;
+  for (int a = 0; a < 3; a++) g[a] = (v[0][a] + v[1][a] + v[2][a]) / 3.0;
+  for (int k = 0; k < 3; k++) {
+    double d[3];
+    sub3(v[k], g, d);
+    r = fmax(r, sqrt(dot3d(d, d)));
+    tab[4 * t + k] = make_float4((float)(v[k][0] - c[0]), (float)(v[k][1] - c[1]), (float)(v[k][2] - c[2]), 0.0f);
+  }
+  tab[4 * t + 3] = make_float4((float)(g[0] - c[0]), (float)(g[1] - c[1]), (float)(g[2] - c[2]),
+                               (float)(r * (1.0 + 1e-6) + 1e-5));
+}
+
+// bounding sphere of every cluster of 64 consecutive triangles of a mesh,
+// from the triangles' spheres (one wave per cluster)
+constexpr int CL3 = 64;
+__global__ void k_clusters3d(MemDev md, MeshDev mh, const float4* __restrict__ tab, float4* __restrict__ ctab,
+                             int ncl) {
+  const int gk = (int)((blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  if (gk >= ncl) return;
+  int m = 0;
+  while (m + 1 < md.K && mh.coff[m + 1] <= gk) m++;
+  const int t0 = mh.toff[m] + (gk - mh.coff[m]) * CL3, t1 = min(t0 + CL3, mh.toff[m + 1]);
+  const int t = t0 + lane;
+  const bool live = t < t1;
+  float4 sp = live ? tab[4 * t + 3] : make_float4(0.f, 0.f, 0.f, 0.f);
+  float sx = sp.x, sy = sp.y, sz = sp.z;
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o, 64);
+    sy += __shfl_xor(sy, o, 64);
+    sz += __shfl_xor(sz, o, 64);
+  }
+  const float inv = 1.0f / (float)(t1 - t0);
+  const float cx = sx * inv, cy = sy * inv, cz = sz * inv;
+  float r = 0.0f;
+  if (live) {
+    const float dx = sp.x - cx, dy = sp.y - cy, dz = sp.z - cz;
+    r = sqrtf(dx * dx + dy * dy + dz * dz) + sp.w;
+  }
+  for (int o = 32; o > 0; o >>= 1) r = fmaxf(r, __shfl_xor(r, o, 64));
+  if (lane == 0) ctab[gk] = make_float4(cx, cy, cz, r * (1.0f + 1e-5f) + 1e-4f);
+}
+
+__device__ __forceinline__ float dot3f(float ax, float ay, float az, float bx, float by, float bz) {
+  return ax * bx + ay * by + az * bz;
+}
+
+// distance from p to the centre of bounding sphere s (radius in s.w)
+__device__ __forceinline__ float sph_dist(float px, float py, float pz, float4 s) {
+  const float dx = px - s.x, dy = py - s.y, dz = pz - s.z;
+  return sqrtf(dx * dx + dy * dy + dz * dz);
+}
+
+// squared distance from p to the segment s0 + t e (t in [0,1]), ie = 1/|e|^2
+__device__ __forceinline__ float seg_d2f(float px, float py, float pz, float ex, float ey, float ez,
+                                         float ie) {
+  const float t = fminf(fmaxf(dot3f(px, py, pz, ex, ey, ez) * ie, 0.0f), 1.0f);
+  const float dx = px - t * ex, dy = py - t * ey, dz = pz - t * ez;
+  return dx * dx + dy * dy + dz * dz;
+}
+
+// FP32 squared distance from p to triangle (a, b, c), all in one frame
+__device__ __forceinline__ float tri_d2f_vtx(float px, float py, float pz, float4 a, float4 b, float4 c) {
+  const float e0x = b.x - a.x, e0y = b.y - a.y, e0z = b.z - a.z;
+  const float e1x = c.x - a.x, e1y = c.y - a.y, e1z = c.z - a.z;
+  const float apx = px - a.x, apy = py - a.y, apz = pz - a.z;
+  const float nx = e0y * e1z - e0z * e1y, ny = e0z * e1x - e0x * e1z, nz = e0x * e1y - e0y * e1x;
+  const float nn = nx * nx + ny * ny + nz * nz;
+  if (nn > 0.0f) {
+    const float inn = 1.0f / nn;
+    // u = ((ap x e1) . n) / nn, v = ((e0 x ap) . n) / nn
+    const float u = ((apy * e1z - apz * e1y) * nx + (apz * e1x - apx * e1z) * ny + (apx * e1y - apy * e1x) * nz) * inn;
+    const float v = ((e0y * apz - e0z * apy) * nx + (e0z * apx - e0x * apz) * ny + (e0x * apy - e0y * apx) * nz) * inn;
+    if (u > 0.0f && v > 0.0f && u + v < 1.0f) {
+      const float h = apx * nx + apy * ny + apz * nz;
+      return h * h * inn;
+    }
+  }
+  const float l0 = e0x * e0x + e0y * e0y + e0z * e0z, l1 = e1x * e1x + e1y * e1y + e1z * e1z;
+  const float e2x = e1x - e0x, e2y = e1y - e0y, e2z = e1z - e0z;
+  const float l2 = e2x * e2x + e2y * e2y + e2z * e2z;
+  float d = seg_d2f(apx, apy, apz, e0x, e0y, e0z, l0 > 0.0f ? 1.0f / l0 : 0.0f);
+  d = fminf(d, seg_d2f(apx, apy, apz, e1x, e1y, e1z, l1 > 0.0f ? 1.0f / l1 : 0.0f));
+  d = fminf(d, seg_d2f(apx - e0x, apy - e0y, apz - e0z, e2x, e2y, e2z, l2 > 0.0f ? 1.0f / l2 : 0.0f));
+  return d;
+}
+
+// candidate geometry in LDS, FP32 relative to the tile centre, precomputed in
+// FP64: G0 = (a, 1/|e0|^2), G1 = (e0, 1/|e1|^2), G2 = (e1, 1/|e2|^2),
+// G3 = (e1 x n)/|n|^2, G4 = (n x e0)/|n|^2, G5 = n/|n|, so that the
+// barycentric coordinates of the projection are ap.G3, ap.G4; and the
+// bounding sphere G6 = (centroid, radius)
+constexpr int C3_LIST = 512;   // candidates whose geometry is staged at once
+constexpr int C3_IDS = 4096;   // candidate ids of one tile
+constexpr int C3_GEO = 7;
+constexpr int C3_TIES = 8;    // near-ties a node keeps in registers
+
+__device__ __forceinline__ void geo_store(float4 (*sg)[C3_LIST], int j, const double* a, const double* b,
+                                          const double* c, const double* pc) {
+  double e0[3], e1[3], e2[3], n[3], U[3], V[3], g[3];
+  sub3(b, a, e0);
+  sub3(c, a, e1);
+  sub3(e1, e0, e2);
+  cross3d(e0, e1, n);
+  const double nn = dot3d(n, n);
+  const double inn = nn > 0.0 ? 1.0 / nn : 0.0;
+  cross3d(e1, n, U);
+  cross3d(n, e0, V);
+  const double l0 = dot3d(e0, e0), l1 = dot3d(e1, e1), l2 = dot3d(e2, e2);
+  const double rn = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+  for (int q = 0; q < 3; q++) g[q] = (a[q] + b[q] + c[q]) / 3.0;
+  double r = 0.0;
+  const double* P[3] = {a, b, c};
+  for (int k = 0; k < 3; k++) {
+    double d[3];
+    sub3(P[k], g, d);
+    r = fmax(r, sqrt(dot3d(d, d)));
+  }
+  sg[0][j] = make_float4((float)(a[0] - pc[0]), (float)(a[1] - pc[1]), (float)(a[2] - pc[2]),
+                         l0 > 0.0 ? (float)(1.0 / l0) : 0.0f);
+  sg[1][j] = make_float4((float)e0[0], (float)e0[1], (float)e0[2], l1 > 0.0 ? (float)(1.0 / l1) : 0.0f);
+  sg[2][j] = make_float4((float)e1[0], (float)e1[1], (float)e1[2], l2 > 0.0 ? (float)(1.0 / l2) : 0.0f);
+  sg[3][j] = make_float4((float)(U[0] * inn), (float)(U[1] * inn), (float)(U[2] * inn), 0.0f);
+  sg[4][j] = make_float4((float)(V[0] * inn), (float)(V[1] * inn), (float)(V[2] * inn), 0.0f);
+  sg[5][j] = make_float4((float)(n[0] * rn), (float)(n[1] * rn), (float)(n[2] * rn), 0.0f);
+  sg[6][j] = make_float4((float)(g[0] - pc[0]), (float)(g[1] - pc[1]), (float)(g[2] - pc[2]),
+                         (float)(r * (1.0 + 1e-6) + 1e-5));
+}
+
+__device__ __forceinline__ float geo_d2f(const float4 (*sg)[C3_LIST], int j, float px, float py, float pz) {
+  const float4 g0 = sg[0][j], g1 = sg[1][j], g2 = sg[2][j], g3 = sg[3][j], g4 = sg[4][j], g5 = sg[5][j];
+  const float apx = px - g0.x, apy = py - g0.y, apz = pz - g0.z;
+  const float u = dot3f(apx, apy, apz, g3.x, g3.y, g3.z), v = dot3f(apx, apy, apz, g4.x, g4.y, g4.z);
+  const float h = dot3f(apx, apy, apz, g5.x, g5.y, g5.z);
+  float d = seg_d2f(apx, apy, apz, g1.x, g1.y, g1.z, g0.w);
+  d = fminf(d, seg_d2f(apx, apy, apz, g2.x, g2.y, g2.z, g1.w));
+  d = fminf(d, seg_d2f(apx - g1.x, apy - g1.y, apz - g1.z, g2.x - g1.x, g2.y - g1.y, g2.z - g1.z, g2.w));
+  return (u > 0.0f && v > 0.0f && u + v < 1.0f) ? h * h : d;
+}
+
+// side of point P (true: inside) at its closest triangle tg with weights w:
+// face normal, sum of the two face normals at an edge, or the angle-weighted
+// vertex normal (outward for orientation o = +1)
+__device__ __forceinline__ bool mesh_side(const MemDev& md, const MeshDev& mh, int tg, const double* w,
+                                          const double* P, double o) {
+  const int* tv = mh.tri + 3 * tg;
+  double Qp[3] = {0, 0, 0}, nrm[3];
+  for (int k = 0; k < 3; k++)
+    for (int a = 0; a < 3; a++) Qp[a] += w[k] * md.X[3 * tv[k] + a];
+  const int zeros = (w[0] == 0.0) + (w[1] == 0.0) + (w[2] == 0.0);
+  if (zeros == 0) {
+    for (int a = 0; a < 3; a++) nrm[a] = mh.fn[3 * tg + a];
+  } else if (zeros == 1) {
+    const int k = w[0] == 0.0 ? 0 : (w[1] == 0.0 ? 1 : 2);  // edge opposite vertex k
+    const int nb = mh.tadj[3 * tg + (k + 1) % 3];
+    for (int a = 0; a < 3; a++) nrm[a] = mh.fn[3 * tg + a] + mh.fn[3 * nb + a];
+  } else {
+    const int k = w[0] != 0.0 ? 0 : (w[1] != 0.0 ? 1 : 2);
+    for (int a = 0; a < 3; a++) nrm[a] = mh.vn[3 * tv[k] + a];
+  }
+  double dv[3];
+  sub3(P, Qp, dv);
+  return o * dot3d(dv, nrm) < 0.0;
+}
+
+__device__ __forceinline__ double tri_d2_id(const MemDev& md, const MeshDev& mh, int tg, const double* P,
+                                            double* w) {
+  const int* tv = mh.tri + 3 * tg;
+  return tri_d2(P, md.X + 3 * tv[0], md.X + 3 * tv[1], md.X + 3 * tv[2], w);
+}
+
+// (d2, index) argmin with the lowest index on ties
+__device__ __forceinline__ void argmin_merge(double& d, int& i, double d2, int i2) {
+  if (d2 < d || (d2 == d && i2 >= 0 && (i < 0 || i2 < i))) {
+    d = d2;
+    i = i2;
+  }
+}
+
+__device__ __forceinline__ void wave_argmin(double& d, int& i) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double d2 = __shfl_xor(d, o, 64);
+    const int i2 = __shfl_xor(i, o, 64);
+    argmin_merge(d, i, d2, i2);
+  }
+}
+
+__device__ __forceinline__ float wave_minf(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int NT>
+__device__ void block_argmin(double& d, int& i, double* sd, int* si) {
+  wave_argmin(d, i);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sd[wv] = d;
+    si[wv] = i;
+  }
+  __syncthreads();
+  d = sd[0];
+  i = si[0];
+  for (int k = 1; k < NT / 64; k++) argmin_merge(d, i, sd[k], si[k]);
+  __syncthreads();
+}
+
+template <int NT>
+__device__ float block_minf(float v, float* sh) {
+  v = wave_minf(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  float t = sh[0];
+  for (int k = 1; k < NT / 64; k++) t = fminf(t, sh[k]);
+  __syncthreads();
+  return t;
+}
+
+// one 8^3 tile per workgroup of 512 threads (grid-stride over the active
+// tiles); wave w holds the 4^3 sub-tile (w & 1, (w >> 1) & 1, w >> 2)
 template <class St, typename R, int NT>
 __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMap tm, Coup3Args ca,
+                                                   const float4* __restrict__ ttab,
+                                                   const float4* __restrict__ ctab,
                                                    double* __restrict__ Ifield, St cur) {
-  __shared__ int s_cand[COUP3_CHUNK];
+  static_assert(NT == 512, "one thread per node of an 8^3 tile");
+  __shared__ float4 s_g[C3_GEO][C3_LIST];
+  __shared__ int s_id[C3_IDS];
+  __shared__ unsigned short s_wl[NT / 64][C3_LIST];
   __shared__ int s_cnt;
   __shared__ double s_red[NT / 64];
+  __shared__ int s_redi[NT / 64];
+  __shared__ float s_redf[NT / 64];
   __shared__ int b_tri[COUP3_KEEP][NT];
-  __shared__ double b_w[COUP3_KEEP][3][NT];
   __shared__ double b_sd[COUP3_KEEP][NT];
   const int ntl = tm.tstate[0];
   const double reach = ca.r_cut + 1.0;
-  const double hd = 0.5 * TILE3 * 1.7320508075688772;
+  const double hd = 0.5 * TILE3 * 1.7320508075688772;  // tile half-diagonal (box tests)
+  // largest distance of a node from the centre of its tile / sub-tile
+  const double rn8 = 0.5 * (TILE3 - 1) * 1.7320508075688772;
+  const double rn4 = 0.5 * (TILE3 / 2 - 1) * 1.7320508075688772;
+  const float mg = 0.01f;                                // FP32 distance margin
   const int per[3] = {1, !ca.wall_y, !ca.wall_z};
   const int dims[3] = {ca.nx, ca.ny, ca.nz};
+  const int lt = (int)threadIdx.x, lane = lt & 63, wv = lt >> 6;
+  const int off[3] = {(wv & 1) * 4 + (lane & 3), ((wv >> 1) & 1) * 4 + ((lane >> 2) & 3),
+                      (wv >> 2) * 4 + (lane >> 4)};
+  // sub-tile centre relative to the tile centre
+  const float cwf[3] = {(wv & 1) ? 2.0f : -2.0f, ((wv >> 1) & 1) ? 2.0f : -2.0f, (wv >> 2) ? 2.0f : -2.0f};
+  const unsigned long long below = (1ull << lane) - 1ull;
   for (int li = blockIdx.x; li < ntl; li += gridDim.x) {
     const int t = tm.tlist[li];
     const int tx = t % tm.ntx, ty = (t / tm.ntx) % tm.nty, tz = t / (tm.ntx * tm.nty);
     const int t0[3] = {tx * TILE3, ty * TILE3, tz * TILE3};
-    const int lt = (int)threadIdx.x;
-    const int xi[3] = {t0[0] + lt % TILE3, t0[1] + (lt / TILE3) % TILE3, t0[2] + lt / (TILE3 * TILE3)};
+    const int xi[3] = {t0[0] + off[0], t0[1] + off[1], t0[2] + off[2]};
     const bool valid = xi[0] < ca.nx && xi[1] < ca.ny && xi[2] < ca.nz;
     const double ct[3] = {t0[0] + 0.5 * (TILE3 - 1), t0[1] + 0.5 * (TILE3 - 1), t0[2] + 0.5 * (TILE3 - 1)};
     double Itot = 0.0;
@@ -242,114 +489,311 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
       const TileGeo g = tile_geo(md.mbox + 8 * m, ct, xi, t0, dims, per, hd, reach, valid);
       if (g.miss) continue;  // uniform over the block
       const int t0m = mh.toff[m], nt = mh.toff[m + 1] - t0m;
+      const double o = md.mbox[8 * m + 6];
       const int slot = kept++;
-      double d2b = 1e300, wb[3] = {0, 0, 0};
+      double d2b = 1e300;
       int tb = -1;
-      bool far = false;  // the whole tile lies beyond r_cut: I from the ray parity
-      int par = 0;
-      if (!g.split) {
-        double dmin = 1e300;
-        int cr = 0;
-        // ray parity of the tile centre, with the same tiny offset of the ray
-        // in y and z that keeps it off edges and vertices
-        const double pr[3] = {g.pc[0], g.pc[1] + 1.2345678e-7, g.pc[2] + 2.3456789e-7};
-        for (int q = threadIdx.x; q < nt; q += NT) {
-          const int* tv = mh.tri + 3 * (t0m + q);
-          double w[3];
-          dmin = fmin(dmin, tri_d2(g.pc, md.X + 3 * tv[0], md.X + 3 * tv[1], md.X + 3 * tv[2], w));
-          cr += ray_tri(pr, md.X + 3 * tv[0], md.X + 3 * tv[1], md.X + 3 * tv[2]);
+      bool decided = false;  // I of this node already added (no band data)
+      if (g.split) {
+        // nodes of different images: each searches the whole mesh in FP64
+        if (g.inbox)
+          for (int q = 0; q < nt; q++) {
+            double w[3];
+            argmin_merge(d2b, tb, tri_d2_id(md, mh, t0m + q, g.pp, w), q);
+          }
+      } else {
+        const double* bx = md.mbox + 8 * m;
+        const float pcr[3] = {(float)(g.pc[0] - 0.5 * (bx[0] + bx[3])), (float)(g.pc[1] - 0.5 * (bx[1] + bx[4])),
+                              (float)(g.pc[2] - 0.5 * (bx[2] + bx[5]))};
+        const float4* tab = ttab + 4 * (size_t)t0m;
+        const float4* cls = ctab + mh.coff[m];
+        const int ncl = mh.coff[m + 1] - mh.coff[m];
+        // distance of the tile centre to the mesh: the least cluster upper
+        // bound, then exact distances in the clusters that reach below it
+        // (one wave per cluster, one lane per triangle)
+        float ul = 3.0e38f;
+        for (int k = lt; k < ncl; k += NT) ul = fminf(ul, sph_dist(pcr[0], pcr[1], pcr[2], cls[k]) + cls[k].w);
+        const float U = block_minf<NT>(ul, s_redf) + mg;
+        float dl = 3.0e38f;
+        for (int k = wv; k < ncl; k += NT / 64) {
+          const float4 cs = cls[k];
+          if (sph_dist(pcr[0], pcr[1], pcr[2], cs) - cs.w > U) continue;
+          const int q = k * CL3 + lane;
+          if (q < nt) dl = fminf(dl, tri_d2f_vtx(pcr[0], pcr[1], pcr[2], tab[4 * q], tab[4 * q + 1], tab[4 * q + 2]));
         }
-        dmin = sqrt(block_min<NT>(dmin, s_red));
-        par = ((int)block_sum<NT>((double)cr, s_red)) & 1;
-        far = dmin > ca.r_cut + hd;
-        if (!far) {
-          // every node's closest triangle lies within dmin + 2 hd of the centre
-          const double cull = dmin + 2.0 * hd + 1e-6;
-          for (int c0 = 0; c0 < nt; c0 += COUP3_CHUNK) {
-            if (threadIdx.x == 0) s_cnt = 0;
-            __syncthreads();
-            for (int q = c0 + threadIdx.x; q < min(nt, c0 + COUP3_CHUNK); q += NT) {
-              const int* tv = mh.tri + 3 * (t0m + q);
+        const float dminf = sqrtf(block_minf<NT>(dl, s_redf));
+        if ((double)dminf > ca.r_cut + rn8 + 0.02) {
+          // the whole tile is beyond r_cut: every node is on the side of the
+          // tile centre, taken at the centre's closest triangle
+          const float tl = dminf * dminf + 0.05f + 1e-4f * dminf * dminf;
+          const float tlr = sqrtf(tl) + mg;
+          double dc = 1e300;
+          int ic = -1;
+          for (int k = wv; k < ncl; k += NT / 64) {
+            const float4 cs = cls[k];
+            if (sph_dist(pcr[0], pcr[1], pcr[2], cs) - cs.w > tlr) continue;
+            const int q = k * CL3 + lane;
+            if (q < nt &&
+                tri_d2f_vtx(pcr[0], pcr[1], pcr[2], tab[4 * q], tab[4 * q + 1], tab[4 * q + 2]) <= tl) {
               double w[3];
-              if (tri_d2(g.pc, md.X + 3 * tv[0], md.X + 3 * tv[1], md.X + 3 * tv[2], w) <= cull * cull)
-                s_cand[atomicAdd(&s_cnt, 1)] = q;
+              argmin_merge(dc, ic, tri_d2_id(md, mh, t0m + q, g.pc, w), q);
             }
-            __syncthreads();
-            const int nc = s_cnt;
-            if (g.inbox)
-              for (int q = 0; q < nc; q++) {
-                const int tq = s_cand[q];
-                const int* tv = mh.tri + 3 * (t0m + tq);
-                double w[3];
-                const double d2 = tri_d2(g.pp, md.X + 3 * tv[0], md.X + 3 * tv[1], md.X + 3 * tv[2], w);
-                if (d2 < d2b || (d2 == d2b && tq < tb)) {
-                  d2b = d2;
-                  tb = tq;
-                  wb[0] = w[0];
-                  wb[1] = w[1];
-                  wb[2] = w[2];
+          }
+          block_argmin<NT>(dc, ic, s_red, s_redi);
+          if (ic >= 0) {  // always: the FP32 minimum itself is within tl
+            double w[3];
+            tri_d2_id(md, mh, t0m + ic, g.pc, w);
+            if (g.inbox && mesh_side(md, mh, t0m + ic, w, g.pc, o)) Itot += 1.0;
+          }
+          decided = true;
+        } else {
+          // tile candidates: every node's closest triangle lies within
+          // dmin + 2 rn8 of the tile centre.  Their ids go to LDS; their
+          // geometry is staged C3_LIST at a time.
+          const float cull = dminf + (float)(2.0 * rn8) + 0.02f;
+          if (lt == 0) s_cnt = 0;
+          __syncthreads();
+          for (int k = wv; k < ncl; k += NT / 64) {
+            const float4 cs = cls[k];
+            if (sph_dist(pcr[0], pcr[1], pcr[2], cs) - cs.w > cull) continue;
+            const int q = k * CL3 + lane;
+            bool in = false;
+            if (q < nt) {
+              const float4 sp = tab[4 * q + 3];
+              const float dc = sph_dist(pcr[0], pcr[1], pcr[2], sp);
+              in = dc - sp.w <= cull &&
+                   (dc + sp.w <= cull ||
+                    tri_d2f_vtx(pcr[0], pcr[1], pcr[2], tab[4 * q], tab[4 * q + 1], tab[4 * q + 2]) <= cull * cull);
+            }
+            const unsigned long long mk = __ballot(in);
+            int base = 0;
+            if (lane == 0 && mk) base = atomicAdd(&s_cnt, __popcll(mk));
+            base = __shfl(base, 0, 64);
+            const int j = base + __popcll(mk & below);
+            if (in && j < C3_IDS) s_id[j] = q;
+          }
+          __syncthreads();
+          const int nc = s_cnt;
+          if (nc > C3_IDS) {
+            // more candidates than ids fit: chunks of the whole mesh, every
+            // node re-evaluating the chunk's candidates in FP64
+            for (int c0 = 0; c0 < nt; c0 += C3_IDS) {
+              __syncthreads();
+              if (lt == 0) s_cnt = 0;
+              __syncthreads();
+              for (int q = c0 + lt; q < min(nt, c0 + C3_IDS); q += NT)
+                if (tri_d2f_vtx(pcr[0], pcr[1], pcr[2], tab[4 * q], tab[4 * q + 1], tab[4 * q + 2]) <= cull * cull)
+                  s_id[atomicAdd(&s_cnt, 1)] = q;
+              __syncthreads();
+              const int ncc = s_cnt;
+              if (g.inbox)
+                for (int j = 0; j < ncc; j++) {
+                  double w[3];
+                  argmin_merge(d2b, tb, tri_d2_id(md, mh, t0m + s_id[j], g.pp, w), s_id[j]);
+                }
+            }
+          } else {
+            const int nch = (nc + C3_LIST - 1) / C3_LIST;
+            // stage the geometry of chunk c (all threads; the caller syncs)
+            auto stage = [&](int c) {
+              const int c0 = c * C3_LIST, n0 = min(C3_LIST, nc - c0);
+              for (int j = lt; j < n0; j += NT) {
+                const int* tv = mh.tri + 3 * (t0m + s_id[c0 + j]);
+                geo_store(s_g, j, md.X + 3 * tv[0], md.X + 3 * tv[1], md.X + 3 * tv[2], g.pc);
+              }
+            };
+            // 1. sub-tile centre distance over all candidates (the least
+            //    upper bound so far gates the exact distances)
+            float dw = 3.0e38f, uw = 3.0e38f;
+            for (int c = 0; c < nch; c++) {
+              __syncthreads();
+              stage(c);
+              __syncthreads();
+              const int n0 = min(C3_LIST, nc - c * C3_LIST);
+              float u = uw;
+              for (int j = lane; j < n0; j += 64) u = fminf(u, sph_dist(cwf[0], cwf[1], cwf[2], s_g[6][j]) + s_g[6][j].w);
+              uw = wave_minf(u);
+              // entries whose sphere reaches below uw, compacted, then exact
+              int ne = 0;
+              for (int base = 0; base < n0; base += 64) {
+                const int j = base + lane;
+                const bool pr = j < n0 && sph_dist(cwf[0], cwf[1], cwf[2], s_g[6][j]) - s_g[6][j].w <= uw + mg;
+                const unsigned long long mk = __ballot(pr);
+                if (pr) s_wl[wv][ne + __popcll(mk & below)] = (unsigned short)j;
+                ne += __popcll(mk);
+              }
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              for (int k = lane; k < ne; k += 64) dw = fminf(dw, geo_d2f(s_g, s_wl[wv][k], cwf[0], cwf[1], cwf[2]));
+              __builtin_amdgcn_wave_barrier();
+            }
+            dw = wave_minf(dw);
+            const float dwr = sqrtf(dw);
+            // the whole sub-tile beyond r_cut: the side of its centre
+            const bool wfar = (double)dwr > ca.r_cut + rn4 + 0.01;  // uniform over the wave
+            const double pw[3] = {g.pc[0] + cwf[0], g.pc[1] + cwf[1], g.pc[2] + cwf[2]};
+            const float tlw = dw + 0.05f + 1e-4f * dw;
+            const float tlwr = sqrtf(tlw) + mg;
+            const float cwr = dwr + (float)(2.0 * rn4) + mg;
+            const float pn[3] = {(float)(g.pp[0] - g.pc[0]), (float)(g.pp[1] - g.pc[1]), (float)(g.pp[2] - g.pc[2])};
+            // the sub-tile's share of chunk c (bounding spheres within reach),
+            // compacted with ballots
+            auto wave_list = [&](int c) {
+              const int n0 = min(C3_LIST, nc - c * C3_LIST);
+              int cnt = 0;
+              for (int base = 0; base < n0; base += 64) {
+                const int j = base + lane;
+                const bool pr = j < n0 && sph_dist(cwf[0], cwf[1], cwf[2], s_g[6][j]) - s_g[6][j].w <= cwr;
+                const unsigned long long mk = __ballot(pr);
+                if (pr) s_wl[wv][cnt + __popcll(mk & below)] = (unsigned short)j;
+                cnt += __popcll(mk);
+              }
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              return cnt;
+            };
+            // 2. far sub-tiles: FP64 near-ties of the centre; near ones: the
+            //    FP32 minimum of every node
+            double dc = 1e300;
+            int ic = -1;
+            float bf = 3.0e38f;
+            int cnt = 0;
+            // entries that were within the tie tolerance of the node's
+            // running FP32 minimum when scanned (a superset of its final
+            // near-ties), one bit per wave-list entry
+            unsigned long long msk[C3_LIST / 64];
+#pragma unroll
+            for (int w = 0; w < C3_LIST / 64; w++) msk[w] = 0ull;
+            for (int c = 0; c < nch; c++) {
+              if (nch > 1) {
+                __syncthreads();
+                stage(c);
+                __syncthreads();
+              }
+              const int c0 = c * C3_LIST, n0 = min(C3_LIST, nc - c0);
+              if (wfar) {
+                for (int j = lane; j < n0; j += 64) {
+                  if (sph_dist(cwf[0], cwf[1], cwf[2], s_g[6][j]) - s_g[6][j].w > tlwr) continue;
+                  if (geo_d2f(s_g, j, cwf[0], cwf[1], cwf[2]) <= tlw) {
+                    double w[3];
+                    argmin_merge(dc, ic, tri_d2_id(md, mh, t0m + s_id[c0 + j], pw, w), s_id[c0 + j]);
+                  }
+                }
+              } else {
+                cnt = wave_list(c);
+                if (g.inbox && nch == 1) {
+#pragma unroll
+                  for (int w = 0; w < C3_LIST / 64; w++) {
+                    const int k0 = w * 64, k1 = min(cnt, k0 + 64);
+                    unsigned long long mw = 0ull;
+                    for (int k = k0; k < k1; k++) {
+                      const float d = geo_d2f(s_g, s_wl[wv][k], pn[0], pn[1], pn[2]);
+                      bf = fminf(bf, d);
+                      mw |= (d <= bf + 1e-3f + 1e-5f * bf ? 1ull : 0ull) << (k - k0);
+                    }
+                    msk[w] = mw;
+                  }
+                } else if (g.inbox) {
+                  for (int k = 0; k < cnt; k++) bf = fminf(bf, geo_d2f(s_g, s_wl[wv][k], pn[0], pn[1], pn[2]));
                 }
               }
-            __syncthreads();
-          }
-        }
-      } else if (g.inbox) {
-        // nodes of different images: each searches the whole mesh
-        for (int q = 0; q < nt; q++) {
-          const int* tv = mh.tri + 3 * (t0m + q);
-          double w[3];
-          const double d2 = tri_d2(g.pp, md.X + 3 * tv[0], md.X + 3 * tv[1], md.X + 3 * tv[2], w);
-          if (d2 < d2b) {
-            d2b = d2;
-            tb = q;
-            wb[0] = w[0];
-            wb[1] = w[1];
-            wb[2] = w[2];
+            }
+            if (wfar) {
+              wave_argmin(dc, ic);
+              if (ic >= 0) {  // always: the FP32 minimum itself is within tlw
+                double w[3];
+                tri_d2_id(md, mh, t0m + ic, pw, w);
+                if (g.inbox && mesh_side(md, mh, t0m + ic, w, pw, o)) Itot += 1.0;
+              }
+              decided = true;
+            }
+            // 3. near sub-tiles: FP64 re-evaluation of every candidate within
+            //    the FP32 rounding margin of the node's minimum
+            const float tol = 1e-3f + 1e-5f * bf;
+            const float tolr = sqrtf(bf + tol) + mg;
+            for (int c = 0; c < nch; c++) {
+              if (nch > 1) {
+                __syncthreads();
+                stage(c);
+                __syncthreads();
+              }
+              if (!wfar) {
+                const int c0 = c * C3_LIST;
+                if (nch > 1) cnt = wave_list(c);
+                // each node first collects its own near-ties (in registers),
+                // then all lanes re-evaluate theirs together, so the wave runs
+                // as many FP64 evaluations as the largest tie set, not as the
+                // union of all its nodes' ties
+                int tie[C3_TIES];
+                int nti = 0;
+                bool more = false;
+                auto add_tie = [&](int q) {
+#pragma unroll
+                  for (int r = 0; r < C3_TIES; r++)
+                    if (r == nti) tie[r] = q;
+                  more |= nti == C3_TIES;
+                  nti += nti < C3_TIES;
+                };
+                if (g.inbox && nch == 1) {
+                  // only the entries marked in the first scan
+#pragma unroll
+                  for (int w = 0; w < C3_LIST / 64; w++) {
+                    unsigned long long mw = msk[w];
+                    while (mw) {
+                      const int k = w * 64 + __ffsll((long long)mw) - 1;
+                      mw &= mw - 1ull;
+                      const int j = s_wl[wv][k];
+                      if (geo_d2f(s_g, j, pn[0], pn[1], pn[2]) <= bf + tol) add_tie(s_id[j]);
+                    }
+                  }
+                } else if (g.inbox) {
+                  for (int k = 0; k < cnt; k++) {
+                    const int j = s_wl[wv][k];
+                    const float4 sp = s_g[6][j];
+                    if (sph_dist(pn[0], pn[1], pn[2], sp) - sp.w > tolr) continue;
+                    if (geo_d2f(s_g, j, pn[0], pn[1], pn[2]) > bf + tol) continue;
+                    add_tie(s_id[c0 + j]);
+                  }
+                }
+#pragma unroll
+                for (int r = 0; r < C3_TIES; r++)
+                  if (r < nti) {
+                    double w[3];
+                    argmin_merge(d2b, tb, tri_d2_id(md, mh, t0m + tie[r], g.pp, w), tie[r]);
+                  }
+                if (more)  // more ties than registers: every candidate again
+                  for (int k = 0; k < cnt; k++) {
+                    const int j = s_wl[wv][k];
+                    if (geo_d2f(s_g, j, pn[0], pn[1], pn[2]) > bf + tol) continue;
+                    double w[3];
+                    argmin_merge(d2b, tb, tri_d2_id(md, mh, t0m + s_id[c0 + j], g.pp, w), s_id[c0 + j]);
+                  }
+              }
+            }
           }
         }
       }
       double sd = 0.0;
       bool band = false;
-      if (far) {
-        if (g.inbox && par) Itot += 1.0;
-      } else if (g.inbox && tb >= 0) {
-        const int tg = t0m + tb;
-        const int* tv = mh.tri + 3 * tg;
-        double Qp[3] = {0, 0, 0}, nrm[3];
-        for (int k = 0; k < 3; k++)
-          for (int a = 0; a < 3; a++) Qp[a] += wb[k] * md.X[3 * tv[k] + a];
-        const int zeros = (wb[0] == 0.0) + (wb[1] == 0.0) + (wb[2] == 0.0);
-        if (zeros == 0) {
-          for (int a = 0; a < 3; a++) nrm[a] = mh.fn[3 * tg + a];
-        } else if (zeros == 1) {
-          const int k = wb[0] == 0.0 ? 0 : (wb[1] == 0.0 ? 1 : 2);  // edge opposite vertex k
-          const int nb = mh.tadj[3 * tg + (k + 1) % 3];
-          for (int a = 0; a < 3; a++) nrm[a] = mh.fn[3 * tg + a] + mh.fn[3 * nb + a];
-        } else {
-          const int k = wb[0] != 0.0 ? 0 : (wb[1] != 0.0 ? 1 : 2);
-          for (int a = 0; a < 3; a++) nrm[a] = mh.vn[3 * tv[k] + a];
-        }
-        double dv[3];
-        sub3(g.pp, Qp, dv);
-        const double o = md.mbox[8 * m + 6];
-        const bool in = o * dot3d(dv, nrm) < 0.0;  // outward normals for o = +1
+      if (!decided && g.inbox && tb >= 0) {
+        double w[3];
+        tri_d2_id(md, mh, t0m + tb, g.pp, w);
+        const bool in = mesh_side(md, mh, t0m + tb, w, g.pp, o);
         const double d = sqrt(d2b);
         sd = in ? d : -d;
         band = d <= ca.r_cut;
         Itot += band ? 0.5 * (1.0 + tanh(sd / (2.0 * ca.alpha))) : (in ? 1.0 : 0.0);
       }
       if (slot < COUP3_KEEP) {
-        b_tri[slot][threadIdx.x] = band ? t0m + tb : -1;
-        b_w[slot][0][threadIdx.x] = wb[0];
-        b_w[slot][1][threadIdx.x] = wb[1];
-        b_w[slot][2][threadIdx.x] = wb[2];
-        b_sd[slot][threadIdx.x] = sd;
+        b_tri[slot][lt] = band ? t0m + tb : -1;
+        b_sd[slot][lt] = sd;
       }
+      __syncthreads();  // candidate lists are rebuilt for the next membrane
     }
     const long long node = valid ? ((long long)xi[2] * ca.ny + xi[1]) * ca.nx + xi[0] : 0;
     if (valid) Ifield[node] = Itot;
     if (ca.want_force) {
-      if (kept > COUP3_KEEP && threadIdx.x == 0) md.status[1] = 1;
+      if (kept > COUP3_KEEP && lt == 0) md.status[1] = 1;
       double psi = 0.0;
       if (valid) {
         using L = Lattice<19>;
@@ -372,12 +816,13 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
         const TileGeo g = tile_geo(md.mbox + 8 * m, ct, xi, t0, dims, per, hd, reach, valid);
         if (g.miss) continue;
         const int my = slot++;
-        const int tg = b_tri[my][threadIdx.x];
+        const int tg = b_tri[my][lt];
         if (tg < 0) continue;
-        const double sd = b_sd[my][threadIdx.x];
+        const double sd = b_sd[my][lt];
         const double d = fabs(sd);
         if (d == 0.0) continue;
-        const double w[3] = {b_w[my][0][threadIdx.x], b_w[my][1][threadIdx.x], b_w[my][2][threadIdx.x]};
+        double w[3];
+        tri_d2_id(md, mh, tg, g.pp, w);
         const int* tv = mh.tri + 3 * tg;
         double Qp[3] = {0, 0, 0};
         for (int k = 0; k < 3; k++)

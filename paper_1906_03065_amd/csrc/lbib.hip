@@ -59,7 +59,8 @@ struct Layout {
   size_t Ifield, fib, force, tflag, tlist, tstate, stage, part;
   size_t X, U, F, Facc, rest, moff, mid, ks, kb, mbox, status, memE;
   // 3D: moment field and triangle meshes
-  size_t mom, tri, toff, edge, erest, eoff, emem, tadj, vtoff, vt, fn, vn;
+  size_t mom, tri, toff, edge, erest, eoff, emem, tadj, vtoff, vt, fn, vn, ttab, ctab, coff;
+  int maxCl;
   int maxT, maxE;
   size_t total;
   long long ntiles;
@@ -147,6 +148,10 @@ Layout make_layout(const lbib_params* p) {
   L.vt = c.take((size_t)L.maxT * 3 * 4);
   L.fn = c.take((size_t)L.maxT * 3 * 8);
   L.vn = c.take(d3 ? (size_t)M * 3 * 8 : 0);
+  L.ttab = c.take((size_t)L.maxT * 4 * 16);
+  L.maxCl = d3 ? L.maxT / CL3 + K : 0;  // 64-triangle clusters, one partial per mesh
+  L.ctab = c.take((size_t)L.maxCl * 16);
+  L.coff = c.take(d3 ? (size_t)(K + 1) * 4 : 0);
   L.total = c.off;
   return L;
 }
@@ -167,7 +172,7 @@ struct lbib_sim {
   int K = 0, M = 0;
   std::vector<int> moff{0};
   int ntri = 0, nedge = 0;                 // triangles and edges of all meshes (3D)
-  std::vector<int> toff{0}, eoff{0}, vtoff{0};
+  std::vector<int> toff{0}, eoff{0}, vtoff{0}, coff{0};
   double r_cut = 0;
   int bx = 256, seg = 0;  // fused-kernel launch shape (seg 0: automatic)
   int nxcd = 1;           // L2 domains workgroups are dealt to (1: plain strip order)
@@ -256,6 +261,7 @@ struct lbib_sim {
     h.vt = at<int>(L.vt);
     h.fn = at<double>(L.fn);
     h.vn = at<double>(L.vn);
+    h.coff = at<int>(L.coff);
     h.T = ntri;
     h.E = nedge;
     return h;
@@ -555,9 +561,14 @@ struct Engine3D final : lbib_sim {
     hipLaunchKernelGGL(k_facenormals, dim3((ntri + 255) / 256), dim3(256), 0, stream, md, mh);
     hipLaunchKernelGGL(k_meshvolume<256>, dim3(K), dim3(256), 0, stream, md, mh);
     hipLaunchKernelGGL(k_vertexnormals, dim3((M + 255) / 256), dim3(256), 0, stream, md, mh);
+    hipLaunchKernelGGL(k_tritable3d, dim3((ntri + 255) / 256), dim3(256), 0, stream, md, mh, at<float4>(L.ttab));
+    const int ncl = coff.back();
+    hipLaunchKernelGGL(k_clusters3d, dim3((ncl * 64 + 255) / 256), dim3(256), 0, stream, md, mh,
+                       (const float4*)at<float4>(L.ttab), at<float4>(L.ctab), ncl);
     const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 4096);
     hipLaunchKernelGGL((k_coupling3d<St, R, COUP3_THREADS>), dim3(grid), dim3(COUP3_THREADS), 0, stream,
-                       md, mh, tm, coup_args(want_force), at<double>(L.Ifield), store(cur));
+                       md, mh, tm, coup_args(want_force), (const float4*)at<float4>(L.ttab),
+                       (const float4*)at<float4>(L.ctab), at<double>(L.Ifield), store(cur));
     return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
   }
 
@@ -870,10 +881,12 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
     HIPCHK(hipMemcpyAsync(w + s->L.emem + (size_t)s->nedge * 4, emem.data(), emem.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w + s->L.vt + (size_t)s->vtoff.back() * 4, vt_g.data(), vt_g.size() * 4, hipMemcpyHostToDevice, st));
     s->toff.push_back(s->ntri + n_elems);
+    s->coff.push_back(s->coff.back() + (n_elems + CL3 - 1) / CL3);
     s->eoff.push_back(s->nedge + ne);
     for (int v = 0; v < n; v++) s->vtoff.push_back(vtoff_g[v]);
     HIPCHK(hipMemcpyAsync(w + s->L.toff, s->toff.data(), s->toff.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w + s->L.eoff, s->eoff.data(), s->eoff.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.coff, s->coff.data(), s->coff.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w + s->L.vtoff, s->vtoff.data(), s->vtoff.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));  // host vectors go out of scope
     s->ntri += n_elems;
