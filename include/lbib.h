@@ -172,7 +172,52 @@ long long lbib_steps_done(const lbib_sim* s);
 int lbib_debug_poke(lbib_sim* s, int field, long long idx, double value);
 
 const char* lbib_strerror(int status);
+/* Frees the handle (not the workspace).  A batch member is freed with its
+   batch; destroying the member alone does nothing. */
 void lbib_destroy(lbib_sim* s);
+
+/* ------------------------------------------------------------------------
+   Batches: n independent D2Q9 simulations (FP32 storage, n <= 256) in one
+   workspace, stepped together.  Each phase of a step is one launch over all
+   members (the lattice update one launch per size class: lattice width
+   <= 128, <= 256, larger), and the step is captured once per buffer parity
+   in a hipGraph and replayed (on a stream that can be captured, i.e. not
+   the legacy default stream; otherwise the launches are enqueued directly).
+   Every member gives the same results, bit for bit, as the same
+   simulation created alone.
+   ------------------------------------------------------------------------ */
+
+/* Device bytes for a batch of params[0..n-1] (each as for lbib_create). */
+int lbib_batch_workspace_bytes(int n, const lbib_params* params, size_t* bytes);
+
+/* Create the batch in the caller's workspace.  LBIB_EINVAL for n outside
+   [1, 256], a D3Q19 or non-FP32 member, or invalid parameters. */
+int lbib_batch_create(int n, const lbib_params* params, void* dev_workspace, size_t ws_bytes,
+                      void* hip_stream, lbib_sim** out_batch);
+
+/* Handle of member k (owned by the batch): lbib_add_membrane,
+   lbib_set_fields, lbib_get_fields, lbib_get_membrane, lbib_energy,
+   lbib_save/lbib_load and lbib_check work on it as on a simulation created
+   alone; lbib_step on a member is LBIB_ESTATE.  lbib_step(batch, n)
+   advances every member n steps (all members must have their fields set);
+   lbib_check(batch) checks every member.  Per-simulation calls on the
+   batch handle itself return LBIB_EINVAL. */
+int lbib_batch_member(lbib_sim* batch, int k, lbib_sim** member);
+
+/* Lattice-kernel shape of size class size_class (0: width <= 128, 1:
+   <= 256, 2: wider; -1: all): lanes per workgroup (64, 128, 256), rows per
+   work item (-1: automatic, one resident round of the class's items) and
+   register ring depth (3 or 4); 0 keeps a value.  get_launch also returns
+   the number of members in the class, and the rows in use once the batch
+   has stepped. */
+int lbib_batch_set_launch(lbib_sim* batch, int size_class, int block_x, int seg, int ring);
+int lbib_batch_get_launch(lbib_sim* batch, int size_class, int* block_x, int* seg, int* ring,
+                          int* members);
+
+/* Graph replay on (1, the default) or off (0: direct launches); on < 0
+   leaves it.  *active (may be NULL) is 1 when the last step replayed a
+   graph. */
+int lbib_batch_graph(lbib_sim* batch, int on, int* active);
 
 #ifdef __cplusplus
 }

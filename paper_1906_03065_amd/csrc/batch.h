@@ -1,0 +1,127 @@
+// batch.h -- many independent D2Q9 simulations stepped together.
+//
+// Every phase of the step runs as one launch over all members: a persistent
+// grid walks a queue of work items (a membrane, an active tile, a marker, a
+// (strip, segment) of a lattice) spread over the members, finds the member
+// of each item by binary search over prefix sums, and runs the same device
+// code the single-simulation kernels run.  The lattice kernel runs once per
+// size class, since the strip width (lanes per workgroup) is chosen per
+// class.  All members advance with the same buffer parity.
+#pragma once
+#include "common.h"
+#include "k_ibm.h"
+#include "k_lb.h"
+
+namespace lb {
+
+constexpr int BATCH_MAX = 256;  // members per batch
+
+template <class St>
+struct BMember {
+  LBParams P;  // strips and segments for the member's size class
+  St a, b;     // population buffers (parity 0 reads a, writes b)
+  MemDev md;
+  TileMap tm;
+  CoupArgs ca;
+  double* Ifield;
+  long long* fib;
+  double* force;
+};
+
+// index i in [0, n) with pre[i] <= v < pre[i + 1]
+__device__ __forceinline__ int prefix_find(const int* pre, int n, int v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= v)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class St>
+__global__ void kb_begin(BMember<St>* T, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    int* ts = T[i].tm.tstate;
+    ts[0] = 0;
+    ts[1] = ts[1] + 1;
+  }
+}
+
+// one workgroup per (member, membrane)
+template <class St, int NT>
+__global__ __launch_bounds__(NT) void kb_tiles(const BMember<St>* T, const int2* mems) {
+  const int2 e = mems[blockIdx.x];
+  const BMember<St>& B = T[e.x];
+  tiles_run<NT>(B.md, B.tm, B.P.nx, B.P.ny, 1, B.P.wall_y, 0, 2, B.ca.r_cut + 3.0, e.y);
+}
+
+// persistent: the active tiles of all members
+template <class St, typename R, int NT>
+__global__ __launch_bounds__(NT) void kb_coupling2d(const BMember<St>* T, int n, int parity) {
+  __shared__ int s_pre[BATCH_MAX + 1];
+  for (int i = threadIdx.x; i < n; i += NT) s_pre[i + 1] = T[i].tm.tstate[0];
+  if (threadIdx.x == 0) s_pre[0] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = 0; i < n; i++) s_pre[i + 1] += s_pre[i];
+  __syncthreads();
+  const int total = s_pre[n];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int i = prefix_find(s_pre, n, item);
+    const BMember<St>& B = T[i];
+    coupling2d_tile<St, R, NT>(B.md, B.tm, B.ca, B.Ifield, parity ? B.b : B.a, item - s_pre[i]);
+  }
+}
+
+// markers of all members (mpre: marker prefix, n + 1 entries)
+template <class St>
+__global__ void kb_memforce2d(const BMember<St>* T, const int* __restrict__ mpre, int n) {
+  const int gf = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gf >= mpre[n]) return;
+  const int i = prefix_find(mpre, n, gf);
+  memforce2d_run(T[i].md, gf - mpre[i]);
+}
+
+template <class St>
+__global__ void kb_spread2d(const BMember<St>* T, const int* __restrict__ mpre, int n) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gf = tid >> 4, k = tid & 15;
+  if (gf >= mpre[n]) return;
+  const int i = prefix_find(mpre, n, gf);
+  const BMember<St>& B = T[i];
+  spread2d_run(B.md, B.fib, B.P.nx, B.P.ny, B.P.wall_y, gf - mpre[i], k);
+}
+
+template <class St, typename R>
+__global__ void kb_interp2d(const BMember<St>* T, const int* __restrict__ mpre, int n, int parity) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gf = tid >> 4, k = tid & 15;
+  const bool live = gf < mpre[n];
+  const int i = live ? prefix_find(mpre, n, gf) : 0;
+  const BMember<St>& B = T[i];
+  // after the lattice update the current state is in the buffer written
+  interp2d_run<St, R>(B.md, parity ? B.a : B.b, B.P, B.force, live ? gf - mpre[i] : 0, k, live);
+}
+
+// persistent: the (strip, segment) items of the members of one size class
+// (cm: their member ids, bpre: item prefix, ncm + 1 entries)
+template <class St, typename R, int BX, int NS, int WPE>
+__global__ __launch_bounds__(BX, WPE) void kb_lb2d(const BMember<St>* T, const int* __restrict__ cm,
+                                                   const int* __restrict__ bpre, int ncm, int parity) {
+  const int total = bpre[ncm];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int q = prefix_find(bpre, ncm, item);
+    const BMember<St>& B = T[cm[q]];
+    int strip, sgm;
+    strip_segment(item - bpre[q], B.P.nstrip, B.P.nseg, 1, strip, sgm);
+    lb2d_run<St, R, BX, NS>(parity ? B.b : B.a, parity ? B.a : B.b, B.P, strip, sgm, B.tm.tflag, B.tm.tstate,
+                            B.Ifield, B.fib, B.force);
+    __syncthreads();  // the rings are reused by the next item
+  }
+}
+
+}  // namespace lb

@@ -90,10 +90,9 @@ __global__ void k_begin(int* tstate) {
 
 // bounding box, orientation and active tiles of membrane blockIdx.x
 template <int NT>
-__global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int ny, int nz,
-                                              int wall_y, int wall_z, int D, double reach) {
+__device__ __forceinline__ void tiles_run(const MemDev& md, const TileMap& tm, int nx, int ny, int nz,
+                                          int wall_y, int wall_z, int D, double reach, int m) {
   __shared__ double sh[NT / 64];
-  const int m = blockIdx.x;
   const int tid = threadIdx.x;
   const int b = md.moff[m], e = md.moff[m + 1], n = e - b;
   const int stamp = tm.tstate[1];
@@ -134,13 +133,10 @@ __global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int
     }
   const int dims[3] = {nx, ny, nz};
   const int per[3] = {1, !wall_y, !wall_z};
-  // the periodic image of a node must be unique within the grown box; the 2D
-  // coupling kernel also needs every node of a tile in the tile centre's
-  // image (the 3D kernel searches such tiles node by node)
-  const double slack = D == 2 ? 2.0 * tm.tile : 0.0;
+  // the grown box must be narrower than the period: the band of a membrane
+  // may not reach around the lattice onto itself
   for (int a = 0; a < D; a++)
-    if (per[a] && hi[a] - lo[a] + 2.0 * reach + slack >= dims[a] && tid == 0)
-      md.status[1] = 1;
+    if (per[a] && hi[a] - lo[a] + 2.0 * reach >= dims[a] && tid == 0) md.status[1] = 1;
   int t0[3] = {0, 0, 0}, t1[3] = {0, 0, 0};
   const int nt[3] = {tm.ntx, tm.nty, tm.ntz};
   for (int a = 0; a < D; a++) {
@@ -164,6 +160,12 @@ __global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int
     const int t = (tz * tm.nty + ty) * tm.ntx + tx;
     if (atomicMax(&tm.tflag[t], stamp) < stamp) tm.tlist[atomicAdd(&tm.tstate[0], 1)] = t;
   }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int ny, int nz,
+                                              int wall_y, int wall_z, int D, double reach) {
+  tiles_run<NT>(md, tm, nx, ny, nz, wall_y, wall_z, D, reach, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -236,10 +238,18 @@ __device__ __forceinline__ bool tile_misses(const double* bx, double pxt, double
          pyt - hd > bx[4] + reach;
 }
 
-// one tile per workgroup (grid-stride over the active-tile list)
+// do the nodes of the tile starting at s (width TILE2, lattice n) fall into
+// different periodic images relative to centre c?  (the tile straddles the
+// antipode of c; its nodes are then searched one by one)
+__device__ __forceinline__ bool tile_splits(int s, int n, double c) {
+  const int e = min(s + TILE2 - 1, n - 1);
+  return near_image((double)s, c, n) - s != near_image((double)e, c, n) - e;
+}
+
+// one active tile li of the list, all NT threads of the workgroup
 template <class St, typename R, int NT>
-__global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupArgs ca,
-                                                   double* __restrict__ Ifield, St cur) {
+__device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap& tm, const CoupArgs& ca,
+                                                double* __restrict__ Ifield, const St& cur, int li) {
   __shared__ int s_cand[COUP_CHUNK];
   __shared__ float4 s_geo[COUP_CHUNK];  // candidate start point and edge, relative to the tile centre
   __shared__ float s_inv[COUP_CHUNK];   // 1 / |edge|^2
@@ -248,10 +258,9 @@ __global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupAr
   __shared__ int b_seg[COUP_KEEP][NT];
   __shared__ double b_t[COUP_KEEP][NT];
   __shared__ double b_sd[COUP_KEEP][NT];
-  const int ntl = tm.tstate[0];
   const double reach = ca.r_cut + 1.0;
   const double hd = 0.5 * TILE2 * 1.41421356237309515;
-  for (int li = blockIdx.x; li < ntl; li += gridDim.x) {
+  {
     const int t = tm.tlist[li];
     const int tx = t % tm.ntx, ty = t / tm.ntx;
     const int x = tx * TILE2 + (threadIdx.x % TILE2), y = ty * TILE2 + (threadIdx.x / TILE2);
@@ -264,7 +273,8 @@ __global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupAr
       const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
       const double pxt = near_image(xt, cx, ca.nx);
       const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
-      if (tile_misses(bx, pxt, pyt, hd, reach)) continue;
+      const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
+      if (!split && tile_misses(bx, pxt, pyt, hd, reach)) continue;
       const int b = md.moff[m], n = md.moff[m + 1] - b;
       const double* X = md.X + 3 * b;
       const double o = bx[6];
@@ -272,6 +282,38 @@ __global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupAr
       const double py = ca.wall_y ? (double)y : near_image((double)y, cy, ca.ny);
       const bool inbox = valid && px >= bx[0] - reach && px <= bx[3] + reach &&
                          py >= bx[1] - reach && py <= bx[4] + reach;
+      if (split) {
+        // nodes of different images: each one searches the whole ring
+        const int slot = kept++;
+        double d2b = 1e300, tb = 0.0;
+        int sb = -1;
+        if (inbox)
+          for (int l = 0; l < n; l++) {
+            const int l1 = (l + 1 == n) ? 0 : l + 1;
+            double tt;
+            const double d2 = seg_d2(px, py, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1], tt);
+            if (d2 < d2b) {
+              d2b = d2;
+              sb = l;
+              tb = tt;
+            }
+          }
+        double sd = 0.0;
+        bool band = false;
+        if (inbox && sb >= 0) {
+          const double d = sqrt(d2b);
+          const bool in = ring_side(X, n, o, sb, tb, px, py);
+          sd = in ? d : -d;
+          band = d <= ca.r_cut;
+          Itot += band ? 0.5 * (1.0 + tanh(sd / (2.0 * ca.alpha))) : (in ? 1.0 : 0.0);
+        }
+        if (slot < COUP_KEEP) {
+          b_seg[slot][threadIdx.x] = band ? sb : -1;
+          b_t[slot][threadIdx.x] = tb;
+          b_sd[slot][threadIdx.x] = sd;
+        }
+        continue;
+      }
       // distance of the tile centre to the ring, and its ray parity
       double dmin = 1e300;
       int cr = 0;
@@ -395,7 +437,8 @@ __global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupAr
         const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
         const double pxt = near_image(xt, cx, ca.nx);
         const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
-        if (tile_misses(bx, pxt, pyt, hd, reach)) continue;
+        const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
+        if (!split && tile_misses(bx, pxt, pyt, hd, reach)) continue;
         const int myslot = slot++;
         const int sb = b_seg[myslot][threadIdx.x];
         if (sb < 0) continue;
@@ -426,6 +469,14 @@ __global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupAr
   }
 }
 
+// one tile per workgroup (grid-stride over the active-tile list)
+template <class St, typename R, int NT>
+__global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupArgs ca,
+                                                   double* __restrict__ Ifield, St cur) {
+  const int ntl = tm.tstate[0];
+  for (int li = blockIdx.x; li < ntl; li += gridDim.x) coupling2d_tile<St, R, NT>(md, tm, ca, Ifield, cur, li);
+}
+
 // ---------------------------------------------------------------------------
 // ring strain + bending forces, gathered per marker (deterministic)
 
@@ -453,9 +504,7 @@ __device__ __forceinline__ void bend_grad(double ax, double ay, double bx, doubl
   gby = c1 * tby - c2 * by / lb;
 }
 
-__global__ void k_memforce2d(MemDev md) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= md.M) return;
+__device__ __forceinline__ void memforce2d_run(const MemDev& md, int g) {
   const int m = md.mid[g];
   const int b = md.moff[m], n = md.moff[m + 1] - b;
   const int l = g - b;
@@ -508,13 +557,16 @@ __global__ void k_memforce2d(MemDev md) {
   md.F[3 * g + 2] = 0.0;
 }
 
+__global__ void k_memforce2d(MemDev md) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < md.M) memforce2d_run(md, g);
+}
+
 // spreading, eq. Spreading with delta x = 1 (READING: no extra Delta s):
 // sixteen lanes per marker, each adds F delta_h(x - X) to one stencil node in
 // fixed point (integer sums are order independent)
-__global__ void k_spread2d(MemDev md, long long* __restrict__ fib, int nx, int ny, int wall_y) {
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int g = tid >> 4, k = tid & 15;
-  if (g >= md.M) return;
+__device__ __forceinline__ void spread2d_run(const MemDev& md, long long* __restrict__ fib, int nx, int ny,
+                                             int wall_y, int g, int k) {
   const double X = md.X[3 * g], Y = md.X[3 * g + 1];
   const double Fx = md.F[3 * g], Fy = md.F[3 * g + 1];
   const int cx = (int)floor(X) - 1 + (k & 3), cy = (int)floor(Y) - 1 + (k >> 2);
@@ -525,16 +577,21 @@ __global__ void k_spread2d(MemDev md, long long* __restrict__ fib, int nx, int n
   atomicAdd((unsigned long long*)&fib[2 * node + 1], (unsigned long long)to_fix(Fy * w));
 }
 
+__global__ void k_spread2d(MemDev md, long long* __restrict__ fib, int nx, int ny, int wall_y) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = tid >> 4, k = tid & 15;
+  if (g < md.M) spread2d_run(md, fib, nx, ny, wall_y, g, k);
+}
+
 // interpolation of v* = u(t+1) + f(t) / (2 rho(t+1)) at the stencil of X(t)
 // (eq. Interpolation, READING: the force of step t stands in for the unknown
 // force at t+1), then X(t+1) = X(t) + U (eq. UpdatedXl).  Sixteen lanes per
 // marker (one stencil node each), summed in a fixed butterfly order.
+// all sixteen lanes of a marker group must call it (live false for padding)
 template <class St, typename R>
-__global__ void k_interp2d(MemDev md, St cur, LBParams P, const double* __restrict__ force) {
+__device__ __forceinline__ void interp2d_run(const MemDev& md, const St& cur, const LBParams& P,
+                                             const double* __restrict__ force, int g, int k, bool live) {
   using L = Lattice<9>;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int g = tid >> 4, k = tid & 15;
-  const bool live = g < md.M;
   double Ux = 0, Uy = 0;
   double X = 0, Y = 0;
   if (live) {
@@ -578,6 +635,13 @@ __global__ void k_interp2d(MemDev md, St cur, LBParams P, const double* __restri
     md.X[3 * g] = X + Ux;
     md.X[3 * g + 1] = Y + Uy;
   }
+}
+
+template <class St, typename R>
+__global__ void k_interp2d(MemDev md, St cur, LBParams P, const double* __restrict__ force) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = tid >> 4, k = tid & 15;
+  interp2d_run<St, R>(md, cur, P, force, g, k, g < md.M);
 }
 
 }  // namespace lb

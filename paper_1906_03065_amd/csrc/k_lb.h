@@ -185,13 +185,12 @@ __device__ __forceinline__ void moments9(const R* pf, const R* pg, const R* ph, 
 // ring of four rows), so the loads of one row are in flight while the
 // previous rows are computed.  WPE: waves per SIMD the register budget is
 // sized for.
-template <class St, typename R, int BX, int NS, int WPE>
-__global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
-                                                  const int* __restrict__ tflag,
-                                                  const int* __restrict__ tstate,
-                                                  const double* __restrict__ Ifield,
-                                                  long long* __restrict__ fib,
-                                                  double* __restrict__ force) {
+// One (strip, segment) of the lattice: the whole march of a workgroup.
+template <class St, typename R, int BX, int NS>
+__device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBParams& P, int strip, int sgm,
+                                         const int* __restrict__ tflag, const int* __restrict__ tstate,
+                                         const double* __restrict__ Ifield, long long* __restrict__ fib,
+                                         double* __restrict__ force) {
   static_assert(NS == 3 || NS == 4, "ring of three or four rows");
   constexpr int W = BX - 4;
   __shared__ double s_m[3][3][BX];  // moment ring [slot][drho, phi, psi][lane]
@@ -199,8 +198,6 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
   __shared__ double s_u[3][3][BX];  // chemical-potential ring [slot][mu_rho, mu_phi, mu_psi'][lane]
 
   const int j = threadIdx.x;
-  int strip, sgm;
-  strip_segment((int)blockIdx.x, P.nstrip, P.nseg, P.nxcd, strip, sgm);
   const int xc = strip * W - 2 + j;
   const int x = wrap(xc, P.nx);
   const bool interior = (j >= 2) && (j < BX - 2) && (xc < P.nx);
@@ -344,6 +341,18 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
     if constexpr (NS == 4)
       if (kb + 3 < K) body(std::integral_constant<int, 3>{}, kb + 3);
   }
+}
+
+template <class St, typename R, int BX, int NS, int WPE>
+__global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
+                                                  const int* __restrict__ tflag,
+                                                  const int* __restrict__ tstate,
+                                                  const double* __restrict__ Ifield,
+                                                  long long* __restrict__ fib,
+                                                  double* __restrict__ force) {
+  int strip, sgm;
+  strip_segment((int)blockIdx.x, P.nstrip, P.nseg, P.nxcd, strip, sgm);
+  lb2d_run<St, R, BX, NS>(src, dst, P, strip, sgm, tflag, tstate, Ifield, fib, force);
 }
 
 }  // namespace lb

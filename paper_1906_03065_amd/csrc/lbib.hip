@@ -29,6 +29,7 @@
 #include "k_lb3d.h"
 #include "k_misc.h"
 #include "store.h"
+#include "batch.h"
 
 using namespace lb;
 
@@ -177,6 +178,7 @@ struct lbib_sim {
   int bx = 256, seg = 0;  // fused-kernel launch shape (seg 0: automatic)
   int nxcd = 1;           // L2 domains workgroups are dealt to (1: plain strip order)
   int ring = 3;           // rows in the fused kernel's register ring (4: prefetch)
+  lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
   // optional per-phase timing with HIP events on the stream
   int timing = 0;  // bit mask of timed phases
   std::vector<hipEvent_t> ev_pool;
@@ -230,6 +232,9 @@ struct lbib_sim {
   virtual int check(int* bad_dev) = 0;
   // per-element membrane energies (strain, bending) into out[2 * rows]
   virtual int mem_energy(double* out, long long* rows) = 0;
+  // a member's membranes or state changed (a batch rebuilds its tables)
+  virtual void mark_dirty() {}
+  virtual bool is_batch() const { return false; }
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
   MemDev memdev() const {
@@ -681,6 +686,222 @@ struct Engine3D final : lbib_sim {
   }
 };
 
+
+// Many D2Q9 simulations in one workspace, stepped together (FP32 storage).
+// Members are ordinary simulations on their own slices of the workspace;
+// the batch owns them.  Each phase of a step is one launch over all members
+// (the lattice update one launch per size class), and the whole step is
+// captured once per buffer parity in a hipGraph and replayed.
+struct BatchEngine2D final : lbib_sim {
+  using St = MixStore<9>;
+  using R = float;
+  using Mem = Engine2D<St, R>;
+  std::vector<Mem*> mem;
+  static constexpr int NCLS = 3;  // size classes by lattice width: <= 128, <= 256, larger
+  int cls_bx[NCLS] = {64, 128, 256}, cls_seg[NCLS] = {0, 0, 0}, cls_ring[NCLS] = {3, 3, 3};
+  bool use_graph = true, dirty = true, graph_ok = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  size_t off_tab = 0, off_mems = 0, off_mpre = 0, off_cm = 0, off_bpre = 0;
+  int nmems = 0, Mtot = 0, cgrid = 1;
+  int ncm[NCLS] = {0, 0, 0}, lgrid[NCLS] = {0, 0, 0}, lseg[NCLS] = {0, 0, 0};
+
+  ~BatchEngine2D() override {
+    drop_graphs();
+    for (auto m : mem) delete m;
+  }
+  void drop_graphs() {
+    for (auto& e : gexec)
+      if (e) {
+        (void)hipGraphExecDestroy(e);
+        e = nullptr;
+      }
+    graph_ok = false;
+  }
+  bool is_batch() const override { return true; }
+  void mark_dirty() override { dirty = true; }
+  void setup() override {}
+  int init(const double*) override { return LBIB_ESTATE; }
+  int moments(double*) override { return LBIB_ESTATE; }
+  int energy_nodes(double*, long long*) override { return LBIB_ESTATE; }
+  int coupling(int) override { return LBIB_ESTATE; }
+  int check(int* bad) override {
+    for (auto m : mem) {
+      int rc = m->check(bad);
+      if (rc) return rc;
+    }
+    return LBIB_OK;
+  }
+  int mem_energy(double*, long long*) override { return LBIB_ESTATE; }
+
+  static int size_class(int nx) { return nx <= 128 ? 0 : (nx <= 256 ? 1 : 2); }
+  static size_t table_bytes(int n, int kmax) {
+    return align_up((size_t)n * sizeof(BMember<St>)) + align_up((size_t)std::max(kmax, 1) * sizeof(int2)) +
+           align_up((size_t)(n + 1) * 4) + align_up((size_t)NCLS * n * 4) + align_up((size_t)NCLS * (n + 1) * 4);
+  }
+  const void* lb_kernel(int c) const {
+    const int bx = cls_bx[c];
+    if (cls_ring[c] == 4) {
+      if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 4, 2>;
+      if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 4, 2>;
+      return (const void*)&kb_lb2d<St, R, 64, 4, 2>;
+    }
+    if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 3, 3>;
+    if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 3, 3>;
+    return (const void*)&kb_lb2d<St, R, 64, 3, 3>;
+  }
+  int resident(const void* k, int threads) const {
+    int per_cu = 0, ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0) != hipSuccess || per_cu <= 0 ||
+        ncu <= 0)
+      return 1024;
+    return per_cu * ncu;
+  }
+
+  // device tables and launch plan; graph capture
+  int prepare() {
+    const int n = (int)mem.size();
+    if (n == 0) return LBIB_EINVAL;
+    for (auto m : mem)
+      if (!m->ready || m->cur != mem[0]->cur) return LBIB_ESTATE;
+    std::vector<BMember<St>> T(n);
+    std::vector<int2> mems;
+    std::vector<int> mpre(n + 1, 0), cm(NCLS * n, 0), bpre(NCLS * (n + 1), 0);
+    std::vector<int> cls(n);
+    long long rows[NCLS] = {0, 0, 0};
+    for (int i = 0; i < n; i++) {
+      cls[i] = size_class(mem[i]->p.nx);
+      const int W = cls_bx[cls[i]] - 4;
+      rows[cls[i]] += (long long)((mem[i]->p.nx + W - 1) / W) * mem[i]->p.ny;
+    }
+    for (int c = 0; c < NCLS; c++) {
+      const int slots = resident(lb_kernel(c), cls_bx[c]);
+      lseg[c] = cls_seg[c] > 0 ? cls_seg[c] : (int)std::max<long long>(4, (rows[c] + slots - 1) / slots);
+      ncm[c] = 0;
+    }
+    long long tiles = 0;
+    for (int i = 0; i < n; i++) {
+      Mem* m = mem[i];
+      const int c = cls[i];
+      BMember<St>& B = T[i];
+      B.P = m->P;
+      const int W = cls_bx[c] - 4;
+      B.P.seg = std::min(lseg[c], m->p.ny);
+      B.P.nstrip = (m->p.nx + W - 1) / W;
+      B.P.nseg = (m->p.ny + B.P.seg - 1) / B.P.seg;
+      B.P.nxcd = 1;
+      B.a = m->store(0);
+      B.b = m->store(1);
+      B.md = m->memdev();
+      B.tm = m->tilemap();
+      B.ca = m->coup_args(1);
+      B.Ifield = m->template at<double>(m->L.Ifield);
+      B.fib = m->template at<long long>(m->L.fib);
+      B.force = m->template at<double>(m->L.force);
+      for (int k = 0; k < m->K; k++) mems.push_back(make_int2(i, k));
+      mpre[i + 1] = mpre[i] + m->M;
+      tiles += m->L.ntiles * (m->K > 0);
+      const int q = ncm[c]++;
+      cm[c * n + q] = i;
+      bpre[c * (n + 1) + q + 1] = bpre[c * (n + 1) + q] + B.P.nstrip * B.P.nseg;
+    }
+    nmems = (int)mems.size();
+    Mtot = mpre[n];
+    cgrid = (int)std::max<long long>(1, std::min<long long>(tiles, 4096));
+    for (int c = 0; c < NCLS; c++) {
+      const int items = bpre[c * (n + 1) + ncm[c]];
+      lgrid[c] = std::max(1, std::min(items, resident(lb_kernel(c), cls_bx[c])));
+    }
+    hipStream_t st = stream;
+    HIPCHK(hipMemcpyAsync(ws + off_tab, T.data(), T.size() * sizeof(BMember<St>), hipMemcpyHostToDevice, st));
+    if (!mems.empty())
+      HIPCHK(hipMemcpyAsync(ws + off_mems, mems.data(), mems.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws + off_mpre, mpre.data(), mpre.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws + off_cm, cm.data(), cm.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws + off_bpre, bpre.data(), bpre.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    drop_graphs();
+    if (use_graph) {
+      graph_ok = true;
+      for (int par = 0; par < 2 && graph_ok; par++) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+          graph_ok = false;
+          break;
+        }
+        launch_all(par);
+        if (hipStreamEndCapture(st, &g) != hipSuccess || !g ||
+            hipGraphInstantiate(&gexec[par], g, nullptr, nullptr, 0) != hipSuccess)
+          graph_ok = false;
+        if (g) (void)hipGraphDestroy(g);
+      }
+      if (!graph_ok) {
+        drop_graphs();
+        (void)hipGetLastError();  // a stream that cannot be captured: launch directly
+      }
+    }
+    dirty = false;
+    return LBIB_OK;
+  }
+
+  void launch_all(int parity) {
+    const int n = (int)mem.size();
+    BMember<St>* T = at<BMember<St>>(off_tab);
+    const int* mpre = at<int>(off_mpre);
+    hipLaunchKernelGGL(kb_begin<St>, dim3((n + 63) / 64), dim3(64), 0, stream, T, n);
+    if (nmems > 0) {
+      hipLaunchKernelGGL((kb_tiles<St, 256>), dim3(nmems), dim3(256), 0, stream, (const BMember<St>*)T,
+                         (const int2*)at<int2>(off_mems));
+      hipLaunchKernelGGL((kb_coupling2d<St, R, COUP_THREADS>), dim3(cgrid), dim3(COUP_THREADS), 0, stream,
+                         (const BMember<St>*)T, n, parity);
+      hipLaunchKernelGGL(kb_memforce2d<St>, dim3((Mtot + 255) / 256), dim3(256), 0, stream,
+                         (const BMember<St>*)T, mpre, n);
+      hipLaunchKernelGGL(kb_spread2d<St>, dim3((16 * Mtot + 255) / 256), dim3(256), 0, stream,
+                         (const BMember<St>*)T, mpre, n);
+    }
+    for (int c = 0; c < NCLS; c++) {
+      if (!ncm[c]) continue;
+      const int* cmc = at<int>(off_cm) + c * n;
+      const int* bp = at<int>(off_bpre) + c * (n + 1);
+      const BMember<St>* Tc = T;
+#define KB_LAUNCH(BXV, NSV, WPEV) \
+  hipLaunchKernelGGL((kb_lb2d<St, R, BXV, NSV, WPEV>), dim3(lgrid[c]), dim3(BXV), 0, stream, Tc, cmc, bp, ncm[c], parity)
+      if (cls_ring[c] == 4) {
+        if (cls_bx[c] == 128) KB_LAUNCH(128, 4, 2);
+        else if (cls_bx[c] == 256) KB_LAUNCH(256, 4, 2);
+        else KB_LAUNCH(64, 4, 2);
+      } else {
+        if (cls_bx[c] == 128) KB_LAUNCH(128, 3, 3);
+        else if (cls_bx[c] == 256) KB_LAUNCH(256, 3, 3);
+        else KB_LAUNCH(64, 3, 3);
+      }
+#undef KB_LAUNCH
+    }
+    if (nmems > 0)
+      hipLaunchKernelGGL((kb_interp2d<St, R>), dim3((16 * Mtot + 255) / 256), dim3(256), 0, stream,
+                         (const BMember<St>*)T, mpre, n, parity);
+  }
+
+  int step() override {
+    if (dirty) {
+      int rc = prepare();
+      if (rc) return rc;
+    }
+    const int parity = mem[0]->cur;
+    if (graph_ok) {
+      if (hipGraphLaunch(gexec[parity], stream) != hipSuccess) return LBIB_EHIP;
+    } else {
+      launch_all(parity);
+    }
+    for (auto m : mem) {
+      m->cur = 1 - m->cur;
+      m->steps++;
+    }
+    return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+};
+
 lbib_sim* make_engine(const lbib_params* p) {
   if (p->lattice == LBIB_D2Q9) {
     switch (p->storage) {
@@ -759,25 +980,10 @@ int mesh_topology(int n, int nt, const int* tri, MeshTopo& mt) {
 
 }  // namespace
 
-// C ABI
-extern "C" {
+namespace {
 
-int lbib_workspace_bytes(const lbib_params* p, size_t* bytes) {
-  int rc = validate(p);
-  if (rc) return rc;
-  if (!bytes) return LBIB_EINVAL;
-  *bytes = make_layout(p).total;
-  return LBIB_OK;
-}
-
-int lbib_create(const lbib_params* p, void* ws, size_t ws_bytes, void* stream, lbib_sim** out) {
-  int rc = validate(p);
-  if (rc) return rc;
-  if (!ws || !out || ((uintptr_t)ws % kAlign) != 0) return LBIB_EINVAL;
-  Layout L = make_layout(p);
-  if (ws_bytes < L.total) return LBIB_ENOMEM;
-  lbib_sim* s = make_engine(p);
-  if (!s) return LBIB_ENOMEM;
+// common set-up of a simulation object on its workspace
+int init_sim(lbib_sim* s, const lbib_params* p, const Layout& L, char* ws, hipStream_t stream) {
   s->p = *p;
   s->L = L;
   s->ws = (char*)ws;
@@ -797,16 +1003,45 @@ int lbib_create(const lbib_params* p, void* ws, size_t ws_bytes, void* stream, l
       hipMemsetAsync(s->ws + L.Facc, 0, (size_t)std::max(p->max_markers, 1) * 3 * 8, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.status, 0, 64, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.force, 0, (size_t)s->N * s->D * 8, st) != hipSuccess ||
-      hipMemsetAsync(s->ws + L.moff, 0, 4, st) != hipSuccess) {
-    delete s;
+      hipMemsetAsync(s->ws + L.moff, 0, 4, st) != hipSuccess)
     return LBIB_EHIP;
+  return LBIB_OK;
+}
+
+}  // namespace
+
+// C ABI
+extern "C" {
+
+int lbib_workspace_bytes(const lbib_params* p, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) return LBIB_EINVAL;
+  *bytes = make_layout(p).total;
+  return LBIB_OK;
+}
+
+int lbib_create(const lbib_params* p, void* ws, size_t ws_bytes, void* stream, lbib_sim** out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!ws || !out || ((uintptr_t)ws % kAlign) != 0) return LBIB_EINVAL;
+  Layout L = make_layout(p);
+  if (ws_bytes < L.total) return LBIB_ENOMEM;
+  lbib_sim* s = make_engine(p);
+  if (!s) return LBIB_ENOMEM;
+  rc = init_sim(s, p, L, (char*)ws, (hipStream_t)stream);
+  if (rc) {
+    delete s;
+    return rc;
   }
   *out = s;
   return LBIB_OK;
 }
 
+
 int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const int* conn, double ks,
                       double kb, int* id) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || !X || n < 3) return LBIB_EINVAL;
   if (s->ready) return LBIB_ESTATE;
   if (s->D == 2 && (n_elems != 0 || conn)) return LBIB_EINVAL;
@@ -896,11 +1131,13 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
   if (id) *id = s->K;
   s->K += 1;
   s->M += n;
+  if (s->owner) s->owner->mark_dirty();
   return LBIB_OK;
 }
 
 int lbib_set_fields(lbib_sim* s, const double* rho, const double* phi, const double* psi,
                     const double* ux, const double* uy, const double* uz) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || !rho || !phi || !psi) return LBIB_EINVAL;
   const long long N = s->N;
   for (long long n = 0; n < N; n++)
@@ -930,12 +1167,13 @@ int lbib_set_fields(lbib_sim* s, const double* rho, const double* phi, const dou
   HIPCHK(hipStreamSynchronize(st));
   s->ready = true;
   s->steps = 0;
+  if (s->owner) s->owner->mark_dirty();
   return LBIB_OK;
 }
 
 int lbib_step(lbib_sim* s, int n) {
   if (!s || n < 0) return LBIB_EINVAL;
-  if (!s->ready) return LBIB_ESTATE;
+  if (!s->ready || s->owner) return LBIB_ESTATE;  // batch members step with their batch
   for (int k = 0; k < n; k++) {
     int rc = s->step();
     if (rc) return rc;
@@ -947,6 +1185,7 @@ int lbib_step(lbib_sim* s, int n) {
 long long lbib_steps_done(const lbib_sim* s) { return s ? s->steps : -1; }
 
 int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   if (ring != 0 && ring != 3 && ring != 4) return LBIB_EINVAL;
   if (ring) s->ring = ring;
@@ -960,6 +1199,7 @@ int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
 }
 
 int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* ring) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   if (ring) *ring = s->ring;
   if (block_x) *block_x = s->bx;
@@ -969,6 +1209,7 @@ int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* r
 }
 
 int lbib_timing_enable(lbib_sim* s, int on) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   int rc = s->timing_flush();
   if (rc) return rc;
@@ -979,6 +1220,7 @@ int lbib_timing_enable(lbib_sim* s, int on) {
 }
 
 int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || n < 0 || n > 4 || (n > 0 && !ms)) return LBIB_EINVAL;
   int rc = s->timing_flush();
   if (rc) return rc;
@@ -989,6 +1231,7 @@ int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps) {
 
 int lbib_get_fields(lbib_sim* s, double* rho, double* c1, double* c2, double* c3, double* ux,
                     double* uy, double* uz) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   if (!s->ready) return LBIB_ESTATE;
   double* stage = s->at<double>(s->L.stage);
@@ -1003,6 +1246,7 @@ int lbib_get_fields(lbib_sim* s, double* rho, double* c1, double* c2, double* c3
 }
 
 int lbib_get_membrane(lbib_sim* s, int id, double* X, double* U, double* F) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || id < 0 || id >= s->K) return LBIB_EINVAL;
   const int b = s->moff[id], n = s->moff[id + 1] - b;
   std::vector<double> buf((size_t)3 * n);
@@ -1019,6 +1263,7 @@ int lbib_get_membrane(lbib_sim* s, int id, double* X, double* U, double* F) {
 }
 
 int lbib_energy(lbib_sim* s, lbib_energies* out) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || !out) return LBIB_EINVAL;
   if (!s->ready) return LBIB_ESTATE;
   double* stage = s->at<double>(s->L.stage);
@@ -1060,6 +1305,13 @@ int lbib_energy(lbib_sim* s, lbib_energies* out) {
 
 int lbib_check(lbib_sim* s) {
   if (!s) return LBIB_EINVAL;
+  if (s->is_batch()) {
+    for (auto m : static_cast<BatchEngine2D*>(s)->mem) {
+      int rc = lbib_check(m);
+      if (rc) return rc;
+    }
+    return LBIB_OK;
+  }
   if (!s->ready) return LBIB_ESTATE;
   int* st = s->at<int>(s->L.status);
   HIPCHK(hipMemsetAsync(st + 8, 0, 4, s->stream));
@@ -1074,6 +1326,7 @@ int lbib_check(lbib_sim* s) {
 }
 
 int lbib_device_view(lbib_sim* s, int field, void** ptr, size_t* elems) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || !ptr || !elems) return LBIB_EINVAL;
   switch (field) {
     case 0:
@@ -1093,6 +1346,7 @@ int lbib_device_view(lbib_sim* s, int field, void** ptr, size_t* elems) {
 }
 
 int lbib_save(lbib_sim* s, void* buf, size_t* bytes) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || !bytes) return LBIB_EINVAL;
   if (!s->ready) return LBIB_ESTATE;
   const size_t need = 16 + s->L.pop_bytes + (size_t)s->M * 24 * 3;
@@ -1115,6 +1369,7 @@ int lbib_save(lbib_sim* s, void* buf, size_t* bytes) {
 }
 
 int lbib_load(lbib_sim* s, const void* buf, size_t bytes) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || !buf) return LBIB_EINVAL;
   const size_t need = 16 + s->L.pop_bytes + (size_t)s->M * 24 * 3;
   if (bytes < need) return LBIB_EINVAL;
@@ -1130,10 +1385,12 @@ int lbib_load(lbib_sim* s, const void* buf, size_t bytes) {
   HIPCHK(hipStreamSynchronize(s->stream));
   s->steps = hdr[0];
   s->ready = true;
+  if (s->owner) s->owner->mark_dirty();
   return LBIB_OK;
 }
 
 int lbib_debug_poke(lbib_sim* s, int field, long long idx, double value) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   if (field == 2) {
     if (idx < 0 || idx >= (long long)s->M * 3) return LBIB_EINVAL;
@@ -1178,6 +1435,119 @@ const char* lbib_strerror(int status) {
   return "unknown status";
 }
 
-void lbib_destroy(lbib_sim* s) { delete s; }
+void lbib_destroy(lbib_sim* s) {
+  if (s && !s->owner) delete s;  // batch members are destroyed with their batch
+}
+
+// ---------------------------------------------------------------------------
+// batches of D2Q9 simulations
+
+int lbib_batch_workspace_bytes(int n, const lbib_params* params, size_t* bytes) {
+  if (n < 1 || n > BATCH_MAX || !params || !bytes) return LBIB_EINVAL;
+  size_t tot = 0;
+  int kmax = 0;
+  for (int i = 0; i < n; i++) {
+    int rc = validate(&params[i]);
+    if (rc) return rc;
+    if (params[i].lattice != LBIB_D2Q9 || params[i].storage != LBIB_FP32) return LBIB_EINVAL;
+    tot += align_up(make_layout(&params[i]).total);
+    kmax += params[i].max_membranes;
+  }
+  *bytes = BatchEngine2D::table_bytes(n, kmax) + tot;
+  return LBIB_OK;
+}
+
+int lbib_batch_create(int n, const lbib_params* params, void* ws, size_t ws_bytes, void* stream,
+                      lbib_sim** out) {
+  size_t need = 0;
+  int rc = lbib_batch_workspace_bytes(n, params, &need);
+  if (rc) return rc;
+  if (!ws || !out || ((uintptr_t)ws % kAlign) != 0) return LBIB_EINVAL;
+  if (ws_bytes < need) return LBIB_ENOMEM;
+  int kmax = 0;
+  for (int i = 0; i < n; i++) kmax += params[i].max_membranes;
+  BatchEngine2D* b = new (std::nothrow) BatchEngine2D();
+  if (!b) return LBIB_ENOMEM;
+  b->p = params[0];
+  b->ws = (char*)ws;
+  b->stream = (hipStream_t)stream;
+  b->ready = true;
+  b->off_tab = 0;
+  b->off_mems = align_up((size_t)n * sizeof(BMember<BatchEngine2D::St>));
+  b->off_mpre = b->off_mems + align_up((size_t)std::max(kmax, 1) * sizeof(int2));
+  b->off_cm = b->off_mpre + align_up((size_t)(n + 1) * 4);
+  b->off_bpre = b->off_cm + align_up((size_t)BatchEngine2D::NCLS * n * 4);
+  size_t off = BatchEngine2D::table_bytes(n, kmax);
+  for (int i = 0; i < n; i++) {
+    Layout L = make_layout(&params[i]);
+    BatchEngine2D::Mem* m = new (std::nothrow) BatchEngine2D::Mem();
+    if (!m) {
+      delete b;
+      return LBIB_ENOMEM;
+    }
+    rc = init_sim(m, &params[i], L, (char*)ws + off, (hipStream_t)stream);
+    m->owner = b;
+    b->mem.push_back(m);
+    if (rc) {
+      delete b;
+      return rc;
+    }
+    off += align_up(L.total);
+  }
+  *out = b;
+  return LBIB_OK;
+}
+
+int lbib_batch_member(lbib_sim* batch, int k, lbib_sim** member) {
+  if (!batch || !batch->is_batch() || !member) return LBIB_EINVAL;
+  BatchEngine2D* b = static_cast<BatchEngine2D*>(batch);
+  if (k < 0 || k >= (int)b->mem.size()) return LBIB_EINVAL;
+  *member = b->mem[k];
+  return LBIB_OK;
+}
+
+int lbib_batch_set_launch(lbib_sim* batch, int size_class, int block_x, int seg, int ring) {
+  if (!batch || !batch->is_batch()) return LBIB_EINVAL;
+  if (size_class < -1 || size_class >= BatchEngine2D::NCLS) return LBIB_EINVAL;
+  if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 256) return LBIB_EINVAL;
+  if (ring != 0 && ring != 3 && ring != 4) return LBIB_EINVAL;
+  if (seg < -1) return LBIB_EINVAL;
+  BatchEngine2D* b = static_cast<BatchEngine2D*>(batch);
+  for (int c = 0; c < BatchEngine2D::NCLS; c++) {
+    if (size_class >= 0 && c != size_class) continue;
+    if (block_x) b->cls_bx[c] = block_x;
+    if (ring) b->cls_ring[c] = ring;
+    if (seg > 0) b->cls_seg[c] = seg;
+    if (seg < 0) b->cls_seg[c] = 0;
+  }
+  b->dirty = true;
+  return LBIB_OK;
+}
+
+int lbib_batch_get_launch(lbib_sim* batch, int size_class, int* block_x, int* seg, int* ring, int* members) {
+  if (!batch || !batch->is_batch()) return LBIB_EINVAL;
+  if (size_class < 0 || size_class >= BatchEngine2D::NCLS) return LBIB_EINVAL;
+  BatchEngine2D* b = static_cast<BatchEngine2D*>(batch);
+  if (block_x) *block_x = b->cls_bx[size_class];
+  if (ring) *ring = b->cls_ring[size_class];
+  if (seg) *seg = b->dirty ? b->cls_seg[size_class] : b->lseg[size_class];
+  if (members) {
+    int c = 0;
+    for (auto m : b->mem) c += BatchEngine2D::size_class(m->p.nx) == size_class;
+    *members = c;
+  }
+  return LBIB_OK;
+}
+
+int lbib_batch_graph(lbib_sim* batch, int on, int* active) {
+  if (!batch || !batch->is_batch()) return LBIB_EINVAL;
+  BatchEngine2D* b = static_cast<BatchEngine2D*>(batch);
+  if (on >= 0) {
+    b->use_graph = on != 0;
+    b->dirty = true;
+  }
+  if (active) *active = (!b->dirty && b->graph_ok) ? 1 : 0;
+  return LBIB_OK;
+}
 
 }  // extern "C"

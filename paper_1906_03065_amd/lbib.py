@@ -18,6 +18,7 @@ D2Q9, D3Q19 = 0, 1
 FP32, FP16, BF16, FP64 = 0, 1, 2, 3
 STORAGE = {"fp32": FP32, "fp16": FP16, "bf16": BF16, "fp64": FP64}
 
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 STATUS = {0: "LBIB_OK", -1: "LBIB_EINVAL", -2: "LBIB_ENOMEM", -3: "LBIB_EHIP",
           -4: "LBIB_ENONFINITE", -5: "LBIB_EUNSTABLE", -6: "LBIB_ESTATE"}
 
@@ -71,6 +72,12 @@ SIGNATURES = [
     ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
     ("lbib_strerror", C.c_char_p, [C.c_int]),
     ("lbib_destroy", None, [_vp]),
+    ("lbib_batch_workspace_bytes", C.c_int, [C.c_int, _vp, C.POINTER(C.c_size_t)]),
+    ("lbib_batch_create", C.c_int, [C.c_int, _vp, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    ("lbib_batch_member", C.c_int, [_vp, C.c_int, C.POINTER(_vp)]),
+    ("lbib_batch_set_launch", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("lbib_batch_get_launch", C.c_int, [_vp, C.c_int, _ip, _ip, _ip, _ip]),
+    ("lbib_batch_graph", C.c_int, [_vp, C.c_int, _ip]),
 ]
 
 
@@ -151,7 +158,28 @@ class Sim:
         self.h = h
         self.mem_sizes = []
 
+    @classmethod
+    def _member(cls, batch, h, p: dict):
+        """Wrap member handle h of a Batch (owned by the batch)."""
+        self = cls.__new__(cls)
+        self.torch = batch.torch
+        self.p = dict(p)
+        self.prm = None
+        self.D = 2
+        self.shape = (int(p["ny"]), int(p["nx"]))
+        self.N = int(np.prod(self.shape))
+        self.device = batch.device
+        self.ws = None
+        self.stream = batch.stream
+        self.h = h
+        self.mem_sizes = []
+        self.owner = batch
+        return self
+
     def close(self):
+        if getattr(self, "owner", None) is not None:
+            self.h = None  # freed with its batch
+            return
         if getattr(self, "h", None):
             lib().lbib_destroy(self.h)
             self.h = None
@@ -258,6 +286,90 @@ class Sim:
         ptr, n = _vp(), C.c_size_t(0)
         _chk("lbib_device_view", lib().lbib_device_view(self.h, field, C.byref(ptr), C.byref(n)))
         return ptr.value, n.value
+
+
+class Batch:
+    """n independent D2Q9 simulations (FP32) stepped together: one launch
+    per phase over all members, the step replayed from a hipGraph.  The
+    batch runs on its own (capturable) stream unless one is given."""
+
+    def __init__(self, params: list, membranes: list = None, device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        n = len(params)
+        membranes = membranes or [()] * n
+        arr = (Params * n)(*[make_params(p, "fp32", membranes=m) for p, m in zip(params, membranes)])
+        self._prms = arr
+        nb = C.c_size_t(0)
+        _chk("lbib_batch_workspace_bytes", lib().lbib_batch_workspace_bytes(n, C.byref(arr), C.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        h = _vp()
+        _chk("lbib_batch_create", lib().lbib_batch_create(n, C.byref(arr), _vp(self.ws.data_ptr()), nb.value,
+                                                          _vp(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.members = []
+        for k in range(n):
+            mh = _vp()
+            _chk("lbib_batch_member", lib().lbib_batch_member(self.h, k, C.byref(mh)))
+            self.members.append(Sim._member(self, mh, params[k]))
+
+    def __len__(self):
+        return len(self.members)
+
+    def __getitem__(self, k) -> Sim:
+        return self.members[k]
+
+    def step(self, n=1):
+        _chk("lbib_step", lib().lbib_step(self.h, int(n)))
+
+    def check(self) -> int:
+        return lib().lbib_check(self.h)
+
+    def set_launch(self, size_class=-1, block_x=0, seg=0, ring=0):
+        _chk("lbib_batch_set_launch", lib().lbib_batch_set_launch(self.h, int(size_class), int(block_x),
+                                                                  int(seg), int(ring)))
+
+    def get_launch(self, size_class: int) -> dict:
+        a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        _chk("lbib_batch_get_launch", lib().lbib_batch_get_launch(self.h, int(size_class), C.byref(a),
+                                                                  C.byref(b), C.byref(c), C.byref(d)))
+        return {"block_x": a.value, "seg": b.value, "ring": c.value, "members": d.value}
+
+    def graph(self, on: int = -1) -> int:
+        """Switch graph replay on (1) or off (0); returns whether the last
+        step replayed a graph."""
+        a = C.c_int(0)
+        _chk("lbib_batch_graph", lib().lbib_batch_graph(self.h, int(on), C.byref(a)))
+        return a.value
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "h", None):
+            for m in self.members:
+                m.h = None
+            lib().lbib_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @classmethod
+    def from_workloads(cls, ws: list, device="cuda:0", stream=None) -> "Batch":
+        b = cls([w["params"] for w in ws], [w["membranes"] for w in ws], device=device, stream=stream)
+        for m, w in zip(b.members, ws):
+            for mem in w["membranes"]:
+                m.add_membrane(mem["X"], mem.get("tris"), mem["kappa_s"], mem["kappa_b"])
+            f = w["fields"]
+            m.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
+        return b
 
 
 def from_workload(w: dict, storage="fp32", device="cuda:0", **kw) -> Sim:

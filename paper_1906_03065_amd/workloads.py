@@ -297,6 +297,17 @@ def drop3d(nx=24, ny=22, nz=20, R=6.0, wall_y=0, wall_z=1, kappa=(0.02, 0.03, 0.
                 name=f"drop3d_{nx}x{ny}x{nz}")
 
 
+def sphere3d(n=64, R=16.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1):
+    """D3Q19 n^3, periodic: a C3 sphere of radius R centred in C1 (no C2)."""
+    p = base_params(n, n, n, lattice=1, wall_y=0, wall_z=0, kappa=kappa, alpha=alpha, kappa_c=0.0,
+                    mobility=mobility)
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64),) * 3, indexing="ij")
+    c = (n - 1) / 2.0
+    C3 = tanh_profile(R - np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2), alpha)
+    return dict(params=p, fields=fields_from_C(1.0 - C3, np.zeros_like(C3), C3), membranes=[],
+                name=f"sphere3d_{n}")
+
+
 def lens3d(n=64, R=16.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_z=1):
     """D3Q19 n^3: a C3 sphere centred on a flat C1/C2 interface at
     z0 = (n-1)/2 (C1 below, C2 above), periodic in x and y."""

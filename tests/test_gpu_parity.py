@@ -155,3 +155,23 @@ def test_c2_fullsize_fp32_vs_oracle(orc):
     for k, v in errs.items():
         assert v <= 1e-5, (k, v)
     assert marker_err(g, o, 16) < 1e-6
+
+
+@pytest.mark.parametrize("wall_y", [1, 0])
+def test_fp64_parity_band_near_period(orc, wall_y):
+    """Capsule band (r_cut + 3 around the ring) nearly as wide as the
+    periodic lattice: tiles that straddle the antipode of the capsule hold
+    nodes of two periodic images and are searched node by node."""
+    w = W.capsule_at_interface(nx=80, ny=82, R=18.5, n_markers=144, centre=(37.3, 40.2),
+                               wall_y=wall_y, seed=9)
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    for n in (1, 30):
+        o.step(n - o.steps_done)
+        g.step(n - g.steps_done)
+        errs = compare(g, o)
+        _report(f"fp64 band near period wall={wall_y} step {n}", errs)
+        for k, v in errs.items():
+            assert v < 1e-9, (n, k, v)
+        assert marker_err(g, o, 1) < 1e-9
+    assert g.check() == 0
