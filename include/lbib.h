@@ -97,6 +97,14 @@ int lbib_create(const lbib_params* p, void* dev_workspace, size_t ws_bytes, void
 int lbib_add_membrane(lbib_sim* s, int n_nodes, const double* X, int n_elems, const int* conn,
                       double kappa_s, double kappa_b, int* membrane_id);
 
+/* Replace the rest lengths of membrane id (host array): 2D, one per
+   segment l -> l+1 in marker order; 3D, one per mesh edge, edges ordered by
+   (smaller vertex index, larger vertex index).  By default the rest lengths
+   are those of the configuration given to lbib_add_membrane (the reference
+   state of the strain energy, eq. DiscreteSE).  LBIB_EINVAL for a length
+   that is not positive and finite. */
+int lbib_set_rest(lbib_sim* s, int id, const double* rest);
+
 /* Initial macroscopic fields (host, N doubles each; uz may be NULL in 2D and
    ux, uy may be NULL for a fluid at rest).  Builds the equilibrium
    populations of eq. EDF, with the chemical potentials of Appendix A taken
@@ -218,6 +226,38 @@ int lbib_batch_get_launch(lbib_sim* batch, int size_class, int* block_x, int* se
    leaves it.  *active (may be NULL) is 1 when the last step replayed a
    graph. */
 int lbib_batch_graph(lbib_sim* batch, int on, int* active);
+
+/* ------------------------------------------------------------------------
+   Warm-start network (not part of the paper's method: a learned initial
+   guess of a 2D capsule's equilibrium shape; the plain cold start stays the
+   reference).  A fully connected FP32 map 6 -> 128 -> 128 -> 32 with GELU
+   (z Phi(z), Phi by erff) after both hidden layers; parameters in one array
+   of lbib_mlp_param_count() floats: W1 [128][6], b1 [128], W2 [128][128],
+   b2 [128], W3 [32][128], b3 [32] (row-major, output index first).  Inputs
+   x [B][6] and targets t [B][32] are device arrays; the loss is
+   sum (y - t)^2 / (2 B).  Training is deterministic (fixed-order sums).
+   ------------------------------------------------------------------------ */
+typedef struct lbib_mlp lbib_mlp;
+
+int lbib_mlp_param_count(void);
+/* Device bytes for batches of up to batch_max rows. */
+int lbib_mlp_workspace_bytes(int batch_max, size_t* bytes);
+int lbib_mlp_create(int batch_max, void* dev_workspace, size_t ws_bytes, void* hip_stream, lbib_mlp** out);
+/* Host parameter arrays; set_params also clears the Adam moments and step
+   count.  LBIB_EINVAL for non-finite values. */
+int lbib_mlp_set_params(lbib_mlp* h, const float* host_params);
+int lbib_mlp_get_params(lbib_mlp* h, float* host_params);
+/* y_dev [B][32] = network(x_dev [B][6]), 1 <= B <= batch_max; enqueued. */
+int lbib_mlp_forward(lbib_mlp* h, const float* x_dev, int B, float* y_dev);
+/* Loss (may be NULL) and its gradient with respect to the parameters
+   (host array, may be NULL); synchronises when either is asked for. */
+int lbib_mlp_gradient(lbib_mlp* h, const float* x_dev, const float* t_dev, int B, double* loss,
+                      float* grad_host);
+/* One Adam step (bias-corrected moments) on the batch; loss (may be NULL)
+   is that of the parameters before the step. */
+int lbib_mlp_adam_step(lbib_mlp* h, const float* x_dev, const float* t_dev, int B, float lr, float beta1,
+                       float beta2, float eps, double* loss);
+void lbib_mlp_destroy(lbib_mlp* h);
 
 #ifdef __cplusplus
 }

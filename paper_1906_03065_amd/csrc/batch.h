@@ -28,6 +28,10 @@ struct BMember {
   double* force;
 };
 
+// The member descriptors live in global memory; every kernel copies the one
+// it works on into registers first, so the stores of the step cannot be
+// taken to alias it (which would force a reload after each store).
+
 // index i in [0, n) with pre[i] <= v < pre[i + 1]
 __device__ __forceinline__ int prefix_find(const int* pre, int n, int v) {
   int lo = 0, hi = n - 1;
@@ -55,8 +59,11 @@ __global__ void kb_begin(BMember<St>* T, int n) {
 template <class St, int NT>
 __global__ __launch_bounds__(NT) void kb_tiles(const BMember<St>* T, const int2* mems) {
   const int2 e = mems[blockIdx.x];
-  const BMember<St>& B = T[e.x];
-  tiles_run<NT>(B.md, B.tm, B.P.nx, B.P.ny, 1, B.P.wall_y, 0, 2, B.ca.r_cut + 3.0, e.y);
+  const MemDev md = T[e.x].md;
+  const TileMap tm = T[e.x].tm;
+  const LBParams P = T[e.x].P;
+  const double rc = T[e.x].ca.r_cut;
+  tiles_run<NT>(md, tm, P.nx, P.ny, 1, P.wall_y, 0, 2, rc + 3.0, e.y);
 }
 
 // persistent: the active tiles of all members
@@ -72,8 +79,12 @@ __global__ __launch_bounds__(NT) void kb_coupling2d(const BMember<St>* T, int n,
   const int total = s_pre[n];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int i = prefix_find(s_pre, n, item);
-    const BMember<St>& B = T[i];
-    coupling2d_tile<St, R, NT>(B.md, B.tm, B.ca, B.Ifield, parity ? B.b : B.a, item - s_pre[i]);
+    const MemDev md = T[i].md;
+    const TileMap tm = T[i].tm;
+    const CoupArgs ca = T[i].ca;
+    double* Ifield = T[i].Ifield;
+    const St cur = parity ? T[i].b : T[i].a;
+    coupling2d_tile<St, R, NT>(md, tm, ca, Ifield, cur, item - s_pre[i]);
   }
 }
 
@@ -83,7 +94,8 @@ __global__ void kb_memforce2d(const BMember<St>* T, const int* __restrict__ mpre
   const int gf = blockIdx.x * blockDim.x + threadIdx.x;
   if (gf >= mpre[n]) return;
   const int i = prefix_find(mpre, n, gf);
-  memforce2d_run(T[i].md, gf - mpre[i]);
+  const MemDev md = T[i].md;
+  memforce2d_run(md, gf - mpre[i]);
 }
 
 template <class St>
@@ -92,8 +104,10 @@ __global__ void kb_spread2d(const BMember<St>* T, const int* __restrict__ mpre, 
   const int gf = tid >> 4, k = tid & 15;
   if (gf >= mpre[n]) return;
   const int i = prefix_find(mpre, n, gf);
-  const BMember<St>& B = T[i];
-  spread2d_run(B.md, B.fib, B.P.nx, B.P.ny, B.P.wall_y, gf - mpre[i], k);
+  const MemDev md = T[i].md;
+  long long* fib = T[i].fib;
+  const int nx = T[i].P.nx, ny = T[i].P.ny, wy = T[i].P.wall_y;
+  spread2d_run(md, fib, nx, ny, wy, gf - mpre[i], k);
 }
 
 template <class St, typename R>
@@ -102,9 +116,12 @@ __global__ void kb_interp2d(const BMember<St>* T, const int* __restrict__ mpre, 
   const int gf = tid >> 4, k = tid & 15;
   const bool live = gf < mpre[n];
   const int i = live ? prefix_find(mpre, n, gf) : 0;
-  const BMember<St>& B = T[i];
+  const MemDev md = T[i].md;
+  const LBParams P = T[i].P;
+  const double* force = T[i].force;
   // after the lattice update the current state is in the buffer written
-  interp2d_run<St, R>(B.md, parity ? B.a : B.b, B.P, B.force, live ? gf - mpre[i] : 0, k, live);
+  const St cur = parity ? T[i].a : T[i].b;
+  interp2d_run<St, R>(md, cur, P, force, live ? gf - mpre[i] : 0, k, live);
 }
 
 // persistent: the (strip, segment) items of the members of one size class
@@ -115,11 +132,17 @@ __global__ __launch_bounds__(BX, WPE) void kb_lb2d(const BMember<St>* T, const i
   const int total = bpre[ncm];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int q = prefix_find(bpre, ncm, item);
-    const BMember<St>& B = T[cm[q]];
+    const int i = cm[q];
+    const LBParams P = T[i].P;
+    const St src = parity ? T[i].b : T[i].a, dst = parity ? T[i].a : T[i].b;
+    const int* tflag = T[i].tm.tflag;
+    const int* tstate = T[i].tm.tstate;
+    const double* Ifield = T[i].Ifield;
+    long long* fib = T[i].fib;
+    double* force = T[i].force;
     int strip, sgm;
-    strip_segment(item - bpre[q], B.P.nstrip, B.P.nseg, 1, strip, sgm);
-    lb2d_run<St, R, BX, NS>(parity ? B.b : B.a, parity ? B.a : B.b, B.P, strip, sgm, B.tm.tflag, B.tm.tstate,
-                            B.Ifield, B.fib, B.force);
+    strip_segment(item - bpre[q], P.nstrip, P.nseg, 1, strip, sgm);
+    lb2d_run<St, R, BX, NS>(src, dst, P, strip, sgm, tflag, tstate, Ifield, fib, force);
     __syncthreads();  // the rings are reused by the next item
   }
 }

@@ -30,6 +30,7 @@
 #include "k_misc.h"
 #include "store.h"
 #include "batch.h"
+#include "k_mlp.h"
 
 using namespace lb;
 
@@ -745,9 +746,11 @@ struct BatchEngine2D final : lbib_sim {
       if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 4, 2>;
       return (const void*)&kb_lb2d<St, R, 64, 4, 2>;
     }
-    if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 3, 3>;
-    if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 3, 3>;
-    return (const void*)&kb_lb2d<St, R, 64, 3, 3>;
+    // (the persistent loop needs a few more registers than the single
+    // kernel: ring 3 runs at two waves per SIMD too, without spills)
+    if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 3, 2>;
+    if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 3, 2>;
+    return (const void*)&kb_lb2d<St, R, 64, 3, 2>;
   }
   int resident(const void* k, int threads) const {
     int per_cu = 0, ncu = 0, dev = 0;
@@ -872,9 +875,9 @@ struct BatchEngine2D final : lbib_sim {
         else if (cls_bx[c] == 256) KB_LAUNCH(256, 4, 2);
         else KB_LAUNCH(64, 4, 2);
       } else {
-        if (cls_bx[c] == 128) KB_LAUNCH(128, 3, 3);
-        else if (cls_bx[c] == 256) KB_LAUNCH(256, 3, 3);
-        else KB_LAUNCH(64, 3, 3);
+        if (cls_bx[c] == 128) KB_LAUNCH(128, 3, 2);
+        else if (cls_bx[c] == 256) KB_LAUNCH(256, 3, 2);
+        else KB_LAUNCH(64, 3, 2);
       }
 #undef KB_LAUNCH
     }
@@ -1132,6 +1135,25 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
   s->K += 1;
   s->M += n;
   if (s->owner) s->owner->mark_dirty();
+  return LBIB_OK;
+}
+
+int lbib_set_rest(lbib_sim* s, int id, const double* rest) {
+  if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
+  if (!s || !rest || id < 0 || id >= s->K) return LBIB_EINVAL;
+  hipStream_t st = s->stream;
+  if (s->D == 2) {
+    const int b = s->moff[id], n = s->moff[id + 1] - b;
+    for (int l = 0; l < n; l++)
+      if (!(rest[l] > 0) || !std::isfinite(rest[l])) return LBIB_EINVAL;
+    HIPCHK(hipMemcpyAsync(s->ws + s->L.rest + (size_t)b * 8, rest, (size_t)n * 8, hipMemcpyHostToDevice, st));
+  } else {
+    const int b = s->eoff[id], n = s->eoff[id + 1] - b;
+    for (int e = 0; e < n; e++)
+      if (!(rest[e] > 0) || !std::isfinite(rest[e])) return LBIB_EINVAL;
+    HIPCHK(hipMemcpyAsync(s->ws + s->L.erest + (size_t)b * 8, rest, (size_t)n * 8, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
   return LBIB_OK;
 }
 
@@ -1549,5 +1571,213 @@ int lbib_batch_graph(lbib_sim* batch, int on, int* active) {
   if (active) *active = (!b->dirty && b->graph_ok) ? 1 : 0;
   return LBIB_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// warm-start network
+struct lbib_mlp {
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int bmax = 0;
+  long long t = 0;  // Adam steps taken
+  size_t off_p, off_g, off_m, off_v, off_z1, off_a1, off_z2, off_a2, off_y, off_dy, off_d1, off_d2, off_part;
+  template <typename T>
+  T* at(size_t o) const { return reinterpret_cast<T*>(ws + o); }
+};
+
+namespace {
+
+size_t mlp_layout(lbib_mlp* h, int B) {
+  Carver c{nullptr};
+  const size_t np = (size_t)MLP_NPARAM * 4;
+  const size_t o_p = c.take(np), o_g = c.take(np), o_m = c.take(np), o_v = c.take(np);
+  const size_t hid = (size_t)B * MLP_H * 4, out = (size_t)B * MLP_OUT * 4;
+  const size_t o_z1 = c.take(hid), o_a1 = c.take(hid), o_z2 = c.take(hid), o_a2 = c.take(hid);
+  const size_t o_y = c.take(out), o_dy = c.take(out), o_d1 = c.take(hid), o_d2 = c.take(hid);
+  const size_t o_part = c.take(((size_t)B * MLP_OUT / 256 + 1) * 8);
+  if (h) {
+    h->off_p = o_p;
+    h->off_g = o_g;
+    h->off_m = o_m;
+    h->off_v = o_v;
+    h->off_z1 = o_z1;
+    h->off_a1 = o_a1;
+    h->off_z2 = o_z2;
+    h->off_a2 = o_a2;
+    h->off_y = o_y;
+    h->off_dy = o_dy;
+    h->off_d1 = o_d1;
+    h->off_d2 = o_d2;
+    h->off_part = o_part;
+  }
+  return c.off;
+}
+
+struct MlpParams {
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+};
+template <typename T>
+void mlp_split(T* p, T*& W1, T*& b1, T*& W2, T*& b2, T*& W3, T*& b3) {
+  W1 = p;
+  b1 = W1 + MLP_H * MLP_IN;
+  W2 = b1 + MLP_H;
+  b2 = W2 + MLP_H * MLP_H;
+  W3 = b2 + MLP_H;
+  b3 = W3 + MLP_OUT * MLP_H;
+}
+
+dim3 gemm_grid(int M, int N) { return dim3((N + 63) / 64, (M + 63) / 64); }
+
+void mlp_forward(lbib_mlp* h, const float* X, int B, float* Y) {
+  float *W1, *b1, *W2, *b2, *W3, *b3;
+  mlp_split(h->at<float>(h->off_p), W1, b1, W2, b2, W3, b3);
+  float *Z1 = h->at<float>(h->off_z1), *A1 = h->at<float>(h->off_a1);
+  float *Z2 = h->at<float>(h->off_z2), *A2 = h->at<float>(h->off_a2);
+  hipLaunchKernelGGL(k_gemm<EPI_BIAS_GELU>, gemm_grid(B, MLP_H), dim3(256), 0, h->stream, X, MLP_IN, 1,
+                     (const float*)W1, MLP_IN, 1, B, MLP_H, MLP_IN, (const float*)b1, (const float*)nullptr, Z1,
+                     A1);
+  hipLaunchKernelGGL(k_gemm<EPI_BIAS_GELU>, gemm_grid(B, MLP_H), dim3(256), 0, h->stream, (const float*)A1,
+                     MLP_H, 1, (const float*)W2, MLP_H, 1, B, MLP_H, MLP_H, (const float*)b2,
+                     (const float*)nullptr, Z2, A2);
+  hipLaunchKernelGGL(k_gemm<EPI_BIAS>, gemm_grid(B, MLP_OUT), dim3(256), 0, h->stream, (const float*)A2, MLP_H,
+                     1, (const float*)W3, MLP_H, 1, B, MLP_OUT, MLP_H, (const float*)b3, (const float*)nullptr,
+                     (float*)nullptr, Y);
+}
+
+// forward + loss partials + gradient into off_g
+void mlp_backward(lbib_mlp* h, const float* X, const float* T, int B) {
+  float *W1, *b1, *W2, *b2, *W3, *b3, *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
+  mlp_split(h->at<float>(h->off_p), W1, b1, W2, b2, W3, b3);
+  mlp_split(h->at<float>(h->off_g), gW1, gb1, gW2, gb2, gW3, gb3);
+  float* Y = h->at<float>(h->off_y);
+  float* dY = h->at<float>(h->off_dy);
+  float *Z1 = h->at<float>(h->off_z1), *A1 = h->at<float>(h->off_a1);
+  float *Z2 = h->at<float>(h->off_z2), *A2 = h->at<float>(h->off_a2);
+  float *D1 = h->at<float>(h->off_d1), *D2 = h->at<float>(h->off_d2);
+  mlp_forward(h, X, B, Y);
+  const long long n = (long long)B * MLP_OUT;
+  hipLaunchKernelGGL(k_mse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, (const float*)Y, T, n,
+                     1.0f / (float)B, dY, h->at<double>(h->off_part));
+  // layer 3: dW3 = dY^T A2, db3, dZ2 = (dY W3) * GELU'(Z2)
+  hipLaunchKernelGGL(k_gemm<EPI_NONE>, gemm_grid(MLP_OUT, MLP_H), dim3(256), 0, h->stream, (const float*)dY, 1,
+                     MLP_OUT, (const float*)A2, 1, MLP_H, MLP_OUT, MLP_H, B, (const float*)nullptr,
+                     (const float*)nullptr, (float*)nullptr, gW3);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, h->stream, (const float*)dY, B, MLP_OUT, gb3);
+  hipLaunchKernelGGL(k_gemm<EPI_GELU_GRAD>, gemm_grid(B, MLP_H), dim3(256), 0, h->stream, (const float*)dY,
+                     MLP_OUT, 1, (const float*)W3, 1, MLP_H, B, MLP_H, MLP_OUT, (const float*)nullptr,
+                     (const float*)Z2, (float*)nullptr, D2);
+  // layer 2
+  hipLaunchKernelGGL(k_gemm<EPI_NONE>, gemm_grid(MLP_H, MLP_H), dim3(256), 0, h->stream, (const float*)D2, 1,
+                     MLP_H, (const float*)A1, 1, MLP_H, MLP_H, MLP_H, B, (const float*)nullptr,
+                     (const float*)nullptr, (float*)nullptr, gW2);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, h->stream, (const float*)D2, B, MLP_H, gb2);
+  hipLaunchKernelGGL(k_gemm<EPI_GELU_GRAD>, gemm_grid(B, MLP_H), dim3(256), 0, h->stream, (const float*)D2,
+                     MLP_H, 1, (const float*)W2, 1, MLP_H, B, MLP_H, MLP_H, (const float*)nullptr,
+                     (const float*)Z1, (float*)nullptr, D1);
+  // layer 1
+  hipLaunchKernelGGL(k_gemm<EPI_NONE>, gemm_grid(MLP_H, MLP_IN), dim3(256), 0, h->stream, (const float*)D1, 1,
+                     MLP_H, X, 1, MLP_IN, MLP_H, MLP_IN, B, (const float*)nullptr, (const float*)nullptr,
+                     (float*)nullptr, gW1);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, h->stream, (const float*)D1, B, MLP_H, gb1);
+}
+
+int mlp_loss(lbib_mlp* h, int B, double* loss) {
+  const int nb = (int)(((long long)B * MLP_OUT + 255) / 256);
+  std::vector<double> part(nb);
+  HIPCHK(hipMemcpyAsync(part.data(), h->ws + h->off_part, (size_t)nb * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double s = 0.0;
+  for (double v : part) s += v;
+  *loss = 0.5 * s / B;
+  return LBIB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbib_mlp_param_count(void) { return MLP_NPARAM; }
+
+int lbib_mlp_workspace_bytes(int batch_max, size_t* bytes) {
+  if (batch_max < 1 || batch_max > (1 << 20) || !bytes) return LBIB_EINVAL;
+  *bytes = mlp_layout(nullptr, batch_max);
+  return LBIB_OK;
+}
+
+int lbib_mlp_create(int batch_max, void* ws, size_t ws_bytes, void* stream, lbib_mlp** out) {
+  size_t need = 0;
+  int rc = lbib_mlp_workspace_bytes(batch_max, &need);
+  if (rc) return rc;
+  if (!ws || !out || ((uintptr_t)ws % kAlign) != 0) return LBIB_EINVAL;
+  if (ws_bytes < need) return LBIB_ENOMEM;
+  lbib_mlp* h = new (std::nothrow) lbib_mlp();
+  if (!h) return LBIB_ENOMEM;
+  h->ws = (char*)ws;
+  h->stream = (hipStream_t)stream;
+  h->bmax = batch_max;
+  mlp_layout(h, batch_max);
+  if (hipMemsetAsync(h->ws, 0, need, h->stream) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
+    delete h;
+    return LBIB_EHIP;
+  }
+  *out = h;
+  return LBIB_OK;
+}
+
+int lbib_mlp_set_params(lbib_mlp* h, const float* host) {
+  if (!h || !host) return LBIB_EINVAL;
+  for (int k = 0; k < MLP_NPARAM; k++)
+    if (!std::isfinite(host[k])) return LBIB_EINVAL;
+  HIPCHK(hipMemcpyAsync(h->ws + h->off_p, host, (size_t)MLP_NPARAM * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemsetAsync(h->ws + h->off_m, 0, (size_t)MLP_NPARAM * 4, h->stream));
+  HIPCHK(hipMemsetAsync(h->ws + h->off_v, 0, (size_t)MLP_NPARAM * 4, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->t = 0;
+  return LBIB_OK;
+}
+
+int lbib_mlp_get_params(lbib_mlp* h, float* host) {
+  if (!h || !host) return LBIB_EINVAL;
+  HIPCHK(hipMemcpyAsync(host, h->ws + h->off_p, (size_t)MLP_NPARAM * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBIB_OK;
+}
+
+int lbib_mlp_forward(lbib_mlp* h, const float* x_dev, int B, float* y_dev) {
+  if (!h || !x_dev || !y_dev || B < 1 || B > h->bmax) return LBIB_EINVAL;
+  mlp_forward(h, x_dev, B, y_dev);
+  return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+}
+
+int lbib_mlp_gradient(lbib_mlp* h, const float* x_dev, const float* t_dev, int B, double* loss, float* grad_host) {
+  if (!h || !x_dev || !t_dev || B < 1 || B > h->bmax) return LBIB_EINVAL;
+  mlp_backward(h, x_dev, t_dev, B);
+  if (hipGetLastError() != hipSuccess) return LBIB_EHIP;
+  if (grad_host) {
+    HIPCHK(hipMemcpyAsync(grad_host, h->ws + h->off_g, (size_t)MLP_NPARAM * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  if (loss) return mlp_loss(h, B, loss);
+  return LBIB_OK;
+}
+
+int lbib_mlp_adam_step(lbib_mlp* h, const float* x_dev, const float* t_dev, int B, float lr, float beta1,
+                       float beta2, float eps, double* loss) {
+  if (!h || !x_dev || !t_dev || B < 1 || B > h->bmax) return LBIB_EINVAL;
+  if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0)) return LBIB_EINVAL;
+  mlp_backward(h, x_dev, t_dev, B);
+  h->t += 1;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)h->t));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)h->t));
+  hipLaunchKernelGGL(k_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, h->stream, h->at<float>(h->off_p),
+                     (const float*)h->at<float>(h->off_g), h->at<float>(h->off_m), h->at<float>(h->off_v),
+                     MLP_NPARAM, lr, beta1, beta2, eps, c1, c2);
+  if (hipGetLastError() != hipSuccess) return LBIB_EHIP;
+  if (loss) return mlp_loss(h, B, loss);
+  return LBIB_OK;
+}
+
+void lbib_mlp_destroy(lbib_mlp* h) { delete h; }
 
 }  // extern "C"

@@ -48,6 +48,7 @@ class Energies(C.Structure):
 _lib = None
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
+_fp = C.POINTER(C.c_float)
 _vp = C.c_void_p
 
 # (name, restype, argtypes) of every entry point declared in include/lbib.h
@@ -72,12 +73,23 @@ SIGNATURES = [
     ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
     ("lbib_strerror", C.c_char_p, [C.c_int]),
     ("lbib_destroy", None, [_vp]),
+    ("lbib_set_rest", C.c_int, [_vp, C.c_int, _dp]),
     ("lbib_batch_workspace_bytes", C.c_int, [C.c_int, _vp, C.POINTER(C.c_size_t)]),
     ("lbib_batch_create", C.c_int, [C.c_int, _vp, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     ("lbib_batch_member", C.c_int, [_vp, C.c_int, C.POINTER(_vp)]),
     ("lbib_batch_set_launch", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
     ("lbib_batch_get_launch", C.c_int, [_vp, C.c_int, _ip, _ip, _ip, _ip]),
     ("lbib_batch_graph", C.c_int, [_vp, C.c_int, _ip]),
+    ("lbib_mlp_param_count", C.c_int, []),
+    ("lbib_mlp_workspace_bytes", C.c_int, [C.c_int, C.POINTER(C.c_size_t)]),
+    ("lbib_mlp_create", C.c_int, [C.c_int, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    ("lbib_mlp_set_params", C.c_int, [_vp, _fp]),
+    ("lbib_mlp_get_params", C.c_int, [_vp, _fp]),
+    ("lbib_mlp_forward", C.c_int, [_vp, _vp, C.c_int, _vp]),
+    ("lbib_mlp_gradient", C.c_int, [_vp, _vp, _vp, C.c_int, C.POINTER(C.c_double), _fp]),
+    ("lbib_mlp_adam_step", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float,
+                                     C.POINTER(C.c_double)]),
+    ("lbib_mlp_destroy", None, [_vp]),
 ]
 
 
@@ -190,7 +202,7 @@ class Sim:
         except Exception:
             pass
 
-    def add_membrane(self, X, tris=None, kappa_s=0.0, kappa_b=0.0) -> int:
+    def add_membrane(self, X, tris=None, kappa_s=0.0, kappa_b=0.0, rest=None) -> int:
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, self.D)
         mid = C.c_int(-1)
         if tris is None:
@@ -202,7 +214,13 @@ class Sim:
                                          t.ctypes.data_as(_ip), kappa_s, kappa_b, C.byref(mid))
         _chk("lbib_add_membrane", rc)
         self.mem_sizes.append(X.shape[0])
+        if rest is not None:
+            self.set_rest(mid.value, rest)
         return mid.value
+
+    def set_rest(self, i: int, rest):
+        r = np.ascontiguousarray(rest, dtype=np.float64).reshape(-1)
+        _chk("lbib_set_rest", lib().lbib_set_rest(self.h, int(i), _d(r)))
 
     def set_fields(self, rho, phi, psi, u=None):
         arr = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, phi, psi)]
@@ -348,6 +366,28 @@ class Batch:
     def synchronize(self):
         self.stream.synchronize()
 
+    def markers(self) -> list:
+        """Marker positions of every member's membranes, [(n, 2)] per member
+        and membrane, gathered on the device and copied in one transfer."""
+        t = self.torch
+        if not hasattr(self, "_views"):
+            base = self.ws.data_ptr()
+            self._views = []
+            for m in self.members:
+                ptr, n = m.device_view(2)
+                off = ptr - base
+                self._views.append(self.ws[off:off + 8 * n].view(t.float64).view(-1, 3))
+        with t.cuda.stream(self.stream):
+            allx = t.cat(self._views).cpu().numpy()
+        out, o = [], 0
+        for m in self.members:
+            mk = []
+            for n in m.mem_sizes:
+                mk.append(allx[o:o + n, :2].copy())
+                o += n
+            out.append(mk)
+        return out
+
     def close(self):
         if getattr(self, "h", None):
             for m in self.members:
@@ -366,17 +406,90 @@ class Batch:
         b = cls([w["params"] for w in ws], [w["membranes"] for w in ws], device=device, stream=stream)
         for m, w in zip(b.members, ws):
             for mem in w["membranes"]:
-                m.add_membrane(mem["X"], mem.get("tris"), mem["kappa_s"], mem["kappa_b"])
+                m.add_membrane(mem["X"], mem.get("tris"), mem["kappa_s"], mem["kappa_b"], mem.get("rest"))
             f = w["fields"]
             m.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
         return b
+
+
+class Mlp:
+    """The warm-start network's device state (parameters, Adam moments,
+    activations for up to batch_max rows) in a torch-owned workspace."""
+
+    def __init__(self, batch_max: int, device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.batch_max = int(batch_max)
+        nb = C.c_size_t(0)
+        _chk("lbib_mlp_workspace_bytes", lib().lbib_mlp_workspace_bytes(self.batch_max, C.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        _chk("lbib_mlp_create", lib().lbib_mlp_create(self.batch_max, _vp(self.ws.data_ptr()), nb.value,
+                                                      _vp(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.nparam = lib().lbib_mlp_param_count()
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32).reshape(-1)
+        assert a.size == self.nparam
+        _chk("lbib_mlp_set_params", lib().lbib_mlp_set_params(self.h, a.ctypes.data_as(_fp)))
+
+    def params(self) -> np.ndarray:
+        a = np.empty(self.nparam, dtype=np.float32)
+        _chk("lbib_mlp_get_params", lib().lbib_mlp_get_params(self.h, a.ctypes.data_as(_fp)))
+        return a
+
+    def _dev(self, a, cols):
+        t = self.torch
+        x = t.as_tensor(np.ascontiguousarray(a, dtype=np.float32)) if not t.is_tensor(a) else a
+        x = x.to(self.device, dtype=t.float32).contiguous()
+        assert x.dim() == 2 and x.shape[1] == cols and 1 <= x.shape[0] <= self.batch_max
+        return x
+
+    def forward(self, x):
+        """y [B][32] (torch tensor on the device) for inputs x [B][6]."""
+        x = self._dev(x, 6)
+        y = self.torch.empty((x.shape[0], 32), dtype=self.torch.float32, device=self.device)
+        _chk("lbib_mlp_forward", lib().lbib_mlp_forward(self.h, _vp(x.data_ptr()), x.shape[0], _vp(y.data_ptr())))
+        return y
+
+    def gradient(self, x, t):
+        """(loss, gradient) of the batch (host FP64 loss, FP32 gradient)."""
+        x, t = self._dev(x, 6), self._dev(t, 32)
+        loss = C.c_double(0)
+        g = np.empty(self.nparam, dtype=np.float32)
+        _chk("lbib_mlp_gradient", lib().lbib_mlp_gradient(self.h, _vp(x.data_ptr()), _vp(t.data_ptr()),
+                                                          x.shape[0], C.byref(loss), g.ctypes.data_as(_fp)))
+        return loss.value, g
+
+    def adam_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=False):
+        x, t = self._dev(x, 6), self._dev(t, 32)
+        loss = C.c_double(0)
+        _chk("lbib_mlp_adam_step", lib().lbib_mlp_adam_step(self.h, _vp(x.data_ptr()), _vp(t.data_ptr()),
+                                                            x.shape[0], lr, beta1, beta2, eps,
+                                                            C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbib_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def from_workload(w: dict, storage="fp32", device="cuda:0", **kw) -> Sim:
     """Create a GPU simulation from a workloads.* dictionary."""
     s = Sim(w["params"], storage=storage, membranes=w["membranes"], device=device, **kw)
     for m in w["membranes"]:
-        s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"])
+        s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"], m.get("rest"))
     f = w["fields"]
     s.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
     return s
