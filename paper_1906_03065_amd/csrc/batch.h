@@ -90,6 +90,15 @@ __global__ __launch_bounds__(NT) void kb_coupling2d(const BMember<St>* T, int n,
 
 // markers of all members (mpre: marker prefix, n + 1 entries)
 template <class St>
+__global__ void kb_segtable2d(const BMember<St>* T, const int* __restrict__ mpre, int n) {
+  const int gf = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gf >= mpre[n]) return;
+  const int i = prefix_find(mpre, n, gf);
+  const MemDev md = T[i].md;
+  segtable2d_run(md, gf - mpre[i]);
+}
+
+template <class St>
 __global__ void kb_memforce2d(const BMember<St>* T, const int* __restrict__ mpre, int n) {
   const int gf = blockIdx.x * blockDim.x + threadIdx.x;
   if (gf >= mpre[n]) return;

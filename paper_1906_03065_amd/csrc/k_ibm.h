@@ -40,6 +40,8 @@ struct MemDev {
   double* kb;         // K
   double* mbox;       // 8 per membrane: lo xyz, hi xyz, orientation (+-1), spare
   int* status;        // [0] force/marker out of range, [1] lattice too small / too many membranes
+  float4* stab;       // 2D, per step: segment l -> l+1 as (start - box centre, edge) in FP32
+  float* sinv;        // 2D, per step: 1 / |edge|^2
   int K, M;
 };
 
@@ -75,6 +77,24 @@ __device__ double block_min(double v, double* sh) {
   __syncthreads();
   double t = sh[0];
   for (int i = 1; i < NT / 64; i++) t = fmin(t, sh[i]);
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ float wave_minf(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int NT>
+__device__ float block_minf(float v, float* sh) {
+  v = wave_minf(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  float t = sh[0];
+  for (int k = 1; k < NT / 64; k++) t = fminf(t, sh[k]);
   __syncthreads();
   return t;
 }
@@ -168,6 +188,32 @@ __global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int
   tiles_run<NT>(md, tm, nx, ny, nz, wall_y, wall_z, D, reach, (int)blockIdx.x);
 }
 
+// per-step FP32 segment table of marker g (after the boxes are known)
+__device__ __forceinline__ void segtable2d_run(const MemDev& md, int g) {
+  const int m = md.mid[g];
+  const int b = md.moff[m], n = md.moff[m + 1] - b;
+  const int g1 = (g + 1 - b == n) ? b : g + 1;
+  const double* bx = md.mbox + 8 * m;
+  const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
+  const double ex = md.X[3 * g1] - md.X[3 * g], ey = md.X[3 * g1 + 1] - md.X[3 * g + 1];
+  const double ee = ex * ex + ey * ey;
+  md.stab[g] = make_float4((float)(md.X[3 * g] - cx), (float)(md.X[3 * g + 1] - cy), (float)ex, (float)ey);
+  md.sinv[g] = ee > 0.0 ? (float)(1.0 / ee) : 0.0f;
+}
+
+__global__ void k_segtable2d(MemDev md) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < md.M) segtable2d_run(md, g);
+}
+
+// FP32 squared distance from p to the segment (s.x, s.y) + t (s.z, s.w)
+__device__ __forceinline__ float seg_d2f(float px, float py, float4 sg, float inv) {
+  const float qx = px - sg.x, qy = py - sg.y;
+  const float t = fminf(fmaxf((qx * sg.z + qy * sg.w) * inv, 0.0f), 1.0f);
+  const float dx = qx - t * sg.z, dy = qy - t * sg.w;
+  return dx * dx + dy * dy;
+}
+
 // ---------------------------------------------------------------------------
 // 2D geometry helpers (FP64)
 
@@ -250,11 +296,14 @@ __device__ __forceinline__ bool tile_splits(int s, int n, double c) {
 template <class St, typename R, int NT>
 __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap& tm, const CoupArgs& ca,
                                                 double* __restrict__ Ifield, const St& cur, int li) {
+  static_assert(NT == TILE2 * TILE2, "one thread per node of a tile");
   __shared__ int s_cand[COUP_CHUNK];
   __shared__ float4 s_geo[COUP_CHUNK];  // candidate start point and edge, relative to the tile centre
   __shared__ float s_inv[COUP_CHUNK];   // 1 / |edge|^2
+  __shared__ unsigned short s_wl[NT / 64][COUP_CHUNK];  // per-wave candidate lists
   __shared__ int s_cnt;
   __shared__ double s_red[NT / 64];
+  __shared__ float s_redf[NT / 64];
   __shared__ int b_seg[COUP_KEEP][NT];
   __shared__ double b_t[COUP_KEEP][NT];
   __shared__ double b_sd[COUP_KEEP][NT];
@@ -263,7 +312,14 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
   {
     const int t = tm.tlist[li];
     const int tx = t % tm.ntx, ty = t / tm.ntx;
-    const int x = tx * TILE2 + (threadIdx.x % TILE2), y = ty * TILE2 + (threadIdx.x / TILE2);
+    // wave w holds the 8 x 8 sub-tile (w & 1, w >> 1) of the 16 x 16 tile
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = tx * TILE2 + (wv & 1) * 8 + (lane & 7), y = ty * TILE2 + (wv >> 1) * 8 + (lane >> 3);
+    // sub-tile centre relative to the tile centre
+    const float cwx = (wv & 1) ? 4.0f : -4.0f, cwy = (wv >> 1) ? 4.0f : -4.0f;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // largest distance of a node from its tile / sub-tile centre
+    const double rn16 = 7.5 * 1.41421356237309515, rn8 = 3.5 * 1.41421356237309515;
     const bool valid = (x < ca.nx) && (y < ca.ny);
     const double xt = tx * TILE2 + 0.5 * (TILE2 - 1), yt = ty * TILE2 + 0.5 * (TILE2 - 1);
     double Itot = 0.0;
@@ -314,31 +370,42 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         }
         continue;
       }
-      // distance of the tile centre to the ring, and its ray parity
-      double dmin = 1e300;
-      int cr = 0;
-      for (int l = threadIdx.x; l < n; l += NT) {
-        const int l1 = (l + 1 == n) ? 0 : l + 1;
-        double tt;
-        dmin = fmin(dmin, seg_d2(pxt, pyt, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1], tt));
-        cr += ray_cross(pxt, pyt, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1]);
+      // distance of the tile centre to the ring, in FP32 from the step's
+      // segment table (the first values stay in registers for the
+      // candidate list); the ray parity only for a tile beyond the band
+      const float4* stab = md.stab + b;
+      const float* sinv = md.sinv + b;
+      const float pcx = (float)(pxt - cx), pcy = (float)(pyt - cy);
+      constexpr int KEEPD = COUP_CHUNK / NT;
+      float dl = 3.0e38f, dkeep[KEEPD];
+#pragma unroll
+      for (int r = 0; r < KEEPD; r++) {
+        const int l = threadIdx.x + r * NT;
+        dkeep[r] = l < n ? seg_d2f(pcx, pcy, stab[l], sinv[l]) : 3.0e38f;
+        dl = fminf(dl, dkeep[r]);
       }
-      dmin = sqrt(block_min<NT>(dmin, s_red));
-      const int par = ((int)block_sum<NT>((double)cr, s_red)) & 1;
+      for (int l = threadIdx.x + KEEPD * NT; l < n; l += NT) dl = fminf(dl, seg_d2f(pcx, pcy, stab[l], sinv[l]));
+      const float dminf = sqrtf(block_minf<NT>(dl, s_redf));
       const int slot = kept++;
-      if (dmin > ca.r_cut + hd) {
+      if ((double)dminf > ca.r_cut + rn16 + 0.01) {
         // no node of the tile is within the band: all on the centre's side
+        int cr = 0;
+        for (int l = threadIdx.x; l < n; l += NT) {
+          const int l1 = (l + 1 == n) ? 0 : l + 1;
+          cr += ray_cross(pxt, pyt, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1]);
+        }
+        const int par = ((int)block_sum<NT>((double)cr, s_red)) & 1;
         if (inbox) Itot += par ? 1.0 : 0.0;
         if (slot < COUP_KEEP) b_seg[slot][threadIdx.x] = -1;
         continue;
       }
-      // every node's closest segment lies within dmin + 2 hd of the centre.
-      // Candidates go to LDS with their geometry relative to the tile centre
-      // in FP32 (one reciprocal per segment, none per node); each node finds
-      // the FP32 minimum, then re-evaluates in FP64 every candidate within a
-      // margin that covers the FP32 rounding, so the FP64 closest segment
-      // (lowest index on ties) is the one chosen.
-      const double cull = dmin + 2.0 * hd + 1e-6;
+      // every node's closest segment lies within dmin + 2 rn16 of the
+      // centre.  Candidates go to LDS with their geometry relative to the
+      // tile centre in FP32; each node finds the FP32 minimum, then
+      // re-evaluates in FP64 every candidate within a margin that covers the
+      // FP32 rounding, so the FP64 closest segment (lowest index on ties) is
+      // the one chosen.
+      const float cull = dminf + (float)(2.0 * rn16) + 0.01f;
       const float fx = (float)(px - pxt), fy = (float)(py - pyt);
       double d2b = 1e300, tb = 0.0;
       int sb = -1;
@@ -346,20 +413,62 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         for (int l = c0 + threadIdx.x; l < min(n, c0 + COUP_CHUNK); l += NT) {
-          const int l1 = (l + 1 == n) ? 0 : l + 1;
-          double tt;
-          const double ax = X[3 * l], ay = X[3 * l + 1], ex = X[3 * l1] - ax, ey = X[3 * l1 + 1] - ay;
-          if (seg_d2(pxt, pyt, ax, ay, X[3 * l1], X[3 * l1 + 1], tt) <= cull * cull) {
+          const int r = (l - threadIdx.x) / NT;
+          const float d = (c0 == 0 && r < KEEPD) ? dkeep[r] : seg_d2f(pcx, pcy, stab[l], sinv[l]);
+          if (d <= cull * cull) {
             const int q = atomicAdd(&s_cnt, 1);
+            const float4 sg = stab[l];
             s_cand[q] = l;
-            const double ee = ex * ex + ey * ey;
-            s_geo[q] = make_float4((float)(ax - pxt), (float)(ay - pyt), (float)ex, (float)ey);
-            s_inv[q] = ee > 0.0 ? (float)(1.0 / ee) : 0.0f;
+            s_geo[q] = make_float4(sg.x - pcx, sg.y - pcy, sg.z, sg.w);
+            s_inv[q] = sinv[l];
           }
         }
         __syncthreads();
         const int nc = s_cnt;
-        if (inbox && nc > 0) {
+        if (n <= COUP_CHUNK) {
+          // one chunk holds every candidate: each wave narrows the list to
+          // its 8 x 8 sub-tile (closest segments of its nodes lie within
+          // d(sub-tile centre) + 2 rn8 of the sub-tile centre)
+          auto d2f = [&](int q, float px_, float py_) {
+            const float4 g4 = s_geo[q];
+            const float qx = px_ - g4.x, qy = py_ - g4.y;
+            const float sp = fminf(fmaxf((qx * g4.z + qy * g4.w) * s_inv[q], 0.0f), 1.0f);
+            const float dx = qx - sp * g4.z, dy = qy - sp * g4.w;
+            return dx * dx + dy * dy;
+          };
+          float dw = 3.0e38f;
+          for (int q = lane; q < nc; q += 64) dw = fminf(dw, d2f(q, cwx, cwy));
+          for (int o2 = 32; o2 > 0; o2 >>= 1) dw = fminf(dw, __shfl_xor(dw, o2, 64));
+          const float cr = sqrtf(dw) + (float)(2.0 * rn8) + 1e-3f;
+          int cnt = 0;
+          for (int base = 0; base < nc; base += 64) {
+            const int q = base + lane;
+            const bool pr = q < nc && d2f(q, cwx, cwy) <= cr * cr;
+            const unsigned long long mk = __ballot(pr);
+            if (pr) s_wl[wv][cnt + __popcll(mk & below)] = (unsigned short)q;
+            cnt += __popcll(mk);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          if (inbox) {
+            float bf = 3.0e38f;
+            for (int k = 0; k < cnt; k++) bf = fminf(bf, d2f(s_wl[wv][k], fx, fy));
+            const float tol = 2e-3f + 2e-5f * bf;
+            for (int k = 0; k < cnt; k++) {
+              const int q = s_wl[wv][k];
+              if (d2f(q, fx, fy) > bf + tol) continue;
+              const int s = s_cand[q];
+              const int s1 = (s + 1 == n) ? 0 : s + 1;
+              double tt;
+              const double d2 = seg_d2(px, py, X[3 * s], X[3 * s + 1], X[3 * s1], X[3 * s1 + 1], tt);
+              if (d2 < d2b || (d2 == d2b && s < sb)) {
+                d2b = d2;
+                sb = s;
+                tb = tt;
+              }
+            }
+          }
+        } else if (inbox && nc > 0) {
           float bf = 3.0e38f;
           for (int q = 0; q < nc; q++) {
             const float4 g4 = s_geo[q];
@@ -368,7 +477,7 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
             const float dx = qx - sp * g4.z, dy = qy - sp * g4.w;
             bf = fminf(bf, dx * dx + dy * dy);
           }
-          const float tol = 1e-3f + 1e-5f * bf;
+          const float tol = 2e-3f + 2e-5f * bf;
           for (int q = 0; q < nc; q++) {
             const float4 g4 = s_geo[q];
             const float qx = fx - g4.x, qy = fy - g4.y;
@@ -471,7 +580,7 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
 
 // one tile per workgroup (grid-stride over the active-tile list)
 template <class St, typename R, int NT>
-__global__ __launch_bounds__(NT) void k_coupling2d(MemDev md, TileMap tm, CoupArgs ca,
+__global__ __launch_bounds__(NT, 3) void k_coupling2d(MemDev md, TileMap tm, CoupArgs ca,
                                                    double* __restrict__ Ifield, St cur) {
   const int ntl = tm.tstate[0];
   for (int li = blockIdx.x; li < ntl; li += gridDim.x) coupling2d_tile<St, R, NT>(md, tm, ca, Ifield, cur, li);

@@ -410,10 +410,6 @@ __device__ __forceinline__ void wave_argmin(double& d, int& i) {
   }
 }
 
-__device__ __forceinline__ float wave_minf(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 template <int NT>
 __device__ void block_argmin(double& d, int& i, double* sd, int* si) {
@@ -431,18 +427,6 @@ __device__ void block_argmin(double& d, int& i, double* sd, int* si) {
   __syncthreads();
 }
 
-template <int NT>
-__device__ float block_minf(float v, float* sh) {
-  v = wave_minf(v);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wv] = v;
-  __syncthreads();
-  float t = sh[0];
-  for (int k = 1; k < NT / 64; k++) t = fminf(t, sh[k]);
-  __syncthreads();
-  return t;
-}
 
 // one 8^3 tile per workgroup of 512 threads (grid-stride over the active
 // tiles); wave w holds the 4^3 sub-tile (w & 1, (w >> 1) & 1, w >> 2)

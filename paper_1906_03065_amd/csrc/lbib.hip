@@ -59,7 +59,7 @@ struct Layout {
   size_t pops[2];       // population buffers A, B
   size_t pop_bytes;     // bytes of one buffer
   size_t Ifield, fib, force, tflag, tlist, tstate, stage, part;
-  size_t X, U, F, Facc, rest, moff, mid, ks, kb, mbox, status, memE;
+  size_t X, U, F, Facc, rest, moff, mid, ks, kb, mbox, status, memE, stab, sinv;
   // 3D: moment field and triangle meshes
   size_t mom, tri, toff, edge, erest, eoff, emem, tadj, vtoff, vt, fn, vn, ttab, ctab, coff;
   int maxCl;
@@ -137,6 +137,8 @@ Layout make_layout(const lbib_params* p) {
   L.mbox = c.take((size_t)K * 8 * 8);
   L.status = c.take(64);
   L.memE = c.take(64);
+  L.stab = c.take(D == 2 ? (size_t)M * 16 : 0);
+  L.sinv = c.take(D == 2 ? (size_t)M * 4 : 0);
   const bool d3 = D == 3;
   L.mom = c.take(d3 ? (size_t)N * 3 * 8 : 0);
   L.tri = c.take((size_t)L.maxT * 3 * 4);
@@ -251,6 +253,8 @@ struct lbib_sim {
     m.kb = at<double>(L.kb);
     m.mbox = at<double>(L.mbox);
     m.status = at<int>(L.status);
+    m.stab = at<float4>(L.stab);
+    m.sinv = at<float>(L.sinv);
     m.K = K;
     m.M = M;
     return m;
@@ -385,6 +389,7 @@ struct Engine2D final : lbib_sim {
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
     hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, 1, p.wall_y,
                        0, 2, r_cut + 3.0);
+    hipLaunchKernelGGL(k_segtable2d, dim3((M + 255) / 256), dim3(256), 0, stream, md);
     const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 2048);
     hipLaunchKernelGGL((k_coupling2d<St, R, COUP_THREADS>), dim3(grid), dim3(COUP_THREADS), 0, stream,
                        md, tm, coup_args(want_force), at<double>(L.Ifield), store(cur));
@@ -856,6 +861,8 @@ struct BatchEngine2D final : lbib_sim {
     if (nmems > 0) {
       hipLaunchKernelGGL((kb_tiles<St, 256>), dim3(nmems), dim3(256), 0, stream, (const BMember<St>*)T,
                          (const int2*)at<int2>(off_mems));
+      hipLaunchKernelGGL(kb_segtable2d<St>, dim3((Mtot + 255) / 256), dim3(256), 0, stream,
+                         (const BMember<St>*)T, mpre, n);
       hipLaunchKernelGGL((kb_coupling2d<St, R, COUP_THREADS>), dim3(cgrid), dim3(COUP_THREADS), 0, stream,
                          (const BMember<St>*)T, n, parity);
       hipLaunchKernelGGL(kb_memforce2d<St>, dim3((Mtot + 255) / 256), dim3(256), 0, stream,
