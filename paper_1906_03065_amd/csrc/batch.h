@@ -90,33 +90,15 @@ __global__ __launch_bounds__(NT) void kb_coupling2d(const BMember<St>* T, int n,
 
 // markers of all members (mpre: marker prefix, n + 1 entries)
 template <class St>
-__global__ void kb_segtable2d(const BMember<St>* T, const int* __restrict__ mpre, int n) {
-  const int gf = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gf >= mpre[n]) return;
-  const int i = prefix_find(mpre, n, gf);
-  const MemDev md = T[i].md;
-  segtable2d_run(md, gf - mpre[i]);
-}
-
-template <class St>
-__global__ void kb_memforce2d(const BMember<St>* T, const int* __restrict__ mpre, int n) {
-  const int gf = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gf >= mpre[n]) return;
-  const int i = prefix_find(mpre, n, gf);
-  const MemDev md = T[i].md;
-  memforce2d_run(md, gf - mpre[i]);
-}
-
-template <class St>
-__global__ void kb_spread2d(const BMember<St>* T, const int* __restrict__ mpre, int n) {
+__global__ void kb_forcespread2d(const BMember<St>* T, const int* __restrict__ mpre, int n) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int gf = tid >> 4, k = tid & 15;
-  if (gf >= mpre[n]) return;
-  const int i = prefix_find(mpre, n, gf);
+  const bool live = gf < mpre[n];
+  const int i = live ? prefix_find(mpre, n, gf) : 0;
   const MemDev md = T[i].md;
   long long* fib = T[i].fib;
   const int nx = T[i].P.nx, ny = T[i].P.ny, wy = T[i].P.wall_y;
-  spread2d_run(md, fib, nx, ny, wy, gf - mpre[i], k);
+  forcespread2d_run(md, fib, nx, ny, wy, live ? gf - mpre[i] : 0, k, live);
 }
 
 template <class St, typename R>

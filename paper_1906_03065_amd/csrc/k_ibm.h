@@ -145,6 +145,17 @@ __device__ __forceinline__ void tiles_run(const MemDev& md, const TileMap& tm, i
     }
     md.mbox[8 * m + 6] = area >= 0.0 ? 1.0 : -1.0;
   }
+  // 2D: this step's FP32 segment table, relative to the box centre
+  if (D == 2) {
+    const double cx = 0.5 * (lo[0] + hi[0]), cy = 0.5 * (lo[1] + hi[1]);
+    for (int l = tid; l < n; l += NT) {
+      const int g = b + l, g1 = (l + 1 == n) ? b : g + 1;
+      const double ex = md.X[3 * g1] - md.X[3 * g], ey = md.X[3 * g1 + 1] - md.X[3 * g + 1];
+      const double ee = ex * ex + ey * ey;
+      md.stab[g] = make_float4((float)(md.X[3 * g] - cx), (float)(md.X[3 * g + 1] - cy), (float)ex, (float)ey);
+      md.sinv[g] = ee > 0.0 ? (float)(1.0 / ee) : 0.0f;
+    }
+  }
   // non-finite or runaway markers: flag and leave this membrane off the map
   for (int a = 0; a < D; a++)
     if (!(fabs(lo[a]) < 1e9) || !(fabs(hi[a]) < 1e9)) {
@@ -186,24 +197,6 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int ny, int nz,
                                               int wall_y, int wall_z, int D, double reach) {
   tiles_run<NT>(md, tm, nx, ny, nz, wall_y, wall_z, D, reach, (int)blockIdx.x);
-}
-
-// per-step FP32 segment table of marker g (after the boxes are known)
-__device__ __forceinline__ void segtable2d_run(const MemDev& md, int g) {
-  const int m = md.mid[g];
-  const int b = md.moff[m], n = md.moff[m + 1] - b;
-  const int g1 = (g + 1 - b == n) ? b : g + 1;
-  const double* bx = md.mbox + 8 * m;
-  const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
-  const double ex = md.X[3 * g1] - md.X[3 * g], ey = md.X[3 * g1 + 1] - md.X[3 * g + 1];
-  const double ee = ex * ex + ey * ey;
-  md.stab[g] = make_float4((float)(md.X[3 * g] - cx), (float)(md.X[3 * g + 1] - cy), (float)ex, (float)ey);
-  md.sinv[g] = ee > 0.0 ? (float)(1.0 / ee) : 0.0f;
-}
-
-__global__ void k_segtable2d(MemDev md) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < md.M) segtable2d_run(md, g);
 }
 
 // FP32 squared distance from p to the segment (s.x, s.y) + t (s.z, s.w)
@@ -613,7 +606,7 @@ __device__ __forceinline__ void bend_grad(double ax, double ay, double bx, doubl
   gby = c1 * tby - c2 * by / lb;
 }
 
-__device__ __forceinline__ void memforce2d_run(const MemDev& md, int g) {
+__device__ __forceinline__ void memforce2d_run(const MemDev& md, int g, double& Fxo, double& Fyo) {
   const int m = md.mid[g];
   const int b = md.moff[m], n = md.moff[m + 1] - b;
   const int l = g - b;
@@ -664,20 +657,16 @@ __device__ __forceinline__ void memforce2d_run(const MemDev& md, int g) {
   md.F[3 * g] = Fx;
   md.F[3 * g + 1] = Fy;
   md.F[3 * g + 2] = 0.0;
-}
-
-__global__ void k_memforce2d(MemDev md) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < md.M) memforce2d_run(md, g);
+  Fxo = Fx;
+  Fyo = Fy;
 }
 
 // spreading, eq. Spreading with delta x = 1 (READING: no extra Delta s):
 // sixteen lanes per marker, each adds F delta_h(x - X) to one stencil node in
 // fixed point (integer sums are order independent)
 __device__ __forceinline__ void spread2d_run(const MemDev& md, long long* __restrict__ fib, int nx, int ny,
-                                             int wall_y, int g, int k) {
+                                             int wall_y, int g, int k, double Fx, double Fy) {
   const double X = md.X[3 * g], Y = md.X[3 * g + 1];
-  const double Fx = md.F[3 * g], Fy = md.F[3 * g + 1];
   const int cx = (int)floor(X) - 1 + (k & 3), cy = (int)floor(Y) - 1 + (k >> 2);
   if (wall_y && (cy < 0 || cy >= ny)) return;
   const double w = peskin(cx - X) * peskin(cy - Y);
@@ -686,10 +675,22 @@ __device__ __forceinline__ void spread2d_run(const MemDev& md, long long* __rest
   atomicAdd((unsigned long long*)&fib[2 * node + 1], (unsigned long long)to_fix(Fy * w));
 }
 
-__global__ void k_spread2d(MemDev md, long long* __restrict__ fib, int nx, int ny, int wall_y) {
+// marker forces (strain + bending + coupling, eq. DiscreteTF) by the first
+// lane of each sixteen-lane group, handed to the group by shuffles, then
+// spread by all sixteen; every lane of a group must call it
+__device__ __forceinline__ void forcespread2d_run(const MemDev& md, long long* __restrict__ fib, int nx, int ny,
+                                                  int wall_y, int g, int k, bool live) {
+  double Fx = 0.0, Fy = 0.0;
+  if (live && k == 0) memforce2d_run(md, g, Fx, Fy);
+  Fx = __shfl(Fx, 0, 16);
+  Fy = __shfl(Fy, 0, 16);
+  if (live) spread2d_run(md, fib, nx, ny, wall_y, g, k, Fx, Fy);
+}
+
+__global__ void k_forcespread2d(MemDev md, long long* __restrict__ fib, int nx, int ny, int wall_y) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int g = tid >> 4, k = tid & 15;
-  if (g < md.M) spread2d_run(md, fib, nx, ny, wall_y, g, k);
+  forcespread2d_run(md, fib, nx, ny, wall_y, g, k, g < md.M);
 }
 
 // interpolation of v* = u(t+1) + f(t) / (2 rho(t+1)) at the stencil of X(t)

@@ -389,7 +389,6 @@ struct Engine2D final : lbib_sim {
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
     hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, 1, p.wall_y,
                        0, 2, r_cut + 3.0);
-    hipLaunchKernelGGL(k_segtable2d, dim3((M + 255) / 256), dim3(256), 0, stream, md);
     const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 2048);
     hipLaunchKernelGGL((k_coupling2d<St, R, COUP_THREADS>), dim3(grid), dim3(COUP_THREADS), 0, stream,
                        md, tm, coup_args(want_force), at<double>(L.Ifield), store(cur));
@@ -456,7 +455,6 @@ struct Engine2D final : lbib_sim {
 
   int step() override {
     MemDev md = memdev();
-    const int mb = (M + 255) / 256;
     const int mb16 = (16 * M + 255) / 256;  // sixteen lanes per marker
     if (K > 0) {
       hipEvent_t t0 = tbeg(1);
@@ -464,8 +462,7 @@ struct Engine2D final : lbib_sim {
       if (rc) return rc;
       tend(1, t0);
       t0 = tbeg(2);
-      hipLaunchKernelGGL(k_memforce2d, dim3(mb), dim3(256), 0, stream, md);
-      hipLaunchKernelGGL(k_spread2d, dim3(mb16), dim3(256), 0, stream, md, at<long long>(L.fib), p.nx,
+      hipLaunchKernelGGL(k_forcespread2d, dim3(mb16), dim3(256), 0, stream, md, at<long long>(L.fib), p.nx,
                          p.ny, p.wall_y);
       tend(2, t0);
     }
@@ -861,13 +858,9 @@ struct BatchEngine2D final : lbib_sim {
     if (nmems > 0) {
       hipLaunchKernelGGL((kb_tiles<St, 256>), dim3(nmems), dim3(256), 0, stream, (const BMember<St>*)T,
                          (const int2*)at<int2>(off_mems));
-      hipLaunchKernelGGL(kb_segtable2d<St>, dim3((Mtot + 255) / 256), dim3(256), 0, stream,
-                         (const BMember<St>*)T, mpre, n);
       hipLaunchKernelGGL((kb_coupling2d<St, R, COUP_THREADS>), dim3(cgrid), dim3(COUP_THREADS), 0, stream,
                          (const BMember<St>*)T, n, parity);
-      hipLaunchKernelGGL(kb_memforce2d<St>, dim3((Mtot + 255) / 256), dim3(256), 0, stream,
-                         (const BMember<St>*)T, mpre, n);
-      hipLaunchKernelGGL(kb_spread2d<St>, dim3((16 * Mtot + 255) / 256), dim3(256), 0, stream,
+      hipLaunchKernelGGL(kb_forcespread2d<St>, dim3((16 * Mtot + 255) / 256), dim3(256), 0, stream,
                          (const BMember<St>*)T, mpre, n);
     }
     for (int c = 0; c < NCLS; c++) {
@@ -1013,7 +1006,15 @@ int init_sim(lbib_sim* s, const lbib_params* p, const Layout& L, char* ws, hipSt
       hipMemsetAsync(s->ws + L.Facc, 0, (size_t)std::max(p->max_markers, 1) * 3 * 8, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.status, 0, 64, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.force, 0, (size_t)s->N * s->D * 8, st) != hipSuccess ||
-      hipMemsetAsync(s->ws + L.moff, 0, 4, st) != hipSuccess)
+      hipMemsetAsync(s->ws + L.moff, 0, 4, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.Ifield, 0, (size_t)s->N * 8, st) != hipSuccess)
+    return LBIB_EHIP;
+  // the tile flags start at 0 and the stamp at 1: no tile is active until a
+  // membrane's tile pass flags it (a simulation without membranes never
+  // reads the profile or force maps)
+  static const int stamp0[2] = {0, 1};
+  if (hipMemcpyAsync(s->ws + L.tstate, stamp0, sizeof(stamp0), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
     return LBIB_EHIP;
   return LBIB_OK;
 }
