@@ -213,22 +213,39 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
   const int stamp = tstate[1];  // tiles flagged with this step's stamp are active
   R pf[NS][9], pg[NS][9], ph[NS][9];
   double g0[NS], h0[NS];
+  // tile flag of the row in each register slot, loaded with the row; the
+  // membrane fields of rows k-1 and k-2 are then fetched at the start of
+  // iteration k, beside the pull, instead of after a dependent flag load
+  int tfl[NS];
 
   auto load_row = [&](auto slot_c, int k) {
     constexpr int S = decltype(slot_c)::value;
     const int ry = fd_row(rbase + dir * k, P.ny, P.wall_y);
     pull9(src, P, x, ry, pf[S], pg[S], ph[S], g0[S], h0[S]);
+    tfl[S] = tflag[(ry / P.tile) * P.ntx + x / P.tile];
   };
 
   auto body = [&](auto slot_c, int k) {
     constexpr int S = decltype(slot_c)::value;   // slot of row k
     constexpr int SN = (S + 1) % NS;             // slot of row k+1
     constexpr int SC = (S + NS - 2) % NS;        // slot of row k-2 (collided now)
+    constexpr int SP = (S + NS - 1) % NS;        // slot of row k-1 (chemical potential now)
     const int r = rbase + dir * k;               // row whose moments are formed now
     if constexpr (NS == 4) {
       if (k + 1 < K) load_row(std::integral_constant<int, SN>{}, k + 1);
     } else {
       load_row(std::integral_constant<int, S>{}, k);
+    }
+    const int qy = fd_row(r - dir, P.ny, P.wall_y);  // row of the chemical potential
+    const int cy = r - 2 * dir;                      // row of the collision
+    double Ipre = 0.0;
+    if (k >= 2 && j >= 1 && j < BX - 1 && tfl[SP] == stamp) Ipre = Ifield[(long long)qy * P.nx + x];
+    long long fb0 = 0, fb1 = 0;
+    const bool cact = k >= 4 && interior && tfl[SC] == stamp;
+    if (cact) {
+      const long long* fp = fib + 2 * ((long long)cy * P.nx + x);
+      fb0 = fp[0];
+      fb1 = fp[1];
     }
     // ---- M: moments of row r -> ring slot k%3
     {
@@ -257,11 +274,8 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
         lap[f] = (2.0 / 3.0) * n4 + (1.0 / 6.0) * n8;
         ctr[f] = q;
       }
-      const int qy = fd_row(r - dir, P.ny, P.wall_y);
-      double I = 0.0;
-      if (tflag[(qy / P.tile) * P.ntx + x / P.tile] == stamp) I = Ifield[(long long)qy * P.nx + x];
       double mr, mp, ms;
-      chem_pot(P, ctr[0], ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
+      chem_pot(P, ctr[0], ctr[1], ctr[2], lap[0], lap[1], lap[2], Ipre, mr, mp, ms);
       const int sl = k % 3;
       s_u[sl][0][j] = mr;
       s_u[sl][1][j] = mp;
@@ -270,7 +284,6 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
     __syncthreads();
     // ---- C: collide row r - 2 dir with the registers of slot SC
     if (k >= 4 && interior) {
-      const int cy = r - 2 * dir;
       const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // mu rows cy-dir, cy, cy+dir
       const int sn = dir > 0 ? c : a, ss = dir > 0 ? a : c;   // north (cy+1) and south (cy-1)
       // moments of row cy were stored two iterations ago (slot (k-2)%3 = a)
@@ -292,12 +305,11 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
       double Fx = -(rho * gx[0] + phi * gx[1] + psi * gx[2]);
       double Fy = -(rho * gy[0] + phi * gy[1] + psi * gy[2]);
       const long long node = (long long)cy * P.nx + x;
-      if (tflag[(cy / P.tile) * P.ntx + x / P.tile] == stamp) {
-        long long* fp = fib + 2 * node;
-        Fx += from_fix(fp[0]);
-        Fy += from_fix(fp[1]);
-        fp[0] = 0;
-        fp[1] = 0;
+      if (cact) {
+        Fx += from_fix(fb0);
+        Fy += from_fix(fb1);
+        fib[2 * node] = 0;
+        fib[2 * node + 1] = 0;
         force[2 * node] = Fx;
         force[2 * node + 1] = Fy;
       }
