@@ -27,6 +27,7 @@ constexpr int TILE2 = 16;          // 2D tile edge
 constexpr int COUP_THREADS = 256;  // one thread per node of a 16x16 tile
 constexpr int COUP_CHUNK = 512;    // segments examined per culling chunk
 constexpr int COUP_KEEP = 4;       // membranes per tile whose band data stays in LDS
+constexpr int COUP_ML = 64;        // membranes whose grown boxes may meet one tile
 
 struct MemDev {
   double* X;          // 3 per marker
@@ -285,6 +286,45 @@ __device__ __forceinline__ bool tile_splits(int s, int n, double c) {
   return near_image((double)s, c, n) - s != near_image((double)e, c, n) - e;
 }
 
+// exact FP64 closest segment to (px, py) among the candidates of a wave list
+// whose FP32 value lies within tol of the FP32 minimum bf, reduced over the
+// wave (lowest segment index on equal distances); every lane gets the result
+__device__ __forceinline__ void wave_closest(const unsigned short* wl, int cnt, const int* cand,
+                                             const float4* geo, const float* inv, const double4* end,
+                                             float fx, float fy, float bf, double px, double py, double& d2b,
+                                             int& sb, double& tb) {
+  const float tol = 2e-3f + 2e-5f * bf;
+  d2b = 1e300;
+  sb = 0x7fffffff;
+  tb = 0.0;
+  for (int k = (int)(threadIdx.x & 63); k < cnt; k += 64) {
+    const int q = wl[k];
+    const float4 g4 = geo[q];
+    const float qx = fx - g4.x, qy = fy - g4.y;
+    const float sp = fminf(fmaxf((qx * g4.z + qy * g4.w) * inv[q], 0.0f), 1.0f);
+    const float dx = qx - sp * g4.z, dy = qy - sp * g4.w;
+    if (dx * dx + dy * dy > bf + tol) continue;
+    const double4 e = end[q];
+    double tt;
+    const double d2 = seg_d2(px, py, e.x, e.y, e.z, e.w, tt);
+    const int s = cand[q];
+    if (d2 < d2b || (d2 == d2b && s < sb)) {
+      d2b = d2;
+      sb = s;
+      tb = tt;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double d2o = __shfl_xor(d2b, o, 64), to = __shfl_xor(tb, o, 64);
+    const int so = __shfl_xor(sb, o, 64);
+    if (d2o < d2b || (d2o == d2b && so < sb)) {
+      d2b = d2o;
+      sb = so;
+      tb = to;
+    }
+  }
+}
+
 // one active tile li of the list, all NT threads of the workgroup
 template <class St, typename R, int NT>
 __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap& tm, const CoupArgs& ca,
@@ -293,10 +333,13 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
   __shared__ int s_cand[COUP_CHUNK];
   __shared__ float4 s_geo[COUP_CHUNK];  // candidate start point and edge, relative to the tile centre
   __shared__ float s_inv[COUP_CHUNK];   // 1 / |edge|^2
+  __shared__ double4 s_end[COUP_CHUNK]; // candidate end points X_s, X_s+1 in FP64
   __shared__ unsigned short s_wl[NT / 64][COUP_CHUNK];  // per-wave candidate lists
   __shared__ int s_cnt;
   __shared__ double s_red[NT / 64];
   __shared__ float s_redf[NT / 64];
+  __shared__ int s_ml[COUP_ML];  // membranes whose grown box meets the tile, ascending
+  __shared__ int s_mn, s_wc[NT / 64];
   __shared__ int b_seg[COUP_KEEP][NT];
   __shared__ double b_t[COUP_KEEP][NT];
   __shared__ double b_sd[COUP_KEEP][NT];
@@ -315,15 +358,48 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     const double rn16 = 7.5 * 1.41421356237309515, rn8 = 3.5 * 1.41421356237309515;
     const bool valid = (x < ca.nx) && (y < ca.ny);
     const double xt = tx * TILE2 + 0.5 * (TILE2 - 1), yt = ty * TILE2 + 0.5 * (TILE2 - 1);
-    double Itot = 0.0;
-    int kept = 0;  // membranes met by this tile (uniform)
-    for (int m = 0; m < md.K; m++) {
+    auto meets = [&](int m) {
       const double* bx = md.mbox + 8 * m;
       const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
       const double pxt = near_image(xt, cx, ca.nx);
       const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
       const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
-      if (!split && tile_misses(bx, pxt, pyt, hd, reach)) continue;
+      return split || !tile_misses(bx, pxt, pyt, hd, reach);
+    };
+    // the membranes this tile meets, tested in parallel and listed in
+    // ascending order (ordered compaction by ballots)
+    if (threadIdx.x == 0) s_mn = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < md.K; c0 += NT) {
+      const int m = c0 + threadIdx.x;
+      const bool mt = m < md.K && meets(m);
+      const unsigned long long mk = __ballot(mt);
+      if (lane == 0) s_wc[wv] = __popcll(mk);
+      __syncthreads();
+      int off = s_mn, tot = 0;
+      for (int w = 0; w < NT / 64; w++) {
+        off += w < wv ? s_wc[w] : 0;
+        tot += s_wc[w];
+      }
+      if (mt && off + __popcll(mk & below) < COUP_ML) s_ml[off + __popcll(mk & below)] = m;
+      __syncthreads();
+      if (threadIdx.x == 0) s_mn += tot;
+      __syncthreads();
+    }
+    const int nm = s_mn;
+    if (nm > COUP_ML && threadIdx.x == 0) md.status[1] = 1;
+    double Itot = 0.0;
+    // a node farther than r_cut from a ring lies on the side of its
+    // sub-tile centre (the segment between them meets no marker) when the
+    // band is wider than a sub-tile's reach
+    const bool shortcut = ca.r_cut > rn8 + 1.0;
+    for (int slot = 0; slot < min(nm, COUP_ML); slot++) {
+      const int m = s_ml[slot];
+      const double* bx = md.mbox + 8 * m;
+      const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
+      const double pxt = near_image(xt, cx, ca.nx);
+      const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
+      const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
       const int b = md.moff[m], n = md.moff[m + 1] - b;
       const double* X = md.X + 3 * b;
       const double o = bx[6];
@@ -333,7 +409,6 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
                          py >= bx[1] - reach && py <= bx[4] + reach;
       if (split) {
         // nodes of different images: each one searches the whole ring
-        const int slot = kept++;
         double d2b = 1e300, tb = 0.0;
         int sb = -1;
         if (inbox)
@@ -379,7 +454,6 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       }
       for (int l = threadIdx.x + KEEPD * NT; l < n; l += NT) dl = fminf(dl, seg_d2f(pcx, pcy, stab[l], sinv[l]));
       const float dminf = sqrtf(block_minf<NT>(dl, s_redf));
-      const int slot = kept++;
       if ((double)dminf > ca.r_cut + rn16 + 0.01) {
         // no node of the tile is within the band: all on the centre's side
         int cr = 0;
@@ -394,14 +468,15 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       }
       // every node's closest segment lies within dmin + 2 rn16 of the
       // centre.  Candidates go to LDS with their geometry relative to the
-      // tile centre in FP32; each node finds the FP32 minimum, then
-      // re-evaluates in FP64 every candidate within a margin that covers the
-      // FP32 rounding, so the FP64 closest segment (lowest index on ties) is
-      // the one chosen.
+      // tile centre in FP32 and their end points in FP64; each node finds
+      // the FP32 minimum, then re-evaluates in FP64 every candidate within a
+      // margin that covers the FP32 rounding, so the FP64 closest segment
+      // (lowest index on ties) is the one chosen.
       const float cull = dminf + (float)(2.0 * rn16) + 0.01f;
       const float fx = (float)(px - pxt), fy = (float)(py - pyt);
       double d2b = 1e300, tb = 0.0;
       int sb = -1;
+      int side = -1;  // side of a node beyond the band (-1: not decided that way)
       for (int c0 = 0; c0 < n; c0 += COUP_CHUNK) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
@@ -411,9 +486,11 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
           if (d <= cull * cull) {
             const int q = atomicAdd(&s_cnt, 1);
             const float4 sg = stab[l];
+            const int l1 = (l + 1 == n) ? 0 : l + 1;
             s_cand[q] = l;
             s_geo[q] = make_float4(sg.x - pcx, sg.y - pcy, sg.z, sg.w);
             s_inv[q] = sinv[l];
+            s_end[q] = make_double4(X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1]);
           }
         }
         __syncthreads();
@@ -443,21 +520,42 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           __builtin_amdgcn_wave_barrier();
-          if (inbox) {
+          // side of the sub-tile centre, from its exact closest segment
+          auto centre_side = [&]() {
+            double d2c, tc;
+            int sc;
+            wave_closest(s_wl[wv], cnt, s_cand, s_geo, s_inv, s_end, cwx, cwy, dw, pxt + cwx, pyt + cwy, d2c, sc,
+                         tc);
+            return ring_side(X, n, o, sc, tc, pxt + cwx, pyt + cwy) ? 1 : 0;
+          };
+          const float rb = (float)(ca.r_cut + rn8);
+          if (shortcut && dw - (2e-3f + 2e-5f * dw) > rb * rb) {
+            // the whole sub-tile lies beyond the band
+            side = centre_side();
+          } else {
             float bf = 3.0e38f;
-            for (int k = 0; k < cnt; k++) bf = fminf(bf, d2f(s_wl[wv][k], fx, fy));
+            if (inbox)
+              for (int k = 0; k < cnt; k++) bf = fminf(bf, d2f(s_wl[wv][k], fx, fy));
             const float tol = 2e-3f + 2e-5f * bf;
-            for (int k = 0; k < cnt; k++) {
-              const int q = s_wl[wv][k];
-              if (d2f(q, fx, fy) > bf + tol) continue;
-              const int s = s_cand[q];
-              const int s1 = (s + 1 == n) ? 0 : s + 1;
-              double tt;
-              const double d2 = seg_d2(px, py, X[3 * s], X[3 * s + 1], X[3 * s1], X[3 * s1 + 1], tt);
-              if (d2 < d2b || (d2 == d2b && s < sb)) {
-                d2b = d2;
-                sb = s;
-                tb = tt;
+            const float rc = (float)ca.r_cut;
+            const bool beyond = shortcut && inbox && bf - tol > rc * rc;
+            if (__ballot(beyond)) {
+              const int sc = centre_side();
+              if (beyond) side = sc;
+            }
+            if (inbox && !beyond) {
+              for (int k = 0; k < cnt; k++) {
+                const int q = s_wl[wv][k];
+                if (d2f(q, fx, fy) > bf + tol) continue;
+                const int s = s_cand[q];
+                const double4 e = s_end[q];
+                double tt;
+                const double d2 = seg_d2(px, py, e.x, e.y, e.z, e.w, tt);
+                if (d2 < d2b || (d2 == d2b && s < sb)) {
+                  d2b = d2;
+                  sb = s;
+                  tb = tt;
+                }
               }
             }
           }
@@ -478,9 +576,9 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
             const float dx = qx - sp * g4.z, dy = qy - sp * g4.w;
             if (dx * dx + dy * dy > bf + tol) continue;
             const int s = s_cand[q];
-            const int s1 = (s + 1 == n) ? 0 : s + 1;
+            const double4 e = s_end[q];
             double tt;
-            const double d2 = seg_d2(px, py, X[3 * s], X[3 * s + 1], X[3 * s1], X[3 * s1 + 1], tt);
+            const double d2 = seg_d2(px, py, e.x, e.y, e.z, e.w, tt);
             if (d2 < d2b || (d2 == d2b && s < sb)) {
               d2b = d2;
               sb = s;
@@ -492,7 +590,9 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       }
       double sd = 0.0;
       bool band = false;
-      if (inbox && sb >= 0) {
+      if (inbox && side >= 0) {
+        Itot += side ? 1.0 : 0.0;
+      } else if (inbox && sb >= 0) {
         const double d = sqrt(d2b);
         const bool in = ring_side(X, n, o, sb, tb, px, py);
         sd = in ? d : -d;
@@ -515,9 +615,13 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       // band node, kappa_c/(4 alpha) (psi - I) sech^2(d/2 alpha) dd/dX_v with
       // dd/dX_v = -sign(d) nhat w_v (nhat from the closest point to the
       // node, w_v the closest point's weight on vertex v)
-      if (kept > COUP_KEEP && threadIdx.x == 0) md.status[1] = 1;
+      if (nm > COUP_KEEP && threadIdx.x == 0) md.status[1] = 1;
+      const int nk = min(nm, COUP_KEEP);
+      bool anyband = false;
+      for (int slot = 0; slot < nk; slot++) anyband |= b_seg[slot][threadIdx.x] >= 0;
+      // psi only where a node of the wave is in a band
       double psi = 0.0;
-      if (valid) {
+      if (valid && __ballot(anyband)) {
         using L = Lattice<9>;
         psi = cur.rest(2, node);
         for (int i = 1; i < 9; i++) {
@@ -533,20 +637,15 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
           psi += (double)cur.template load<R>(2, dir, sn);
         }
       }
-      int slot = 0;
-      for (int m = 0; m < md.K && slot < COUP_KEEP; m++) {
-        const double* bx = md.mbox + 8 * m;
-        const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
-        const double pxt = near_image(xt, cx, ca.nx);
-        const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
-        const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
-        if (!split && tile_misses(bx, pxt, pyt, hd, reach)) continue;
-        const int myslot = slot++;
-        const int sb = b_seg[myslot][threadIdx.x];
+      for (int slot = 0; slot < nk; slot++) {
+        const int sb = b_seg[slot][threadIdx.x];
         if (sb < 0) continue;
-        const double sd = b_sd[myslot][threadIdx.x], tb = b_t[myslot][threadIdx.x];
+        const double sd = b_sd[slot][threadIdx.x], tb = b_t[slot][threadIdx.x];
         const double d = fabs(sd);
         if (d == 0.0) continue;
+        const int m = s_ml[slot];
+        const double* bx = md.mbox + 8 * m;
+        const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
         const int b = md.moff[m], n = md.moff[m + 1] - b;
         const double* X = md.X + 3 * b;
         const int s1 = (sb + 1 == n) ? 0 : sb + 1;
@@ -567,7 +666,7 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         atomicAdd((unsigned long long*)&B[1], (unsigned long long)to_fix(gy * tb));
       }
     }
-    __syncthreads();  // LDS band data is rewritten by the next tile
+    __syncthreads();  // LDS band data and lists are rewritten by the next tile
   }
 }
 
