@@ -168,7 +168,10 @@ int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps);
    workgroups are dealt to in turn, ring the rows held in registers (3, or 4
    to load the next row while the current ones are computed).  0 keeps the
    current value; seg = -1 returns to the automatic choice (as many
-   workgroups as fit on the GPU at once, so none waits for a second round). */
+   workgroups as fit on the GPU at once, so none waits for a second round),
+   nxcd = -1 to the automatic dealing (one domain for D2Q9, eight for the
+   D3Q19 tiles, whose halo lines are then shared inside one L2).  A value
+   reported as 0 means automatic.  Invalid values change nothing. */
 int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring);
 int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* ring);
 

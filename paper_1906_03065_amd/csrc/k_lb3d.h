@@ -163,12 +163,16 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
   __shared__ double s_m[3][3][T3H * T3H];  // moments ring: drho, phi, psi
   __shared__ double s_u[3][3][T3U * T3U];  // chemical-potential ring
   const int tid = threadIdx.x;
-  const int tx = blockIdx.x % ntilex, ty = blockIdx.x / ntilex;
+  // (tile, segment) of this workgroup: each XCD gets a contiguous run of
+  // the tile order, so tiles that share halo lines meet in one L2
+  int tl, sgm;
+  strip_segment((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)gridDim.x, (int)gridDim.y, P.nxcd, tl, sgm);
+  const int tx = tl % ntilex, ty = tl / ntilex;
   const int x0 = tx * T3, y0t = ty * T3;
-  const int z0 = (int)blockIdx.y * P.seg;
+  const int z0 = sgm * P.seg;
   const int z1 = min(z0 + P.seg, P.nz);
   const int K = (z1 - z0) + 4;
-  const int dir = (blockIdx.y & 1) ? -1 : 1;
+  const int dir = (sgm & 1) ? -1 : 1;
   const int zbase = dir > 0 ? z0 - 2 : z1 + 1;
   const int stamp = tstate[1];
   // this thread's interior node
@@ -177,20 +181,66 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
   const bool own = gx < P.nx && gy < P.ny;
   const int xw = wrap(gx, P.nx);
 
+  // tile flags of this thread's chemical-potential nodes and collision node,
+  // loaded one plane ahead so that every load of an iteration (moments,
+  // profile field, pull, spread force) is issued before the first wait
+  int fU[2] = {0, 0}, fC = 0;
   for (int k = 0; k < K; k++) {
     const int zk = zbase + dir * k;
     const int slot = k % 3;
-    // ---- L: stage the moments of plane zk on the 20 x 20 region
-    {
-      const int zr = halo_row(zk, P.nz, P.wall_z);
-      for (int q = tid; q < T3H * T3H; q += 256) {
+    // ---- issue: moments of plane zk on the 20 x 20 region
+    const int zr = halo_row(zk, P.nz, P.wall_z);
+    double mv[2][3];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int q = tid + 256 * r;
+      if (q < T3H * T3H) {
         const int hx = q % T3H, hy = q / T3H;
         const int xx = wrap(x0 - 2 + hx, P.nx);
         const int yy = halo_row(y0t - 2 + hy, P.ny, P.wall_y);
         const long long nd = ((long long)zr * P.ny + yy) * P.nx + xx;
-        s_m[slot][0][q] = M.d[nd];
-        s_m[slot][1][q] = M.phi[nd];
-        s_m[slot][2][q] = M.psi[nd];
+        mv[r][0] = M.d[nd];
+        mv[r][1] = M.phi[nd];
+        mv[r][2] = M.psi[nd];
+      }
+    }
+    // ---- issue: profile field of plane z_{k-1} where its tile is active
+    const int zq = halo_row(zk - dir, P.nz, P.wall_z);
+    double Iv[2] = {0.0, 0.0};
+    int nfU[2] = {0, 0};
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int q = tid + 256 * r;
+      if (q < T3U * T3U) {
+        const int xx = wrap(x0 - 1 + q % T3U, P.nx);
+        const int yy = halo_row(y0t - 1 + q / T3U, P.ny, P.wall_y);
+        if (k >= 2 && fU[r] == stamp) Iv[r] = Ifield[((long long)zq * P.ny + yy) * P.nx + xx];
+        if (k + 1 < K) nfU[r] = tflag[tile3(P, xx, yy, zr)];
+      }
+    }
+    // ---- issue: pull of plane z_{k-2} and its spread force
+    const int cz = zk - 2 * dir;
+    const bool doC = k >= 4 && own;
+    const bool cact = doC && fC == stamp;
+    const long long node = ((long long)cz * P.ny + gy) * P.nx + xw;
+    R pf[19], pg[19], ph[19];
+    double g0 = 0.0, h0 = 0.0;
+    long long fb[3] = {0, 0, 0};
+    if (doC) {
+      pull19(src, P, xw, gy, cz, pf, pg, ph, g0, h0);
+      if (cact)
+        for (int a3 = 0; a3 < 3; a3++) fb[a3] = fib[3 * node + a3];
+    }
+    int nfC = 0;
+    if (k >= 3 && k + 1 < K && own) nfC = tflag[tile3(P, xw, gy, zk - dir)];
+    // ---- L: moments to the ring
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int q = tid + 256 * r;
+      if (q < T3H * T3H) {
+        s_m[slot][0][q] = mv[r][0];
+        s_m[slot][1][q] = mv[r][1];
+        s_m[slot][2][q] = mv[r][2];
       }
     }
     __syncthreads();
@@ -198,8 +248,10 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
     if (k >= 2) {
       const int a = (k + 1) % 3, b = (k + 2) % 3, c = slot;  // planes z_{k-2}, z_{k-1}, z_k
       const int pa = dir > 0 ? a : c, pc = dir > 0 ? c : a;   // planes below / above in z
-      const int zq = halo_row(zk - dir, P.nz, P.wall_z);
-      for (int q = tid; q < T3U * T3U; q += 256) {
+#pragma unroll
+      for (int r = 0; r < 2; r++) {
+        const int q = tid + 256 * r;
+        if (q >= T3U * T3U) continue;
         const int ux_ = q % T3U, uy_ = q / T3U;
         const int hq = (uy_ + 1) * T3H + (ux_ + 1);  // centre in the 20 x 20 region
         double lap[3], ctr[3];
@@ -215,12 +267,8 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
           lap[f] = 6.0 * acc;
           ctr[f] = qc;
         }
-        const int xx = wrap(x0 - 1 + ux_, P.nx);
-        const int yy = halo_row(y0t - 1 + uy_, P.ny, P.wall_y);
-        double I = 0.0;
-        if (tflag[tile3(P, xx, yy, zq)] == stamp) I = Ifield[((long long)zq * P.ny + yy) * P.nx + xx];
         double mr, mp, ms;
-        chem_pot(P, ctr[0], ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
+        chem_pot(P, ctr[0], ctr[1], ctr[2], lap[0], lap[1], lap[2], Iv[r], mr, mp, ms);
         s_u[slot][0][q] = mr;
         s_u[slot][1][q] = mp;
         s_u[slot][2][q] = ms;
@@ -228,13 +276,10 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
     }
     __syncthreads();
     // ---- C: collide plane z_{k-2}
-    if (k >= 4 && own) {
-      const int cz = zk - 2 * dir;
+    if (doC) {
       const int a = (k + 1) % 3, b = (k + 2) % 3, c = slot;  // mu planes z_{k-3}, z_{k-2}, z_{k-1}
       const int pa = dir > 0 ? a : c, pc = dir > 0 ? c : a;
-      R pf[19], pg[19], ph[19];
-      double g0, h0, d, jx, jy, jz, phi, psi;
-      pull19(src, P, xw, gy, cz, pf, pg, ph, g0, h0);
+      double d, jx, jy, jz, phi, psi;
       moments19(pf, pg, ph, g0, h0, d, jx, jy, jz, phi, psi);
       const int uq = (iy + 1) * T3U + (ix + 1);
       double gr[3][3];
@@ -256,12 +301,10 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
       const double rho = 1.0 + d;
       double F[3];
       for (int a3 = 0; a3 < 3; a3++) F[a3] = -(rho * gr[0][a3] + phi * gr[1][a3] + psi * gr[2][a3]);
-      const long long node = ((long long)cz * P.ny + gy) * P.nx + xw;
-      if (tflag[tile3(P, xw, gy, cz)] == stamp) {
-        long long* fp = fib + 3 * node;
+      if (cact) {
         for (int a3 = 0; a3 < 3; a3++) {
-          F[a3] += from_fix(fp[a3]);
-          fp[a3] = 0;
+          F[a3] += from_fix(fb[a3]);
+          fib[3 * node + a3] = 0;
           force[3 * node + a3] = F[a3];
         }
       }
@@ -293,6 +336,9 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
         dst.template store<R>(2, i, node, ph[i]);
       }
     }
+    fU[0] = nfU[0];
+    fU[1] = nfU[1];
+    fC = nfC;
     __syncthreads();  // the rings are rewritten by the next plane
   }
 }

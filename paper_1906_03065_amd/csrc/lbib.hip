@@ -179,7 +179,7 @@ struct lbib_sim {
   std::vector<int> toff{0}, eoff{0}, vtoff{0}, coff{0};
   double r_cut = 0;
   int bx = 256, seg = 0;  // fused-kernel launch shape (seg 0: automatic)
-  int nxcd = 1;           // L2 domains workgroups are dealt to (1: plain strip order)
+  int nxcd = 0;           // L2 domains workgroups are dealt to (0: automatic, 1: plain order)
   int ring = 3;           // rows in the fused kernel's register ring (4: prefetch)
   lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
   // optional per-phase timing with HIP events on the stream
@@ -430,7 +430,7 @@ struct Engine2D final : lbib_sim {
     const int W = bx - 4;
     P.nstrip = (p.nx + W - 1) / W;
     P.nseg = (p.ny + P.seg - 1) / P.seg;
-    P.nxcd = nxcd;
+    P.nxcd = nxcd > 0 ? nxcd : 1;
     dim3 grid(P.nstrip * P.nseg);
     const int* tf = at<int>(L.tflag);
     const int* ts = at<int>(L.tstate);
@@ -599,6 +599,7 @@ struct Engine3D final : lbib_sim {
   void launch_lb(St src, St dst) {
     P.seg = pick_seg();
     P.nseg = (p.nz + P.seg - 1) / P.seg;
+    P.nxcd = nxcd > 0 ? nxcd : 8;
     Moments3 m3 = mom3();
     const int nb = (int)((N + 255) / 256);
     hipLaunchKernelGGL((k_mom3d<St, R>), dim3(nb), dim3(256), 0, stream, src, P, m3);
@@ -1218,13 +1219,14 @@ int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
   if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   if (ring != 0 && ring != 3 && ring != 4) return LBIB_EINVAL;
-  if (ring) s->ring = ring;
   if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 256) return LBIB_EINVAL;
-  if (seg < -1 || nxcd < 0 || nxcd > 64) return LBIB_EINVAL;
+  if (seg < -1 || nxcd < -1 || nxcd > 64) return LBIB_EINVAL;
+  if (ring) s->ring = ring;
   if (block_x) s->bx = block_x;
   if (seg > 0) s->seg = std::max(1, std::min(seg, s->D == 3 ? s->p.nz : s->p.ny));
   if (seg < 0) s->seg = 0;  // back to automatic
-  if (nxcd) s->nxcd = nxcd;
+  if (nxcd > 0) s->nxcd = nxcd;
+  if (nxcd < 0) s->nxcd = 0;  // back to automatic
   return LBIB_OK;
 }
 
