@@ -175,3 +175,23 @@ def test_fp64_parity_band_near_period(orc, wall_y):
             assert v < 1e-9, (n, k, v)
         assert marker_err(g, o, 1) < 1e-9
     assert g.check() == 0
+
+
+@pytest.mark.parametrize("r_cut", [4.0, 8.0])
+def test_fp64_parity_band_widths(orc, r_cut):
+    """Bands narrower than the default 17: with r_cut = 4 every band node of
+    a sub-tile is searched exactly (no node is provably beyond the band from
+    its sub-tile centre); with r_cut = 8 the capsule interior beyond the
+    band takes the side of its sub-tile centres, wave by wave and node by
+    node.  Both must give the oracle's profile and forces."""
+    w = W.c1(r_cut=r_cut, R=16.0, n_markers=100)
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    for n in (1, 40):
+        o.step(n - o.steps_done)
+        g.step(n - g.steps_done)
+        errs = compare(g, o)
+        _report(f"fp64 r_cut={r_cut} step {n}", errs)
+        for k, v in errs.items():
+            assert v < 1e-9, (n, k, v)
+        assert marker_err(g, o, 1) < 1e-9
