@@ -49,7 +49,7 @@ struct MemDev {
 struct TileMap {
   int* tflag;         // per tile: stamp of the last step it was active in
   int* tlist;         // active tiles of this step
-  int* tstate;        // [0] active-tile count, [1] stamp of this step
+  int* tstate;        // [0] active-tile count, [1] stamp of this step, [2] 3D tile counter
   int ntx, nty, ntz, tile;
 };
 
@@ -102,10 +102,13 @@ __device__ float block_minf(float v, float* sh) {
 
 // ---------------------------------------------------------------------------
 // start of a step: new stamp, empty active-tile list (one thread)
+// new step of the tile map: [0] active-tile count, [1] stamp, [2] counter
+// the 3D profile kernel's workgroups take tiles from
 __global__ void k_begin(int* tstate) {
   if (threadIdx.x == 0) {
     tstate[0] = 0;
     tstate[1] = tstate[1] + 1;
+    tstate[2] = 0;
   }
 }
 

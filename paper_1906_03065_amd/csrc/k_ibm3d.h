@@ -428,8 +428,10 @@ __device__ void block_argmin(double& d, int& i, double* sd, int* si) {
 }
 
 
-// one 8^3 tile per workgroup of 512 threads (grid-stride over the active
-// tiles); wave w holds the 4^3 sub-tile (w & 1, (w >> 1) & 1, w >> 2)
+// one 8^3 tile at a time per workgroup of 512 threads; resident workgroups
+// take the active tiles from a counter (tiles differ in cost by 20x, so a
+// fixed assignment leaves CUs idle at the end); wave w holds the 4^3
+// sub-tile (w & 1, (w >> 1) & 1, w >> 2)
 template <class St, typename R, int NT>
 __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMap tm, Coup3Args ca,
                                                    const float4* __restrict__ ttab,
@@ -445,6 +447,7 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
   __shared__ float s_redf[NT / 64];
   __shared__ int b_tri[COUP3_KEEP][NT];
   __shared__ double b_sd[COUP3_KEEP][NT];
+  __shared__ int s_li;
   const int ntl = tm.tstate[0];
   const double reach = ca.r_cut + 1.0;
   const double hd = 0.5 * TILE3 * 1.7320508075688772;  // tile half-diagonal (box tests)
@@ -460,7 +463,12 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
   // sub-tile centre relative to the tile centre
   const float cwf[3] = {(wv & 1) ? 2.0f : -2.0f, ((wv >> 1) & 1) ? 2.0f : -2.0f, (wv >> 2) ? 2.0f : -2.0f};
   const unsigned long long below = (1ull << lane) - 1ull;
-  for (int li = blockIdx.x; li < ntl; li += gridDim.x) {
+  for (;;) {
+    // the previous tile ended with a barrier, so s_li is free to rewrite
+    if (lt == 0) s_li = atomicAdd(&tm.tstate[2], 1);
+    __syncthreads();
+    const int li = s_li;
+    if (li >= ntl) break;  // uniform over the workgroup
     const int t = tm.tlist[li];
     const int tx = t % tm.ntx, ty = (t / tm.ntx) % tm.nty, tz = t / (tm.ntx * tm.nty);
     const int t0[3] = {tx * TILE3, ty * TILE3, tz * TILE3};
@@ -778,8 +786,12 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
     if (valid) Ifield[node] = Itot;
     if (ca.want_force) {
       if (kept > COUP3_KEEP && lt == 0) md.status[1] = 1;
+      bool anyband = false;
+      for (int k = 0; k < min(kept, COUP3_KEEP); k++) anyband |= b_tri[k][lt] >= 0;
+      // psi and the force pass only in waves that hold band nodes
       double psi = 0.0;
-      if (valid) {
+      const bool wband = __ballot(anyband) != 0ull;
+      if (valid && wband) {
         using L = Lattice<19>;
         psi = cur.rest(2, node);
         for (int i = 1; i < 19; i++) {
@@ -796,7 +808,7 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
         }
       }
       int slot = 0;
-      for (int m = 0; m < md.K && slot < COUP3_KEEP; m++) {
+      for (int m = 0; wband && m < md.K && slot < COUP3_KEEP; m++) {
         const TileGeo g = tile_geo(md.mbox + 8 * m, ct, xi, t0, dims, per, hd, reach, valid);
         if (g.miss) continue;
         const int my = slot++;

@@ -573,11 +573,27 @@ struct Engine3D final : lbib_sim {
     const int ncl = coff.back();
     hipLaunchKernelGGL(k_clusters3d, dim3((ncl * 64 + 255) / 256), dim3(256), 0, stream, md, mh,
                        (const float4*)at<float4>(L.ttab), at<float4>(L.ctab), ncl);
-    const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 4096);
+    // resident workgroups only: they take the active tiles from a counter
+    const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), coup3_slots());
     hipLaunchKernelGGL((k_coupling3d<St, R, COUP3_THREADS>), dim3(grid), dim3(COUP3_THREADS), 0, stream,
                        md, mh, tm, coup_args(want_force), (const float4*)at<float4>(L.ttab),
                        (const float4*)at<float4>(L.ctab), at<double>(L.Ifield), store(cur));
     return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+  }
+
+  // workgroups of the profile kernel resident at once (queried once)
+  int c3slots = 0;
+  int coup3_slots() {
+    if (c3slots > 0) return c3slots;
+    int per_cu = 0, ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_coupling3d<St, R, COUP3_THREADS>,
+                                                     COUP3_THREADS, 0) != hipSuccess ||
+        per_cu <= 0 || ncu <= 0)
+      return 1024;
+    c3slots = per_cu * ncu;
+    return c3slots;
   }
 
   // planes per workgroup: with seg = 0, one resident round of workgroups
@@ -1013,7 +1029,7 @@ int init_sim(lbib_sim* s, const lbib_params* p, const Layout& L, char* ws, hipSt
   // the tile flags start at 0 and the stamp at 1: no tile is active until a
   // membrane's tile pass flags it (a simulation without membranes never
   // reads the profile or force maps)
-  static const int stamp0[2] = {0, 1};
+  static const int stamp0[3] = {0, 1, 0};
   if (hipMemcpyAsync(s->ws + L.tstate, stamp0, sizeof(stamp0), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return LBIB_EHIP;
