@@ -185,7 +185,14 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
   // loaded one plane ahead so that every load of an iteration (moments,
   // profile field, pull, spread force) is issued before the first wait
   int fU[2] = {0, 0}, fC = 0;
-  for (int k = 0; k < K; k++) {
+  // the populations of plane z_j are pulled at iteration j + 1 into register
+  // set j & 1 and collided at iteration j + 2: the next plane's pull is in
+  // flight while the current one is computed
+  R pf[2][19], pg[2][19], ph[2][19];
+  double g0[2] = {0.0, 0.0}, h0[2] = {0.0, 0.0};
+  auto body = [&](auto set_c, int k) {
+    constexpr int S = decltype(set_c)::value;  // set collided now (k & 1)
+    constexpr int SN = S ^ 1;                  // set pulled now
     const int zk = zbase + dir * k;
     const int slot = k % 3;
     // ---- issue: moments of plane zk on the 20 x 20 region
@@ -218,21 +225,19 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
         if (k + 1 < K) nfU[r] = tflag[tile3(P, xx, yy, zr)];
       }
     }
-    // ---- issue: pull of plane z_{k-2} and its spread force
+    // ---- issue: pull of plane z_{k-1} (collided next iteration), the
+    // spread force of plane z_{k-2} (collided now)
+    const bool pnext = k >= 3 && k + 1 < K && own;
+    if (pnext) pull19(src, P, xw, gy, zk - dir, pf[SN], pg[SN], ph[SN], g0[SN], h0[SN]);
     const int cz = zk - 2 * dir;
     const bool doC = k >= 4 && own;
     const bool cact = doC && fC == stamp;
     const long long node = ((long long)cz * P.ny + gy) * P.nx + xw;
-    R pf[19], pg[19], ph[19];
-    double g0 = 0.0, h0 = 0.0;
     long long fb[3] = {0, 0, 0};
-    if (doC) {
-      pull19(src, P, xw, gy, cz, pf, pg, ph, g0, h0);
-      if (cact)
-        for (int a3 = 0; a3 < 3; a3++) fb[a3] = fib[3 * node + a3];
-    }
+    if (cact)
+      for (int a3 = 0; a3 < 3; a3++) fb[a3] = fib[3 * node + a3];
     int nfC = 0;
-    if (k >= 3 && k + 1 < K && own) nfC = tflag[tile3(P, xw, gy, zk - dir)];
+    if (pnext) nfC = tflag[tile3(P, xw, gy, zk - dir)];
     // ---- L: moments to the ring
 #pragma unroll
     for (int r = 0; r < 2; r++) {
@@ -279,8 +284,13 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
     if (doC) {
       const int a = (k + 1) % 3, b = (k + 2) % 3, c = slot;  // mu planes z_{k-3}, z_{k-2}, z_{k-1}
       const int pa = dir > 0 ? a : c, pc = dir > 0 ? c : a;
+      R* pfc = pf[S];
+      R* pgc = pg[S];
+      R* phc = ph[S];
+      double& g0c = g0[S];
+      double& h0c = h0[S];
       double d, jx, jy, jz, phi, psi;
-      moments19(pf, pg, ph, g0, h0, d, jx, jy, jz, phi, psi);
+      moments19(pfc, pgc, phc, g0c, h0c, d, jx, jy, jz, phi, psi);
       const int uq = (iy + 1) * T3U + (ix + 1);
       double gr[3][3];
 #pragma unroll
@@ -308,38 +318,42 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
           force[3 * node + a3] = F[a3];
         }
       }
-      collide19(P, pf, pg, ph, g0, h0, d, jx, jy, jz, phi, psi, s_u[b][1][uq], s_u[b][2][uq], F[0], F[1],
+      collide19(P, pfc, pgc, phc, g0c, h0c, d, jx, jy, jz, phi, psi, s_u[b][1][uq], s_u[b][2][uq], F[0], F[1],
                 F[2]);
       if constexpr (St::kQuantized) {
         R ef = 0, eg = 0, eh = 0;
 #pragma unroll
         for (int i = 1; i < 19; i++) {
-          const R qf = dst.quantize(pf[i]), qg = dst.quantize(pg[i]), qh = dst.quantize(ph[i]);
-          ef += pf[i] - qf;
-          eg += pg[i] - qg;
-          eh += ph[i] - qh;
-          pf[i] = qf;
-          pg[i] = qg;
-          ph[i] = qh;
+          const R qf = dst.quantize(pfc[i]), qg = dst.quantize(pgc[i]), qh = dst.quantize(phc[i]);
+          ef += pfc[i] - qf;
+          eg += pgc[i] - qg;
+          eh += phc[i] - qh;
+          pfc[i] = qf;
+          pgc[i] = qg;
+          phc[i] = qh;
         }
-        pf[0] += ef;
-        g0 += (double)eg;
-        h0 += (double)eh;
+        pfc[0] += ef;
+        g0c += (double)eg;
+        h0c += (double)eh;
       }
-      dst.template store<R>(0, 0, node, pf[0]);
-      dst.store_rest(1, node, g0);
-      dst.store_rest(2, node, h0);
+      dst.template store<R>(0, 0, node, pfc[0]);
+      dst.store_rest(1, node, g0c);
+      dst.store_rest(2, node, h0c);
 #pragma unroll
       for (int i = 1; i < 19; i++) {
-        dst.template store<R>(0, i, node, pf[i]);
-        dst.template store<R>(1, i, node, pg[i]);
-        dst.template store<R>(2, i, node, ph[i]);
+        dst.template store<R>(0, i, node, pfc[i]);
+        dst.template store<R>(1, i, node, pgc[i]);
+        dst.template store<R>(2, i, node, phc[i]);
       }
     }
     fU[0] = nfU[0];
     fU[1] = nfU[1];
     fC = nfC;
     __syncthreads();  // the rings are rewritten by the next plane
+  };
+  for (int k = 0; k < K; k += 2) {
+    body(std::integral_constant<int, 0>{}, k);
+    if (k + 1 < K) body(std::integral_constant<int, 1>{}, k + 1);
   }
 }
 
