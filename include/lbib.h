@@ -163,8 +163,8 @@ int lbib_timing_enable(lbib_sim* s, int on);
 int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps);
 
 /* Launch shape of the fused lattice kernel (a tuning knob; results do not
-   depend on it): block_x lanes per workgroup (64, 128 or 256; block_x - 4
-   interior columns), seg rows per workgroup, nxcd the number of L2 domains
+   depend on it): block_x lanes per workgroup (64, 128, 192 or 256; block_x
+   - 4 interior columns), seg rows per workgroup, nxcd the number of L2 domains
    workgroups are dealt to in turn, ring the rows held in registers (3, or 4
    to load the next row while the current ones are computed).  0 keeps the
    current value; seg = -1 returns to the automatic choice (as many
@@ -216,7 +216,7 @@ int lbib_batch_create(int n, const lbib_params* params, void* dev_workspace, siz
 int lbib_batch_member(lbib_sim* batch, int k, lbib_sim** member);
 
 /* Lattice-kernel shape of size class size_class (0: width <= 128, 1:
-   <= 256, 2: wider; -1: all): lanes per workgroup (64, 128, 256), rows per
+   <= 256, 2: wider; -1: all): lanes per workgroup (64, 128, 192, 256), rows per
    work item (-1: automatic, one resident round of the class's items) and
    register ring depth (3 or 4); 0 keeps a value.  get_launch also returns
    the number of members in the class, and the rows in use once the batch

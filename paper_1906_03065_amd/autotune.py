@@ -16,7 +16,7 @@ import time
 
 from . import lbib
 
-CANDIDATES = [(bx, seg, ring) for bx in (64, 128, 256) for ring in (3, 4) for seg in (-1, 16, 48)]
+CANDIDATES = [(bx, seg, ring) for bx in (64, 128, 192, 256) for ring in (3, 4) for seg in (-1, 16, 48)]
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbib", "autotune.json")
 
 

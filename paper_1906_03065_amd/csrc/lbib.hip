@@ -399,10 +399,12 @@ struct Engine2D final : lbib_sim {
   const void* lb_kernel() const {
     if (ring == 4) {
       if (bx == 128) return (const void*)&k_lb2d<St, R, 128, 4, 2>;
+      if (bx == 192) return (const void*)&k_lb2d<St, R, 192, 4, 2>;
       if (bx == 256) return (const void*)&k_lb2d<St, R, 256, 4, 2>;
       return (const void*)&k_lb2d<St, R, 64, 4, 2>;
     }
     if (bx == 128) return (const void*)&k_lb2d<St, R, 128, 3, 3>;
+    if (bx == 192) return (const void*)&k_lb2d<St, R, 192, 3, 3>;
     if (bx == 256) return (const void*)&k_lb2d<St, R, 256, 3, 3>;
     return (const void*)&k_lb2d<St, R, 64, 3, 3>;
   }
@@ -421,8 +423,10 @@ struct Engine2D final : lbib_sim {
         per_cu <= 0 || ncu <= 0)
       return std::max(4, std::min(p.ny, 16));
     const long long slots = (long long)per_cu * ncu;
-    const long long rows = (p.ny * nstrip + slots - 1) / slots;
-    return (int)std::max(4LL, std::min<long long>(p.ny, rows));
+    long long rows = std::max(4LL, std::min<long long>(p.ny, (p.ny * nstrip + slots - 1) / slots));
+    // rounding the segment count up can still leave a few workgroups over
+    while (rows < p.ny && nstrip * ((p.ny + rows - 1) / rows) > slots) rows++;
+    return (int)rows;
   }
 
   void launch_lb(St src, St dst) {
@@ -443,10 +447,12 @@ struct Engine2D final : lbib_sim {
                      If, fib, frc)
     if (ring == 4) {
       if (bx == 128) LB_LAUNCH(128, 4, 2);
+      else if (bx == 192) LB_LAUNCH(192, 4, 2);
       else if (bx == 256) LB_LAUNCH(256, 4, 2);
       else LB_LAUNCH(64, 4, 2);
     } else {
       if (bx == 128) LB_LAUNCH(128, 3, 3);
+      else if (bx == 192) LB_LAUNCH(192, 3, 3);
       else if (bx == 256) LB_LAUNCH(256, 3, 3);
       else LB_LAUNCH(64, 3, 3);
     }
@@ -762,12 +768,14 @@ struct BatchEngine2D final : lbib_sim {
     const int bx = cls_bx[c];
     if (cls_ring[c] == 4) {
       if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 4, 2>;
+      if (bx == 192) return (const void*)&kb_lb2d<St, R, 192, 4, 2>;
       if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 4, 2>;
       return (const void*)&kb_lb2d<St, R, 64, 4, 2>;
     }
     // (the persistent loop needs a few more registers than the single
     // kernel: ring 3 runs at two waves per SIMD too, without spills)
     if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 3, 2>;
+    if (bx == 192) return (const void*)&kb_lb2d<St, R, 192, 3, 2>;
     if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 3, 2>;
     return (const void*)&kb_lb2d<St, R, 64, 3, 2>;
   }
@@ -889,10 +897,12 @@ struct BatchEngine2D final : lbib_sim {
   hipLaunchKernelGGL((kb_lb2d<St, R, BXV, NSV, WPEV>), dim3(lgrid[c]), dim3(BXV), 0, stream, Tc, cmc, bp, ncm[c], parity)
       if (cls_ring[c] == 4) {
         if (cls_bx[c] == 128) KB_LAUNCH(128, 4, 2);
+        else if (cls_bx[c] == 192) KB_LAUNCH(192, 4, 2);
         else if (cls_bx[c] == 256) KB_LAUNCH(256, 4, 2);
         else KB_LAUNCH(64, 4, 2);
       } else {
         if (cls_bx[c] == 128) KB_LAUNCH(128, 3, 2);
+        else if (cls_bx[c] == 192) KB_LAUNCH(192, 3, 2);
         else if (cls_bx[c] == 256) KB_LAUNCH(256, 3, 2);
         else KB_LAUNCH(64, 3, 2);
       }
@@ -1235,7 +1245,7 @@ int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
   if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   if (ring != 0 && ring != 3 && ring != 4) return LBIB_EINVAL;
-  if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 256) return LBIB_EINVAL;
+  if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 192 && block_x != 256) return LBIB_EINVAL;
   if (seg < -1 || nxcd < -1 || nxcd > 64) return LBIB_EINVAL;
   if (ring) s->ring = ring;
   if (block_x) s->bx = block_x;
@@ -1557,7 +1567,7 @@ int lbib_batch_member(lbib_sim* batch, int k, lbib_sim** member) {
 int lbib_batch_set_launch(lbib_sim* batch, int size_class, int block_x, int seg, int ring) {
   if (!batch || !batch->is_batch()) return LBIB_EINVAL;
   if (size_class < -1 || size_class >= BatchEngine2D::NCLS) return LBIB_EINVAL;
-  if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 256) return LBIB_EINVAL;
+  if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 192 && block_x != 256) return LBIB_EINVAL;
   if (ring != 0 && ring != 3 && ring != 4) return LBIB_EINVAL;
   if (seg < -1) return LBIB_EINVAL;
   BatchEngine2D* b = static_cast<BatchEngine2D*>(batch);
