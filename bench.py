@@ -189,6 +189,23 @@ def main():
                      "kernel_share_of_step": round(lb_ms / (el * 1e3 / args.steps), 4),
                      "launch": g.get_launch()},
     }
+    if not d3:
+        # the same lattice with the regions away from the membranes on a second
+        # stream beside the membrane kernels (a scheduling option, bitwise the
+        # same results); the roofline above stays the single-stream kernel's
+        g.set_overlap(1)
+        k2 = max(args.steps // 4, 1)
+        g.step(max(args.warmup // 4, 1))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        g.step(k2)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t2
+        g.set_overlap(0)
+        out["overlap_on"] = {"value": round(N * k2 / el2 / 1e6, 2), "unit": "MLUPS",
+                             "ms_per_step": round(el2 * 1e3 / k2, 6), "steps": k2,
+                             "what": "lattice regions away from the membranes on a second stream beside "
+                                     "the membrane kernels (lbib_set_overlap)"}
     if not args.no_cpu:
         if d3:
             # the oracle's brute-force mesh distances make a 256^3 step take

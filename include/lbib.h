@@ -175,6 +175,20 @@ int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps);
 int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring);
 int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* ring);
 
+/* D2Q9 step order (a scheduling knob; results are bitwise the same either
+   way): with on = 1 the lattice regions whose workgroups read no membrane
+   field (no active tile within their rows and lanes) are updated on a
+   second stream, created by the library on first use and owned by the
+   handle, while the profile and force kernels of Sec. 3.3 run on the
+   simulation's stream; the regions next to the membranes follow them, and
+   the step ends with the simulation's stream waiting for the second one.
+   on = 0 (the default) runs the whole step on the simulation's stream;
+   on = -1 selects the library's choice, which is 0 (the passes share the
+   memory bandwidth, so the gain is a few per cent).  No effect on D3Q19
+   simulations.  Batch handles and members return LBIB_EINVAL, as do other
+   values of on. */
+int lbib_set_overlap(lbib_sim* s, int on);
+
 /* Number of completed steps. */
 long long lbib_steps_done(const lbib_sim* s);
 

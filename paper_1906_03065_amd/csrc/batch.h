@@ -133,7 +133,8 @@ __global__ __launch_bounds__(BX, WPE) void kb_lb2d(const BMember<St>* T, const i
     double* force = T[i].force;
     int strip, sgm;
     strip_segment(item - bpre[q], P.nstrip, P.nseg, 1, strip, sgm);
-    lb2d_run<St, R, BX, NS>(src, dst, P, strip, sgm, tflag, tstate, Ifield, fib, force);
+    const int y0 = sgm * P.seg, y1 = min(y0 + P.seg, P.ny);
+    lb2d_run<St, R, BX, NS>(src, dst, P, strip, y0, y1, (sgm & 1) ? -1 : 1, tflag, tstate, Ifield, fib, force);
     __syncthreads();  // the rings are reused by the next item
   }
 }

@@ -43,6 +43,9 @@ struct LBParams {
   int seg;                                   // rows (2D) or planes (3D) per workgroup
   int nstrip, nseg;                          // workgroup grid: strips x segments
   int nxcd;                                  // XCDs the dispatcher deals workgroups to
+  int mode;                                  // 2D pass: 0 all, 1 regions without active tiles,
+                                             // 2 regions with active tiles (in pieces)
+  int seg2, npiece;                          // pass 2: rows per piece, pieces per segment
 };
 
 // Workgroup -> (strip, segment).  The dispatcher deals consecutive
@@ -187,10 +190,10 @@ __device__ __forceinline__ void moments9(const R* pf, const R* pg, const R* ph, 
 // sized for.
 // One (strip, segment) of the lattice: the whole march of a workgroup.
 template <class St, typename R, int BX, int NS>
-__device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBParams& P, int strip, int sgm,
-                                         const int* __restrict__ tflag, const int* __restrict__ tstate,
-                                         const double* __restrict__ Ifield, long long* __restrict__ fib,
-                                         double* __restrict__ force) {
+__device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBParams& P, int strip, int y0,
+                                         int y1, int dir, const int* __restrict__ tflag,
+                                         const int* __restrict__ tstate, const double* __restrict__ Ifield,
+                                         long long* __restrict__ fib, double* __restrict__ force) {
   static_assert(NS == 3 || NS == 4, "ring of three or four rows");
   constexpr int W = BX - 4;
   __shared__ double s_m[3][3][BX];  // moment ring [slot][drho, phi, psi][lane]
@@ -201,13 +204,7 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
   const int xc = strip * W - 2 + j;
   const int x = wrap(xc, P.nx);
   const bool interior = (j >= 2) && (j < BX - 2) && (xc < P.nx);
-  const int y0 = sgm * P.seg;
-  const int y1 = min(y0 + P.seg, P.ny);
   const int K = (y1 - y0) + 4;
-  // even segments march up, odd ones down: neighbouring segments then read
-  // the rows they share at the same time (both at their start or both at
-  // their end)
-  const int dir = (sgm & 1) ? -1 : 1;
   const int rbase = dir > 0 ? y0 - 2 : y1 + 1;
 
   const int stamp = tstate[1];  // tiles flagged with this step's stamp are active
@@ -262,14 +259,18 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
     // ---- U: chemical potentials on the previous row -> ring slot k%3
     if (k >= 2 && j >= 1 && j < BX - 1) {
       const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // rows r-2dir, r-dir, r
+      // south (row - 1) and north (row + 1) rows: the sums run in the same
+      // geometric order whichever way the segment marches, so every node
+      // gets the same rounding under any launch shape
+      const int so = dir > 0 ? a : c, no = dir > 0 ? c : a;
       double lap[3], ctr[3];
 #pragma unroll
       for (int f = 0; f < 3; f++) {
         const double q = s_m[b][f][j];
-        const double n4 = (s_m[b][f][j - 1] - q) + (s_m[b][f][j + 1] - q) + (s_m[a][f][j] - q) +
-                          (s_m[c][f][j] - q);
-        const double n8 = (s_m[a][f][j - 1] - q) + (s_m[a][f][j + 1] - q) +
-                          (s_m[c][f][j - 1] - q) + (s_m[c][f][j + 1] - q);
+        const double n4 = (s_m[b][f][j - 1] - q) + (s_m[b][f][j + 1] - q) + (s_m[so][f][j] - q) +
+                          (s_m[no][f][j] - q);
+        const double n8 = (s_m[so][f][j - 1] - q) + (s_m[so][f][j + 1] - q) +
+                          (s_m[no][f][j - 1] - q) + (s_m[no][f][j + 1] - q);
         // lap q = 6 sum_i w_i (q(x + c_i) - q(x)) with the D2Q9 weights
         lap[f] = (2.0 / 3.0) * n4 + (1.0 / 6.0) * n8;
         ctr[f] = q;
@@ -355,6 +356,26 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
   }
 }
 
+// does the (strip, rows [y0, y1)) region of a workgroup read any membrane
+// field, i.e. does an active tile cover a (row, lane) whose profile field or
+// spread force it reads?  (rows y0-1 .. y1 of lanes 1 .. BX-2; every thread
+// of the workgroup must call it)
+template <int BX>
+__device__ __forceinline__ bool region_active(const LBParams& P, const int* __restrict__ tflag, int stamp,
+                                              int strip, int y0, int y1) {
+  const int j = threadIdx.x;
+  const int x = wrap(strip * (BX - 4) - 2 + j, P.nx);
+  bool a = false;
+  if (j >= 1 && j < BX - 1)
+    for (int r = y0 - 1; r <= y1; r++) a |= tflag[(fd_row(r, P.ny, P.wall_y) / P.tile) * P.ntx + x / P.tile] == stamp;
+  return __syncthreads_or(a) != 0;
+}
+
+// The fused step over the whole lattice (mode 0), or split in two passes:
+// mode 1 takes the (strip, segment) regions that read no membrane field and
+// may run beside the membrane kernels; mode 2 takes the others after them,
+// each segment cut into pieces of seg2 rows so that the few regions near the
+// membranes still fill the GPU.
 template <class St, typename R, int BX, int NS, int WPE>
 __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
                                                   const int* __restrict__ tflag,
@@ -362,9 +383,27 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
                                                   const double* __restrict__ Ifield,
                                                   long long* __restrict__ fib,
                                                   double* __restrict__ force) {
-  int strip, sgm;
-  strip_segment((int)blockIdx.x, P.nstrip, P.nseg, P.nxcd, strip, sgm);
-  lb2d_run<St, R, BX, NS>(src, dst, P, strip, sgm, tflag, tstate, Ifield, fib, force);
+  int strip, sgm, piece = 0;
+  if (P.mode == 2) {
+    piece = (int)blockIdx.x % P.npiece;
+    const int rg = (int)blockIdx.x / P.npiece;
+    strip = rg % P.nstrip;
+    sgm = rg / P.nstrip;
+  } else {
+    strip_segment((int)blockIdx.x, P.nstrip, P.nseg, P.nxcd, strip, sgm);
+  }
+  int y0 = sgm * P.seg, y1 = min(y0 + P.seg, P.ny);
+  if (P.mode != 0 && region_active<BX>(P, tflag, tstate[1], strip, y0, y1) != (P.mode == 2)) return;
+  // even segments (pieces) march up, odd ones down: neighbours then read the
+  // rows they share at the same time (both at their start or both at their end)
+  int dir = (sgm & 1) ? -1 : 1;
+  if (P.mode == 2) {
+    y0 += piece * P.seg2;
+    if (y0 >= y1) return;
+    y1 = min(y0 + P.seg2, y1);
+    dir = (piece & 1) ? -1 : 1;
+  }
+  lb2d_run<St, R, BX, NS>(src, dst, P, strip, y0, y1, dir, tflag, tstate, Ifield, fib, force);
 }
 
 }  // namespace lb

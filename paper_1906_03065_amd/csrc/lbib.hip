@@ -181,6 +181,8 @@ struct lbib_sim {
   int bx = 256, seg = 0;  // fused-kernel launch shape (seg 0: automatic)
   int nxcd = 0;           // L2 domains workgroups are dealt to (0: automatic, 1: plain order)
   int ring = 3;           // rows in the fused kernel's register ring (4: prefetch)
+  int overlap = 0;        // 2D: lattice regions away from the membranes beside the
+                          // membrane kernels (0 off, 1 on)
   lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
   // optional per-phase timing with HIP events on the stream
   int timing = 0;  // bit mask of timed phases
@@ -197,18 +199,19 @@ struct lbib_sim {
     }
     return ev_pool[ev_used++];
   }
-  // begin a timed phase: returns the start event (or null when not timing)
-  hipEvent_t tbeg(int phase) {
+  // begin a timed phase on stream s (default: the simulation's stream):
+  // returns the start event (or null when not timing)
+  hipEvent_t tbeg(int phase, hipStream_t s = nullptr) {
     if (!(timing >> phase & 1)) return nullptr;
     hipEvent_t e = ev();
-    if (e) (void)hipEventRecord(e, stream);
+    if (e) (void)hipEventRecord(e, s ? s : stream);
     return e;
   }
-  void tend(int phase, hipEvent_t start) {
+  void tend(int phase, hipEvent_t start, hipStream_t s = nullptr) {
     if (!start) return;
     hipEvent_t e = ev();
     if (!e) return;
-    (void)hipEventRecord(e, stream);
+    (void)hipEventRecord(e, s ? s : stream);
     ev_open.push_back({phase, {start, e}});
   }
   int timing_flush() {
@@ -361,6 +364,9 @@ void fill_params(LBParams& P, const lbib_params& p, const Layout& L, long long N
   P.nty = L.nty;
   P.tile = L.tile;
   P.seg = seg;
+  P.mode = 0;
+  P.seg2 = 0;
+  P.npiece = 1;
 }
 
 template <class St, typename R>
@@ -382,18 +388,50 @@ struct Engine2D final : lbib_sim {
     return c;
   }
 
-  int coupling(int want_force) override {
-    if (K == 0) return LBIB_OK;
+  // boxes, segment table and active-tile map at X(t)
+  void tiles_pass() {
     MemDev md = memdev();
     TileMap tm = tilemap();
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
     hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, 1, p.wall_y,
                        0, 2, r_cut + 3.0);
+  }
+  // profile field and coupling forces on the active tiles
+  void profile_pass(int want_force) {
     const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 2048);
     hipLaunchKernelGGL((k_coupling2d<St, R, COUP_THREADS>), dim3(grid), dim3(COUP_THREADS), 0, stream,
-                       md, tm, coup_args(want_force), at<double>(L.Ifield), store(cur));
+                       memdev(), tilemap(), coup_args(want_force), at<double>(L.Ifield), store(cur));
+  }
+  int coupling(int want_force) override {
+    if (K == 0) return LBIB_OK;
+    tiles_pass();
+    profile_pass(want_force);
     return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
   }
+
+  // second stream and events of the overlapped step (created on first use)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int ensure_side() {
+    if (side) return LBIB_OK;
+    if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) {
+      side = nullptr;
+      return LBIB_EHIP;
+    }
+    if (hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)
+      return LBIB_EHIP;
+    return LBIB_OK;
+  }
+  ~Engine2D() override {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+  }
+  // overlap the lattice regions away from the membranes with the membrane
+  // kernels?  Only on request: the two lattice passes then share the memory
+  // bandwidth with each other and with the membrane kernels
+  bool split_step() const { return K > 0 && overlap > 0; }
 
   // kernel variant for the current (bx, ring)
   const void* lb_kernel() const {
@@ -429,13 +467,18 @@ struct Engine2D final : lbib_sim {
     return (int)rows;
   }
 
-  void launch_lb(St src, St dst) {
+  // the fused kernel on stream s over the whole lattice (mode 0), the
+  // regions that read no membrane field (1) or the others in pieces (2)
+  void launch_lb(St src, St dst, hipStream_t s, int mode) {
     P.seg = pick_seg();
     const int W = bx - 4;
     P.nstrip = (p.nx + W - 1) / W;
     P.nseg = (p.ny + P.seg - 1) / P.seg;
     P.nxcd = nxcd > 0 ? nxcd : 1;
-    dim3 grid(P.nstrip * P.nseg);
+    P.mode = mode;
+    P.npiece = mode == 2 ? (P.seg + 5) / 6 : 1;  // pieces of about five rows
+    P.seg2 = (P.seg + P.npiece - 1) / P.npiece;
+    dim3 grid(P.nstrip * P.nseg * P.npiece);
     const int* tf = at<int>(L.tflag);
     const int* ts = at<int>(L.tstate);
     const double* If = at<double>(L.Ifield);
@@ -443,8 +486,8 @@ struct Engine2D final : lbib_sim {
     double* frc = at<double>(L.force);
     // (lanes, ring depth, waves per SIMD) variants of the fused kernel
 #define LB_LAUNCH(BXV, NSV, WPEV)                                                                  \
-  hipLaunchKernelGGL((k_lb2d<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, stream, src, dst, P, tf, ts, \
-                     If, fib, frc)
+  hipLaunchKernelGGL((k_lb2d<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, If, fib, \
+                     frc)
     if (ring == 4) {
       if (bx == 128) LB_LAUNCH(128, 4, 2);
       else if (bx == 192) LB_LAUNCH(192, 4, 2);
@@ -462,10 +505,22 @@ struct Engine2D final : lbib_sim {
   int step() override {
     MemDev md = memdev();
     const int mb16 = (16 * M + 255) / 256;  // sixteen lanes per marker
+    const bool split = split_step();
+    if (split && ensure_side() != LBIB_OK) return LBIB_EHIP;
     if (K > 0) {
       hipEvent_t t0 = tbeg(1);
-      int rc = coupling(1);
-      if (rc) return rc;
+      tiles_pass();
+      if (split) {
+        // the regions away from the membranes need only the tile map: they
+        // run on the second stream beside the profile and force kernels
+        if (hipEventRecord(ev_fork, stream) != hipSuccess || hipStreamWaitEvent(side, ev_fork, 0) != hipSuccess)
+          return LBIB_EHIP;
+        hipEvent_t ta = tbeg(0, side);
+        launch_lb(store(cur), store(1 - cur), side, 1);
+        tend(0, ta, side);
+        if (hipEventRecord(ev_join, side) != hipSuccess) return LBIB_EHIP;
+      }
+      profile_pass(1);
       tend(1, t0);
       t0 = tbeg(2);
       hipLaunchKernelGGL(k_forcespread2d, dim3(mb16), dim3(256), 0, stream, md, at<long long>(L.fib), p.nx,
@@ -473,8 +528,9 @@ struct Engine2D final : lbib_sim {
       tend(2, t0);
     }
     hipEvent_t t1 = tbeg(0);
-    launch_lb(store(cur), store(1 - cur));
+    launch_lb(store(cur), store(1 - cur), stream, split ? 2 : 0);
     tend(0, t1);
+    if (split && hipStreamWaitEvent(stream, ev_join, 0) != hipSuccess) return LBIB_EHIP;
     if (K > 0) {
       hipEvent_t t2 = tbeg(3);
       hipLaunchKernelGGL((k_interp2d<St, R>), dim3(mb16), dim3(256), 0, stream, md, store(1 - cur), P,
@@ -1253,6 +1309,12 @@ int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
   if (seg < 0) s->seg = 0;  // back to automatic
   if (nxcd > 0) s->nxcd = nxcd;
   if (nxcd < 0) s->nxcd = 0;  // back to automatic
+  return LBIB_OK;
+}
+
+int lbib_set_overlap(lbib_sim* s, int on) {
+  if (!s || s->is_batch() || on < -1 || on > 1) return LBIB_EINVAL;
+  s->overlap = on > 0 ? 1 : 0;
   return LBIB_OK;
 }
 

@@ -68,6 +68,7 @@ SIGNATURES = [
     ("lbib_timing_enable", C.c_int, [_vp, C.c_int]),
     ("lbib_timing_read", C.c_int, [_vp, _dp, C.c_int, _ip]),
     ("lbib_set_launch", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("lbib_set_overlap", C.c_int, [_vp, C.c_int]),
     ("lbib_get_launch", C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     ("lbib_steps_done", C.c_longlong, [_vp]),
     ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
@@ -279,6 +280,12 @@ class Sim:
     def set_launch(self, block_x=0, seg=0, nxcd=0, ring=0):
         _chk("lbib_set_launch", lib().lbib_set_launch(self.h, int(block_x), int(seg), int(nxcd),
                                                       int(ring)))
+
+    def set_overlap(self, on: int = -1):
+        """D2Q9: 1 runs the lattice regions away from the membranes on a second
+        stream beside the membrane kernels, 0 (the default) keeps one stream,
+        -1 lets the library choose (currently 0)."""
+        _chk("lbib_set_overlap", lib().lbib_set_overlap(self.h, int(on)))
 
     def get_launch(self):
         a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()

@@ -43,8 +43,10 @@ def _same(a, b):
         if not np.array_equal(fa[k], fb[k]):
             return False, k, float(np.abs(fa[k] - fb[k]).max())
     for i in range(len(a.mem_sizes)):
-        if not np.array_equal(a.membrane(i)["X"], b.membrane(i)["X"]):
-            return False, f"X{i}", float(np.abs(a.membrane(i)["X"] - b.membrane(i)["X"]).max())
+        ma, mb = a.membrane(i), b.membrane(i)
+        for q in ("X", "U", "F"):
+            if not np.array_equal(ma[q], mb[q]):
+                return False, f"{q}{i}", float(np.abs(ma[q] - mb[q]).max())
     return True, None, 0.0
 
 

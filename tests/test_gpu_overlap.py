@@ -1,0 +1,89 @@
+"""The overlapped D2Q9 step (lattice regions away from the membranes on a
+second stream beside the membrane kernels, the rest after them in short
+pieces) against the single-stream step: every node is updated by the same
+arithmetic, so fields, markers and forces must agree bitwise."""
+import numpy as np
+import pytest
+
+from helpers import run_gpu
+from paper_1906_03065_amd import lbib
+from paper_1906_03065_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(g):
+    f = g.fields()
+    mem = [g.membrane(i) for i in range(len(g.mem_sizes))]
+    return f, mem
+
+
+def _same(a, b):
+    fa, ma = a
+    fb, mb = b
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    for x, y in zip(ma, mb):
+        for k in x:
+            assert np.array_equal(x[k], y[k]), k
+
+
+def _ragged():
+    w = W.capsule_at_interface(nx=300, ny=259, R=22.0, n_markers=176, centre=(80.3, 129.2), wall_y=1,
+                               tau=0.8, tau_phi=1.3, tau_psi=0.9, kappa=(0.02, 0.03, 0.015), seed=21)
+    w["membranes"].append(dict(X=W.circle_markers(220.6, 100.1, 15.0, 120), tris=None, kappa_s=0.05,
+                               kappa_b=1e-3))
+    return w
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16"])
+def test_overlap_bitwise_ragged(storage):
+    """300 x 259 lattice (ragged strips and segments), two capsules, walls
+    in y: 80 steps with the overlap forced on equal 80 steps without."""
+    w = _ragged()
+    a = run_gpu(w, storage)
+    a.set_overlap(0)
+    b = run_gpu(w, storage)
+    b.set_overlap(1)
+    a.step(80)
+    b.step(80)
+    _same(_state(a), _state(b))
+    assert b.check() == 0
+
+
+def test_overlap_bitwise_periodic_and_shapes():
+    """Periodic in y (regions wrap), launch shapes varied on the overlapped
+    side: 192 lanes with ring 4, then 64 lanes with short segments."""
+    w = W.capsule_at_interface(nx=256, ny=192, R=30.0, n_markers=236, centre=(128.0, 20.5), wall_y=0, seed=23)
+    ref = run_gpu(w, "fp32")
+    ref.set_overlap(0)
+    ref.step(40)
+    for bx, seg, ring in ((192, 0, 4), (64, 7, 3)):
+        g = run_gpu(w, "fp32")
+        g.set_overlap(1)
+        g.set_launch(bx, seg, 0, ring)
+        g.step(40)
+        _same(_state(ref), _state(g))
+
+
+def test_overlap_full_size_c2():
+    """The 2048 x 2048 benchmark lattice with the overlap on against the
+    default single-stream step, five steps."""
+    w = W.c2()
+    a = run_gpu(w, "fp32")
+    b = run_gpu(w, "fp32")
+    b.set_overlap(1)
+    a.step(5)
+    b.step(5)
+    _same(_state(a), _state(b))
+
+
+def test_overlap_rejects_bad_values():
+    w = W.c1()
+    g = run_gpu(w, "fp32")
+    for v in (2, -2):
+        with pytest.raises(RuntimeError):
+            g.set_overlap(v)
+    g.set_overlap(1)
+    g.step(3)
+    assert g.check() == 0
