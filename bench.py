@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--seg", type=int, default=0, help="fused kernel rows per workgroup")
     ap.add_argument("--nxcd", type=int, default=0, help="L2 domains workgroups are dealt to")
     ap.add_argument("--ring", type=int, default=0, help="register ring depth (3 or 4)")
+    ap.add_argument("--overlap-steps", type=int, default=-1,
+                    help="D2Q9: steps timed afterwards with the overlapped step order (default "
+                         "steps/4; 0 skips them, e.g. for a profile of the single-stream kernel)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (source + destination "
                          "traffic 2*MIB MiB per launch), --steps times, to scale counters")
@@ -189,12 +192,12 @@ def main():
                      "kernel_share_of_step": round(lb_ms / (el * 1e3 / args.steps), 4),
                      "launch": g.get_launch()},
     }
-    if not d3:
+    k2 = max(args.steps // 4, 1) if args.overlap_steps < 0 else args.overlap_steps
+    if not d3 and k2 > 0:
         # the same lattice with the regions away from the membranes on a second
         # stream beside the membrane kernels (a scheduling option, bitwise the
         # same results); the roofline above stays the single-stream kernel's
         g.set_overlap(1)
-        k2 = max(args.steps // 4, 1)
         g.step(max(args.warmup // 4, 1))
         torch.cuda.synchronize()
         t2 = time.perf_counter()

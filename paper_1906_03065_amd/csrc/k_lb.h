@@ -259,18 +259,17 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
     // ---- U: chemical potentials on the previous row -> ring slot k%3
     if (k >= 2 && j >= 1 && j < BX - 1) {
       const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // rows r-2dir, r-dir, r
-      // south (row - 1) and north (row + 1) rows: the sums run in the same
-      // geometric order whichever way the segment marches, so every node
-      // gets the same rounding under any launch shape
-      const int so = dir > 0 ? a : c, no = dir > 0 ? c : a;
+      // rows a and c swap between up- and down-marching segments: each sum
+      // pairs them in one addition (IEEE addition is commutative), so every
+      // node gets the same rounding under any launch shape
       double lap[3], ctr[3];
 #pragma unroll
       for (int f = 0; f < 3; f++) {
         const double q = s_m[b][f][j];
-        const double n4 = (s_m[b][f][j - 1] - q) + (s_m[b][f][j + 1] - q) + (s_m[so][f][j] - q) +
-                          (s_m[no][f][j] - q);
-        const double n8 = (s_m[so][f][j - 1] - q) + (s_m[so][f][j + 1] - q) +
-                          (s_m[no][f][j - 1] - q) + (s_m[no][f][j + 1] - q);
+        const double n4 = ((s_m[b][f][j - 1] - q) + (s_m[b][f][j + 1] - q)) +
+                          ((s_m[a][f][j] - q) + (s_m[c][f][j] - q));
+        const double n8 = ((s_m[a][f][j - 1] - q) + (s_m[a][f][j + 1] - q)) +
+                          ((s_m[c][f][j - 1] - q) + (s_m[c][f][j + 1] - q));
         // lap q = 6 sum_i w_i (q(x + c_i) - q(x)) with the D2Q9 weights
         lap[f] = (2.0 / 3.0) * n4 + (1.0 / 6.0) * n8;
         ctr[f] = q;
@@ -371,11 +370,7 @@ __device__ __forceinline__ bool region_active(const LBParams& P, const int* __re
   return __syncthreads_or(a) != 0;
 }
 
-// The fused step over the whole lattice (mode 0), or split in two passes:
-// mode 1 takes the (strip, segment) regions that read no membrane field and
-// may run beside the membrane kernels; mode 2 takes the others after them,
-// each segment cut into pieces of seg2 rows so that the few regions near the
-// membranes still fill the GPU.
+// The fused step over the whole lattice: one (strip, segment) per workgroup.
 template <class St, typename R, int BX, int NS, int WPE>
 __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
                                                   const int* __restrict__ tflag,
@@ -383,6 +378,26 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
                                                   const double* __restrict__ Ifield,
                                                   long long* __restrict__ fib,
                                                   double* __restrict__ force) {
+  int strip, sgm;
+  strip_segment((int)blockIdx.x, P.nstrip, P.nseg, P.nxcd, strip, sgm);
+  const int y0 = sgm * P.seg, y1 = min(y0 + P.seg, P.ny);
+  // even segments march up, odd ones down: neighbouring segments then read
+  // the rows they share at the same time (both at their start or both at
+  // their end)
+  lb2d_run<St, R, BX, NS>(src, dst, P, strip, y0, y1, (sgm & 1) ? -1 : 1, tflag, tstate, Ifield, fib, force);
+}
+
+// The same step in two passes: mode 1 takes the (strip, segment) regions
+// that read no membrane field and may run beside the membrane kernels;
+// mode 2 takes the others after them, each segment cut into npiece pieces of
+// seg2 rows so that the few regions near the membranes still fill the GPU.
+template <class St, typename R, int BX, int NS, int WPE>
+__global__ __launch_bounds__(BX, WPE) void k_lb2d_part(St src, St dst, LBParams P,
+                                                       const int* __restrict__ tflag,
+                                                       const int* __restrict__ tstate,
+                                                       const double* __restrict__ Ifield,
+                                                       long long* __restrict__ fib,
+                                                       double* __restrict__ force) {
   int strip, sgm, piece = 0;
   if (P.mode == 2) {
     piece = (int)blockIdx.x % P.npiece;
@@ -393,9 +408,7 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
     strip_segment((int)blockIdx.x, P.nstrip, P.nseg, P.nxcd, strip, sgm);
   }
   int y0 = sgm * P.seg, y1 = min(y0 + P.seg, P.ny);
-  if (P.mode != 0 && region_active<BX>(P, tflag, tstate[1], strip, y0, y1) != (P.mode == 2)) return;
-  // even segments (pieces) march up, odd ones down: neighbours then read the
-  // rows they share at the same time (both at their start or both at their end)
+  if (region_active<BX>(P, tflag, tstate[1], strip, y0, y1) != (P.mode == 2)) return;
   int dir = (sgm & 1) ? -1 : 1;
   if (P.mode == 2) {
     y0 += piece * P.seg2;

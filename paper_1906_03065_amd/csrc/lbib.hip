@@ -486,8 +486,14 @@ struct Engine2D final : lbib_sim {
     double* frc = at<double>(L.force);
     // (lanes, ring depth, waves per SIMD) variants of the fused kernel
 #define LB_LAUNCH(BXV, NSV, WPEV)                                                                  \
-  hipLaunchKernelGGL((k_lb2d<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, If, fib, \
-                     frc)
+  do {                                                                                             \
+    if (mode == 0)                                                                                 \
+      hipLaunchKernelGGL((k_lb2d<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, If, \
+                         fib, frc);                                                                \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_lb2d_part<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, \
+                         If, fib, frc);                                                            \
+  } while (0)
     if (ring == 4) {
       if (bx == 128) LB_LAUNCH(128, 4, 2);
       else if (bx == 192) LB_LAUNCH(192, 4, 2);
