@@ -19,6 +19,9 @@
  *     host arrays passed out are filled by the callee.
  *   - Streams.  hip_stream is a hipStream_t (NULL = the default stream).
  *     lbib_step only enqueues work; the getters synchronise the stream.
+ *     With lbib_set_overlap(s, 1) a D2Q9 step also uses a second stream
+ *     that the handle creates on first use and releases in lbib_destroy;
+ *     every step still ends ordered on hip_stream.
  *     One host thread per handle; calls on one handle must not overlap.
  *   - Errors.  Every call returns an lbib_status; no exception crosses the
  *     ABI.  A failed call leaves the handle as it was, except LBIB_EHIP,
