@@ -1,12 +1,13 @@
 // batch.h -- many independent D2Q9 simulations stepped together.
 //
-// Every phase of the step runs as one launch over all members: a persistent
-// grid walks a queue of work items (a membrane, an active tile, a marker, a
+// Every phase of the step runs as one launch over all members: the grid
+// walks a queue of work items (a membrane, an active tile, a marker, a
 // (strip, segment) of a lattice) spread over the members, finds the member
 // of each item by binary search over prefix sums, and runs the same device
 // code the single-simulation kernels run.  The lattice kernel runs once per
 // size class, since the strip width (lanes per workgroup) is chosen per
-// class.  All members advance with the same buffer parity.
+// class, with one (strip, segment) item per workgroup.  All members advance
+// with the same buffer parity.
 #pragma once
 #include "common.h"
 #include "k_ibm.h"
@@ -115,13 +116,17 @@ __global__ void kb_interp2d(const BMember<St>* T, const int* __restrict__ mpre, 
   interp2d_run<St, R>(md, cur, P, force, live ? gf - mpre[i] : 0, k, live);
 }
 
-// persistent: the (strip, segment) items of the members of one size class
+// one workgroup per (strip, segment) item of the members of one size class
 // (cm: their member ids, bpre: item prefix, ncm + 1 entries)
 template <class St, typename R, int BX, int NS, int WPE>
 __global__ __launch_bounds__(BX, WPE) void kb_lb2d(const BMember<St>* T, const int* __restrict__ cm,
                                                    const int* __restrict__ bpre, int ncm, int parity) {
+  // one work item per workgroup: without a loop over items the kernel
+  // fits the single kernel's register budget (three waves per SIMD)
   const int total = bpre[ncm];
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  {
+    const int item = blockIdx.x;
+    if (item >= total) return;
     const int q = prefix_find(bpre, ncm, item);
     const int i = cm[q];
     const LBParams P = T[i].P;
@@ -135,7 +140,6 @@ __global__ __launch_bounds__(BX, WPE) void kb_lb2d(const BMember<St>* T, const i
     strip_segment(item - bpre[q], P.nstrip, P.nseg, 1, strip, sgm);
     const int y0 = sgm * P.seg, y1 = min(y0 + P.seg, P.ny);
     lb2d_run<St, R, BX, NS>(src, dst, P, strip, y0, y1, (sgm & 1) ? -1 : 1, tflag, tstate, Ifield, fib, force);
-    __syncthreads();  // the rings are reused by the next item
   }
 }
 

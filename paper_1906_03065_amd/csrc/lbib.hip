@@ -834,12 +834,10 @@ struct BatchEngine2D final : lbib_sim {
       if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 4, 2>;
       return (const void*)&kb_lb2d<St, R, 64, 4, 2>;
     }
-    // (the persistent loop needs a few more registers than the single
-    // kernel: ring 3 runs at two waves per SIMD too, without spills)
-    if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 3, 2>;
-    if (bx == 192) return (const void*)&kb_lb2d<St, R, 192, 3, 2>;
-    if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 3, 2>;
-    return (const void*)&kb_lb2d<St, R, 64, 3, 2>;
+    if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 3, 3>;
+    if (bx == 192) return (const void*)&kb_lb2d<St, R, 192, 3, 3>;
+    if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 3, 3>;
+    return (const void*)&kb_lb2d<St, R, 64, 3, 3>;
   }
   int resident(const void* k, int threads) const {
     int per_cu = 0, ncu = 0, dev = 0;
@@ -903,7 +901,7 @@ struct BatchEngine2D final : lbib_sim {
     cgrid = (int)std::max<long long>(1, std::min<long long>(tiles, 4096));
     for (int c = 0; c < NCLS; c++) {
       const int items = bpre[c * (n + 1) + ncm[c]];
-      lgrid[c] = std::max(1, std::min(items, resident(lb_kernel(c), cls_bx[c])));
+      lgrid[c] = std::max(1, items);  // one item per workgroup
     }
     hipStream_t st = stream;
     HIPCHK(hipMemcpyAsync(ws + off_tab, T.data(), T.size() * sizeof(BMember<St>), hipMemcpyHostToDevice, st));
@@ -963,10 +961,10 @@ struct BatchEngine2D final : lbib_sim {
         else if (cls_bx[c] == 256) KB_LAUNCH(256, 4, 2);
         else KB_LAUNCH(64, 4, 2);
       } else {
-        if (cls_bx[c] == 128) KB_LAUNCH(128, 3, 2);
-        else if (cls_bx[c] == 192) KB_LAUNCH(192, 3, 2);
-        else if (cls_bx[c] == 256) KB_LAUNCH(256, 3, 2);
-        else KB_LAUNCH(64, 3, 2);
+        if (cls_bx[c] == 128) KB_LAUNCH(128, 3, 3);
+        else if (cls_bx[c] == 192) KB_LAUNCH(192, 3, 3);
+        else if (cls_bx[c] == 256) KB_LAUNCH(256, 3, 3);
+        else KB_LAUNCH(64, 3, 3);
       }
 #undef KB_LAUNCH
     }
