@@ -1,0 +1,90 @@
+"""Capillary bridge between two elastic capsules (Sec. 4.2).
+
+The capsules' aspect ratio L_c / H_c at mechanical equilibrium against the
+membrane's Young modulus kappa_s, at the paper's three tension ratios
+(kappa_1 in {1, 3, 9} x 1e-3): fifteen runs of one 240 x 120 lattice shape,
+stepped together as one batch on the GPU until each run's aspect ratio
+changes by less than a tolerance over a window of steps.
+
+    python -m paper_1906_03065_amd.bridge [--max-steps N] [--out FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import lbib
+from . import workloads as W
+
+
+def run_sweep(kappa1s=W.BRIDGE_KAPPA1, kappa_ss=W.BRIDGE_KAPPA_S, max_steps: int = 300000,
+              every: int = 1000, window: int = 20000, tol: float = 1e-4, device="cuda:0", log: bool = True):
+    """Step all (kappa_1, kappa_s) runs as one batch for max_steps steps.  A
+    run counts as at equilibrium from the first check at which the aspect
+    ratio of its left capsule has changed by less than tol over the last
+    `window` steps; every run keeps stepping and is measured to the end.
+    Returns a dict with one record per run."""
+    cases = [(k1, ks) for k1 in kappa1s for ks in kappa_ss]
+    ws = [W.bridge2d(kappa1=k1, kappa_s=ks) for k1, ks in cases]
+    nodes = sum(w["params"]["nx"] * w["params"]["ny"] for w in ws)
+    b = lbib.Batch.from_workloads(ws, device=device)
+    hist = [[] for _ in ws]
+    steps = [-1] * len(ws)
+    at_eq = [None] * len(ws)
+    ratio = [None] * len(ws)
+    live = set(range(len(ws)))
+    step = 0
+    t0 = time.perf_counter()
+    while step < max_steps:
+        b.step(every)
+        step += every
+        allx = b.markers()
+        for k in range(len(ws)):
+            r = [W.aspect_ratio(X) for X in allx[k]]
+            ratio[k] = r
+            h = hist[k]
+            h.append((step, r[0]))
+            while h and h[0][0] < step - window:
+                h.pop(0)
+            if k in live and h[0][0] == step - window and abs(r[0] - h[0][1]) < tol:
+                steps[k] = step
+                at_eq[k] = r[0]
+                live.discard(k)
+        if log and step % (20 * every) == 0:
+            print(f"  step {step}: {len(ws) - len(live)} of {len(ws)} at equilibrium", flush=True)
+    b.synchronize()
+    wall = time.perf_counter() - t0
+    rc = b.check()
+    b.close()
+    out = []
+    for k, (k1, ks) in enumerate(cases):
+        kap = ws[k]["params"]["kappa"]
+        out.append(dict(kappa1=k1, kappa_s=ks, g12_g13=(kap[0] + kap[1]) / (kap[0] + kap[2]),
+                        steps=steps[k], aspect_at_equilibrium=at_eq[k], aspect_left=ratio[k][0],
+                        aspect_right=ratio[k][1]))
+    return dict(runs=out, steps_run=step, wall_s=wall, check=int(rc), nodes=nodes,
+                mlups=nodes * step / wall / 1e6, tol=tol, window=window)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--max-steps", type=int, default=300000)
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--window", type=int, default=20000)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+    res = run_sweep(max_steps=args.max_steps, tol=args.tol, window=args.window)
+    for r in res["runs"]:
+        print(f"g12/g13 {r['g12_g13']:.2f}  kappa_s {r['kappa_s']:8.0e}  L_c/H_c {r['aspect_left']:.4f} "
+              f"{r['aspect_right']:.4f}  equilibrium at step {r['steps']}", flush=True)
+    print(f"{res['steps_run']} steps of {len(res['runs'])} runs in {res['wall_s']:.1f} s "
+          f"({res['mlups']:.0f} MLUPS), check {res['check']}", flush=True)
+    if args.out:
+        json.dump(res, open(args.out, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,6 +20,8 @@ Workloads (the paper publishes no datasets; these stand in for its geometries):
   * ``flat``: a flat C1/C2 interface for the tanh-profile / tension checks.
   * ``capsule3d`` / ``c3``: D3Q19 icosphere capsules with a C3 bridge.
   * ``c4``: 64 capsule-at-interface runs of seeded uneven sizes.
+  * ``bridge2d``: two capsules joined by a capillary bridge of fluid 2 in a
+    periodic 12R x 6R box (Sec. 4.2), the paper's second workload.
 Seeds: ``1906030650 + k`` for workload k unless a seed is given.
 """
 from __future__ import annotations
@@ -347,3 +349,52 @@ def c4(seed=SEED_BASE + 3, count=64):
         w["name"] = f"c4_{k}_{n}"
         out.append(w)
     return out
+
+
+# the three tension ratios of the capillary-bridge study (Sec. 4.2): kappa_1
+# with kappa_2 = 3e-3 and kappa_3 = 6e-3
+BRIDGE_KAPPA1 = (1e-3, 3e-3, 9e-3)
+BRIDGE_KAPPA_S = (1e-4, 1e-3, 1e-2, 1e-1, 1.0)
+
+
+def bridge2d(kappa1=3e-3, kappa_s=1e-2, R=20.0, n_markers=160, kappa_b=1e-2, kappa_c=1e-2, alpha=2.0,
+             mobility=0.1, offset=(0.0, 0.0)):
+    """Capillary bridge between two capsules (Sec. 4.2, Fig. 1b): a periodic
+    12R x 6R box of fluid 1; capsules of fluid 3 with radius R centred at
+    (9R/2, 3R) and (15R/2, 3R); between them a rectangle of fluid 2, 2S = R
+    wide and H_b = 31R/10 high, centred in the box.  kappa_2 = 3e-3,
+    kappa_3 = 6e-3, alpha = 2, kappa_b = kappa_c = 1e-2 as in the paper; the
+    rectangle's diffuse edge is the product of two tanh profiles.  No
+    perturbation: the set-up is mirror-symmetric about x = 6R.  ``offset``
+    shifts the whole set-up off the lattice (a node at a capsule centre is
+    equidistant from opposite membrane segments, and with a band wider than
+    R such exact ties are decided by the last bit of each implementation's
+    rounding)."""
+    nx, ny = int(round(12 * R)), int(round(6 * R))
+    # band 12 alpha: the profile is saturated to 6e-6 there, and an elongated
+    # capsule's band (height + 2 reach) still fits the 6R-high periodic box
+    p = base_params(nx, ny, wall_y=0, kappa=(kappa1, 3e-3, 6e-3), alpha=alpha, kappa_c=kappa_c,
+                    mobility=mobility, r_cut=12.0 * alpha)
+    x, y = _grid2(nx, ny)
+    ox, oy = (float(v) for v in offset)
+    centres = ((4.5 * R + ox, 3.0 * R + oy), (7.5 * R + ox, 3.0 * R + oy))
+    C3 = np.zeros((ny, nx))
+    for cx, cy in centres:
+        C3 += tanh_profile(R - np.hypot(_min_image(x - cx, nx), _min_image(y - cy, ny)), alpha)
+    half_w, half_h = 0.5 * R, 0.5 * 3.1 * R
+    rect = tanh_profile(half_w - np.abs(_min_image(x - 6.0 * R - ox, nx)), alpha) * \
+        tanh_profile(half_h - np.abs(_min_image(y - 3.0 * R - oy, ny)), alpha)
+    C2 = rect * (1.0 - C3)
+    C1 = 1.0 - C2 - C3
+    mems = [dict(X=circle_markers(cx, cy, R, n_markers), tris=None, kappa_s=float(kappa_s),
+                 kappa_b=float(kappa_b)) for cx, cy in centres]
+    return dict(params=p, fields=fields_from_C(C1, C2, C3), membranes=mems, R=float(R),
+                name=f"bridge2d_k1_{kappa1:g}_ks_{kappa_s:g}")
+
+
+def aspect_ratio(X):
+    """L_c / H_c of a capsule from its markers (n, 2): horizontal extent over
+    vertical extent."""
+    X = np.asarray(X, dtype=np.float64)
+    return float((X[:, 0].max() - X[:, 0].min()) / (X[:, 1].max() - X[:, 1].min()))
+
