@@ -41,7 +41,8 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("tau_phi", C.c_double), ("tau_psi", C.c_double),
                 ("gamma_phi", C.c_double), ("gamma_psi", C.c_double),
                 ("kappa1", C.c_double), ("kappa2", C.c_double), ("kappa3", C.c_double),
-                ("alpha", C.c_double), ("kappa_c", C.c_double), ("r_cut", C.c_double)]
+                ("alpha", C.c_double), ("kappa_c", C.c_double), ("r_cut", C.c_double),
+                ("force_form", C.c_int)]
 
 
 class Energy(C.Structure):
@@ -92,6 +93,8 @@ def lib():
         L.orc_coupling.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.orc_spread.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
         L.orc_interp.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
+        L.orc_pressure_tensor.argtypes = [C.POINTER(Params), C.c_int, _dp, _dp, _dp, _dp]
+        L.orc_fe_force.argtypes = [C.c_void_p, C.c_int, _dp]
         _lib = L
     return _lib
 
@@ -113,7 +116,22 @@ def make_params(p: dict) -> Params:
                   float(p.get("tau", 1.0)), float(p.get("tau_phi", 1.0)), float(p.get("tau_psi", 1.0)),
                   float(p.get("gamma_phi", 1.0)), float(p.get("gamma_psi", 1.0)),
                   float(p["kappa"][0]), float(p["kappa"][1]), float(p["kappa"][2]),
-                  float(p.get("alpha", 1.0)), float(p.get("kappa_c", 0.0)), float(p.get("r_cut", 0.0)))
+                  float(p.get("alpha", 1.0)), float(p.get("kappa_c", 0.0)), float(p.get("r_cut", 0.0)),
+                  int(p.get("force_form", 0)))
+
+
+def pressure_tensor(p: dict, q, g, l, D: int = 2):
+    """Pressure tensor p' of Appendix A (no ideal gas) at one point: q the
+    three values (rho, phi, psi), g their gradients (3 x 3, row q), l their
+    Laplacians.  Returns a 3 x 3 array."""
+    prm = make_params(p)
+    P = np.zeros(9)
+    gg = np.zeros((3, 3))
+    gg[:, :np.asarray(g).shape[1]] = np.asarray(g, dtype=np.float64)
+    if lib().orc_pressure_tensor(C.byref(prm), int(D), _d(_f64(q)), _d(np.ascontiguousarray(gg.reshape(-1))),
+                                  _d(_f64(l)), _d(P)):
+        raise ValueError("orc_pressure_tensor failed")
+    return P.reshape(3, 3)
 
 
 def set_threads(n: int = 0) -> int:
@@ -194,6 +212,15 @@ class Sim:
         return e.as_dict()
 
     # ---- pieces for unit pins ----
+    def fe_force(self, form: int):
+        """Free-energy force of the current populations (no coupling or
+        membrane force): form 0 potential, 1 divergence of the pressure
+        tensor; shape (N, 3)."""
+        F = np.zeros(3 * self.N)
+        if lib().orc_fe_force(self.h, int(form), _d(F)):
+            raise ValueError("orc_fe_force failed")
+        return F.reshape(self.N, 3)
+
     def grad_lap(self, q):
         q = _f64(q).reshape(-1)
         g = np.empty(self.N * self.D)

@@ -530,6 +530,7 @@ int orc_mesh_forces(int n, const double* X, int ntri, const int* tri, const doub
 orc_sim* orc_create(const orc_params* p) {
   if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
   if (p->tau <= 0.5 || p->tau_phi <= 0.5 || p->tau_psi <= 0.5 || p->alpha <= 0.0) return NULL;
+  if (p->force_form < 0 || p->force_form > 1 || (p->force_form == 1 && p->lattice != 0)) return NULL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   s->p = *p;
   if (s->p.r_cut <= 0.0) s->p.r_cut = 17.0 * s->p.alpha;
@@ -915,6 +916,101 @@ static void compute_moments(orc_sim* s, double* const* pop, double* rho, double*
 }
 
 /* chemical potentials on the whole lattice from rho, phi, psi and I */
+/* ------------------------------------------------------------------ */
+/* pressure tensor, Appendix A.  The gradient part uses the kappa mixing  */
+/* matrix printed there (the Hessian of the gradient energy in rho, phi,  */
+/* psi).  READING: the bulk part is taken from its definition,            */
+/* p_b' = sum_q q mu_q^b - f_b = sum_m [C_m f_m'(C_m) - f_m(C_m)] with    */
+/* f_m = kappa_m/2 C_m^2 (1 - C_m)^2, not from the printed polynomial,    */
+/* which differs from it by a non-constant term; the ideal gas rho c_s^2  */
+/* is left out as in the potential form (it cancels in eq. ForceFE).      */
+/* ------------------------------------------------------------------ */
+int orc_pressure_tensor(const orc_params* p, int D, const double* q, const double* g, const double* l,
+                        double* P) {
+  if (!p || D < 2 || D > 3) return -1;
+  const double k1 = p->kappa1, k2 = p->kappa2, k3 = p->kappa3, a2 = p->alpha * p->alpha;
+  const double K[3][3] = {{(k1 + k2) / 4.0, (k1 - k2) / 4.0, -(k1 + k2) / 4.0},
+                          {(k1 - k2) / 4.0, (k1 + k2) / 4.0, -(k1 - k2) / 4.0},
+                          {-(k1 + k2) / 4.0, -(k1 - k2) / 4.0, (k1 + k2 + 4.0 * k3) / 4.0}};
+  const double C[3] = {0.5 * (q[0] + q[1] - q[2]), 0.5 * (q[0] - q[1] - q[2]), q[2]};
+  const double km[3] = {k1, k2, k3};
+  double pb = 0.0;
+  for (int m = 0; m < 3; m++) {
+    const double c = C[m];
+    const double f = 0.5 * km[m] * c * c * (1.0 - c) * (1.0 - c);
+    const double fp = km[m] * c * (1.0 - c) * (1.0 - 2.0 * c);
+    pb += c * fp - f;
+  }
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) P[3 * a + b] = (a == b && a < D) ? pb : 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      double gg = 0.0;
+      for (int a = 0; a < D; a++) gg += g[3 * i + a] * g[3 * j + a];
+      for (int a = 0; a < D; a++)
+        for (int b = 0; b < D; b++) {
+          double t = g[3 * i + a] * g[3 * j + b];
+          if (a == b) t -= 0.5 * gg + q[i] * l[j];
+          P[3 * a + b] += a2 * K[i][j] * t;
+        }
+    }
+  return 0;
+}
+
+/* p' at lattice point (x, y) of the mirror-extended fields: a point beyond
+   a wall takes the values of its mirror node, with the gradient's component
+   normal to the wall reversed (the fields are even about the wall) */
+static void pressure_at(const orc_sim* s, const double* const qf[3], const double* const gf[3],
+                        const double* const lf[3], int x, int y, double* P) {
+  const int xx = wrapi(x, s->nx);
+  int yy = y, flip = 0;
+  if (s->p.wall_y) {
+    if (y < 0) { yy = -1 - y; flip = 1; }
+    if (y >= s->ny) { yy = 2 * s->ny - 1 - y; flip = 1; }
+  } else {
+    yy = wrapi(y, s->ny);
+  }
+  const long n = nid(s, xx, yy, 0);
+  double q[3], g[9] = {0}, l[3];
+  for (int k = 0; k < 3; k++) {
+    q[k] = qf[k][n];
+    l[k] = lf[k][n];
+    g[3 * k] = gf[k][2 * n];
+    g[3 * k + 1] = flip ? -gf[k][2 * n + 1] : gf[k][2 * n + 1];
+  }
+  orc_pressure_tensor(&s->p, 2, q, g, l, P);
+}
+
+/* -div p' (eq. ForceFE, divergence form) by the isotropic gradient stencil
+   applied to the tensor's columns, 2 components per node into F2 */
+static void div_pressure(const orc_sim* s, double* F2) {
+  const long N = s->N;
+  double* g[3];
+  for (int k = 0; k < 3; k++) g[k] = (double*)malloc(sizeof(double) * 2 * (size_t)N);
+  orc_grad_lap(s, s->rho, g[0], s->lap[0]);
+  orc_grad_lap(s, s->phi, g[1], s->lap[1]);
+  orc_grad_lap(s, s->psi, g[2], s->lap[2]);
+  const double* const qf[3] = {s->rho, s->phi, s->psi};
+  const double* const gf[3] = {g[0], g[1], g[2]};
+  const double* const lf[3] = {s->lap[0], s->lap[1], s->lap[2]};
+  const lat_t* L = &s->L;
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int y = 0; y < s->ny; y++)
+    for (int x = 0; x < s->nx; x++) {
+      double d[2] = {0.0, 0.0};
+      for (int i = 0; i < L->Q; i++) {
+        double P[9];
+        pressure_at(s, qf, gf, lf, x + L->c[i][0], y + L->c[i][1], P);
+        for (int a = 0; a < 2; a++)
+          for (int b = 0; b < 2; b++) d[a] += L->w[i] * L->c[i][b] * P[3 * a + b];
+      }
+      const long n = nid(s, x, y, 0);
+      F2[2 * n] = -d[0] / CS2;
+      F2[2 * n + 1] = -d[1] / CS2;
+    }
+  for (int k = 0; k < 3; k++) free(g[k]);
+}
+
 static void compute_mu(orc_sim* s) {
   orc_grad_lap(s, s->rho, NULL, s->lap[0]);
   orc_grad_lap(s, s->phi, NULL, s->lap[1]);
@@ -1067,8 +1163,26 @@ static void one_step(orc_sim* s) {
   }
 
   /* 5. force f = f_FE + f_IB (eq. ForcingTermLBE, f_ext = 0), with
-        f_FE = -rho grad mu_rho - phi grad mu_phi - psi grad mu_psi' */
-  {
+        f_FE = -rho grad mu_rho - phi grad mu_phi - psi grad mu_psi'
+        (potential form) or -div p' - psi grad kappa_c (psi - I)
+        (divergence form) */
+  if (s->p.force_form == 1) {
+    double* F2 = (double*)malloc(sizeof(double) * 2 * (size_t)N);
+    double* cp = (double*)malloc(sizeof(double) * (size_t)N);
+    double* gc = (double*)malloc(sizeof(double) * 2 * (size_t)N);
+    div_pressure(s, F2);
+    for (long n = 0; n < N; n++) cp[n] = s->p.kappa_c * (s->psi[n] - s->I[n]);
+    orc_grad_lap(s, cp, gc, NULL);
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; n++) {
+      for (int a = 0; a < 3; a++) s->force[3 * n + a] = 0.0;
+      for (int a = 0; a < 2; a++)
+        s->force[3 * n + a] = F2[2 * n + a] - s->psi[n] * gc[2 * n + a] + s->fib[3 * n + a];
+    }
+    free(F2);
+    free(cp);
+    free(gc);
+  } else {
     double* g0 = (double*)malloc(sizeof(double) * D * (size_t)N);
     double* g1 = (double*)malloc(sizeof(double) * D * (size_t)N);
     double* g2 = (double*)malloc(sizeof(double) * D * (size_t)N);
@@ -1142,6 +1256,45 @@ static void one_step(orc_sim* s) {
 int orc_step(orc_sim* s, int n_steps) {
   if (!s || !s->ready || n_steps < 0) return -1;
   for (int k = 0; k < n_steps; k++) one_step(s);
+  return 0;
+}
+
+int orc_fe_force(orc_sim* s, int form, double* F) {
+  if (!s || !s->ready || !F || form < 0 || form > 1 || (form == 1 && s->D != 2)) return -1;
+  const long N = s->N;
+  const int D = s->D;
+  compute_moments(s, s->pop, s->rho, s->u, s->phi, s->psi);
+  for (long n = 0; n < 3 * N; n++) F[n] = 0.0;
+  if (form == 1) {
+    double* F2 = (double*)malloc(sizeof(double) * 2 * (size_t)N);
+    div_pressure(s, F2);
+    for (long n = 0; n < N; n++) {
+      F[3 * n] = F2[2 * n];
+      F[3 * n + 1] = F2[2 * n + 1];
+    }
+    free(F2);
+    return 0;
+  }
+  /* potential form without the coupling term: mu at I = psi */
+  double* mu[3];
+  double* gm = (double*)malloc(sizeof(double) * D * (size_t)N);
+  for (int k = 0; k < 3; k++) mu[k] = (double*)malloc(sizeof(double) * (size_t)N);
+  orc_grad_lap(s, s->rho, NULL, s->lap[0]);
+  orc_grad_lap(s, s->phi, NULL, s->lap[1]);
+  orc_grad_lap(s, s->psi, NULL, s->lap[2]);
+  for (long n = 0; n < N; n++) {
+    double m3[3];
+    orc_mu(&s->p, s->rho[n], s->phi[n], s->psi[n], s->lap[0][n], s->lap[1][n], s->lap[2][n], s->psi[n], m3);
+    for (int k = 0; k < 3; k++) mu[k][n] = m3[k];
+  }
+  const double* qv[3] = {s->rho, s->phi, s->psi};
+  for (int k = 0; k < 3; k++) {
+    orc_grad_lap(s, mu[k], gm, NULL);
+    for (long n = 0; n < N; n++)
+      for (int a = 0; a < D; a++) F[3 * n + a] -= qv[k][n] * gm[(size_t)n * D + a];
+  }
+  for (int k = 0; k < 3; k++) free(mu[k]);
+  free(gm);
   return 0;
 }
 

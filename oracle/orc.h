@@ -34,6 +34,10 @@ typedef struct {
   double r_cut;           /* coupling band: beyond this distance from a membrane
                              the profile I is exactly 0 or 1 and the node adds
                              no coupling force.  <= 0 selects 17*alpha.           */
+  int force_form;         /* free-energy force of eq. ForceFE: 0 potential form
+                             -rho grad mu_rho - phi grad mu_phi - psi grad mu_psi',
+                             1 divergence form -div p' - psi grad kappa_c(psi - I)
+                             with the pressure tensor of Appendix A (D2Q9 only)  */
 } orc_params;
 
 /* energies and conserved sums, all FP64 */
@@ -50,6 +54,17 @@ typedef struct {
 typedef struct orc_sim orc_sim;
 
 orc_sim* orc_create(const orc_params* p);
+
+/* Pressure tensor p' of Appendix A without the ideal-gas part, at one point
+ * from the values q = (rho, phi, psi), their gradients g[q][a] and
+ * Laplacians l[q]; P receives the D x D components (row-major 3 x 3).  */
+int orc_pressure_tensor(const orc_params* p, int D, const double* q, const double* g, const double* l,
+                        double* P);
+
+/* Free-energy force (no coupling term, no membrane force) of the current
+ * populations in the given form (0 potential, 1 divergence; D2Q9 only for
+ * 1): F receives 3 values per node.  */
+int orc_fe_force(orc_sim* s, int form, double* F);
 void     orc_destroy(orc_sim* s);
 int      orc_set_threads(int n);   /* OpenMP threads for node loops; returns the count used */
 
