@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--overlap-steps", type=int, default=-1,
                     help="D2Q9: steps timed afterwards with the overlapped step order (default "
                          "steps/4; 0 skips them, e.g. for a profile of the single-stream kernel)")
+    ap.add_argument("--force-form", type=int, default=0, choices=[0, 1],
+                    help="D2Q9: thermodynamic force in potential (0, the default) or divergence (1) form")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (source + destination "
                          "traffic 2*MIB MiB per launch), --steps times, to scale counters")
@@ -141,6 +143,11 @@ def main():
     d3 = args.workload == "c3"
     size = args.size or (256 if d3 else 2048)
     w = W.c3(n=size) if d3 else W.c2(n=size)
+    if args.force_form:
+        if d3:
+            print("the divergence force form is a D2Q9 option", file=sys.stderr)
+            sys.exit(2)
+        w["params"]["force_form"] = 1
     g = lbib.from_workload(w, storage=args.storage, device="cuda:0")
     g.set_launch(args.block_x, args.seg, args.nxcd, args.ring)
     N = g.N
@@ -182,18 +189,19 @@ def main():
                                 f"D2Q9 {size}x{size}, walls in y, 16 capsules "
                                 f"(R 24-64, {sum(len(m['X']) for m in w['membranes'])} markers), "
                                 f"flat C1/C2 interface, {args.storage} populations"),
+                   "force_form": "divergence" if args.force_form else "potential",
                    "nodes": N, "capsules": len(w["membranes"]),
                    "markers": sum(len(m["X"]) for m in w["membranes"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if d3 else measured_traffic(args.storage, size),
+                     "traffic": None if d3 or args.force_form else measured_traffic(args.storage, size),
                      "kernel": "k_mom3d + k_lb3d" if d3 else "k_lb2d", "kernel_ms": round(lb_ms, 5),
                      "bytes_per_lup": bpl,
                      "kernel_share_of_step": round(lb_ms / (el * 1e3 / args.steps), 4),
                      "launch": g.get_launch()},
     }
     k2 = max(args.steps // 4, 1) if args.overlap_steps < 0 else args.overlap_steps
-    if not d3 and k2 > 0:
+    if not d3 and k2 > 0 and not args.force_form:
         # the same lattice with the regions away from the membranes on a second
         # stream beside the membrane kernels (a scheduling option, bitwise the
         # same results); the roofline above stays the single-stream kernel's

@@ -6,7 +6,7 @@ membrane's Young modulus kappa_s, at the paper's three tension ratios
 stepped together as one batch on the GPU until each run's aspect ratio
 changes by less than a tolerance over a window of steps.
 
-    python -m paper_1906_03065_amd.bridge [--max-steps N] [--out FILE]
+    python -m paper_1906_03065_amd.bridge [--max-steps N] [--force-form F] [--out FILE]
 """
 from __future__ import annotations
 
@@ -21,14 +21,18 @@ from . import workloads as W
 
 
 def run_sweep(kappa1s=W.BRIDGE_KAPPA1, kappa_ss=W.BRIDGE_KAPPA_S, max_steps: int = 300000,
-              every: int = 1000, window: int = 20000, tol: float = 1e-4, device="cuda:0", log: bool = True):
+              every: int = 1000, window: int = 20000, tol: float = 1e-4, device="cuda:0", log: bool = True,
+              force_form: int = 0):
     """Step all (kappa_1, kappa_s) runs as one batch for max_steps steps.  A
     run counts as at equilibrium from the first check at which the aspect
     ratio of its left capsule has changed by less than tol over the last
     `window` steps; every run keeps stepping and is measured to the end.
-    Returns a dict with one record per run."""
+    force_form: 0 the potential form of the thermodynamic force (eq. GradPT),
+    1 its divergence form.  Returns a dict with one record per run."""
     cases = [(k1, ks) for k1 in kappa1s for ks in kappa_ss]
     ws = [W.bridge2d(kappa1=k1, kappa_s=ks) for k1, ks in cases]
+    for w in ws:
+        w["params"]["force_form"] = int(force_form)
     nodes = sum(w["params"]["nx"] * w["params"]["ny"] for w in ws)
     b = lbib.Batch.from_workloads(ws, device=device)
     hist = [[] for _ in ws]
@@ -66,7 +70,7 @@ def run_sweep(kappa1s=W.BRIDGE_KAPPA1, kappa_ss=W.BRIDGE_KAPPA_S, max_steps: int
                         steps=steps[k], aspect_at_equilibrium=at_eq[k], aspect_left=ratio[k][0],
                         aspect_right=ratio[k][1]))
     return dict(runs=out, steps_run=step, wall_s=wall, check=int(rc), nodes=nodes,
-                mlups=nodes * step / wall / 1e6, tol=tol, window=window)
+                mlups=nodes * step / wall / 1e6, tol=tol, window=window, force_form=int(force_form))
 
 
 def main():
@@ -74,9 +78,11 @@ def main():
     ap.add_argument("--max-steps", type=int, default=300000)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--window", type=int, default=20000)
+    ap.add_argument("--force-form", type=int, default=0, choices=[0, 1],
+                    help="thermodynamic force: 0 potential form, 1 divergence form")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
-    res = run_sweep(max_steps=args.max_steps, tol=args.tol, window=args.window)
+    res = run_sweep(max_steps=args.max_steps, tol=args.tol, window=args.window, force_form=args.force_form)
     for r in res["runs"]:
         print(f"g12/g13 {r['g12_g13']:.2f}  kappa_s {r['kappa_s']:8.0e}  L_c/H_c {r['aspect_left']:.4f} "
               f"{r['aspect_right']:.4f}  equilibrium at step {r['steps']}", flush=True)

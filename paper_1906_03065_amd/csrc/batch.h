@@ -118,7 +118,7 @@ __global__ void kb_interp2d(const BMember<St>* T, const int* __restrict__ mpre, 
 
 // one workgroup per (strip, segment) item of the members of one size class
 // (cm: their member ids, bpre: item prefix, ncm + 1 entries)
-template <class St, typename R, int BX, int NS, int WPE>
+template <class St, typename R, int BX, int NS, int WPE, int FORM = 0>
 __global__ __launch_bounds__(BX, WPE) void kb_lb2d(const BMember<St>* T, const int* __restrict__ cm,
                                                    const int* __restrict__ bpre, int ncm, int parity) {
   // one work item per workgroup: without a loop over items the kernel
@@ -139,7 +139,8 @@ __global__ __launch_bounds__(BX, WPE) void kb_lb2d(const BMember<St>* T, const i
     int strip, sgm;
     strip_segment(item - bpre[q], P.nstrip, P.nseg, 1, strip, sgm);
     const int y0 = sgm * P.seg, y1 = min(y0 + P.seg, P.ny);
-    lb2d_run<St, R, BX, NS>(src, dst, P, strip, y0, y1, (sgm & 1) ? -1 : 1, tflag, tstate, Ifield, fib, force);
+    lb2d_run<St, R, BX, NS, FORM>(src, dst, P, strip, y0, y1, (sgm & 1) ? -1 : 1, tflag, tstate, Ifield, fib,
+                                  force);
   }
 }
 

@@ -189,7 +189,12 @@ __device__ __forceinline__ void moments9(const R* pf, const R* pg, const R* ph, 
 // previous rows are computed.  WPE: waves per SIMD the register budget is
 // sized for.
 // One (strip, segment) of the lattice: the whole march of a workgroup.
-template <class St, typename R, int BX, int NS>
+// FORM 0: the force of eq. ForceFE in its potential form, -sum q grad mu_q
+// over q = rho, phi, psi (eq. GradPT).  FORM 1: its divergence form,
+// -div P' - psi grad kappa_c (psi - I), with the non-ideal pressure tensor P'
+// of Appendix A formed per node in the U stage and its divergence taken in
+// the C stage (the two forms agree up to the discretisation error).
+template <class St, typename R, int BX, int NS, int FORM = 0>
 __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBParams& P, int strip, int y0,
                                          int y1, int dir, const int* __restrict__ tflag,
                                          const int* __restrict__ tstate, const double* __restrict__ Ifield,
@@ -198,7 +203,11 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
   constexpr int W = BX - 4;
   __shared__ double s_m[3][3][BX];  // moment ring [slot][drho, phi, psi][lane]
   __shared__ double s_j[3][2][BX];  // momentum ring [slot][jx, jy][lane]
-  __shared__ double s_u[3][3][BX];  // chemical-potential ring [slot][mu_rho, mu_phi, mu_psi'][lane]
+  // chemical-potential ring [slot][mu_rho, mu_phi, mu_psi'][lane]; with
+  // FORM 1 its first field holds P'_xx instead of mu_rho
+  __shared__ double s_u[3][3][BX];
+  // FORM 1 only: [slot][P'_xy, P'_yy, kappa_c (psi - I)][lane]
+  __shared__ double s_p[3][3][FORM == 1 ? BX : 1];
 
   const int j = threadIdx.x;
   const int xc = strip * W - 2 + j;
@@ -277,7 +286,47 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
       double mr, mp, ms;
       chem_pot(P, ctr[0], ctr[1], ctr[2], lap[0], lap[1], lap[2], Ipre, mr, mp, ms);
       const int sl = k % 3;
-      s_u[sl][0][j] = mr;
+      if constexpr (FORM == 1) {
+        // gradients of rho, phi, psi on this row (north and south resolved
+        // by name, so both marching directions round alike)
+        const int sn = dir > 0 ? c : a, ss = dir > 0 ? a : c;
+        double gx[3], gy[3];
+#pragma unroll
+        for (int f = 0; f < 3; f++) {
+          const double e = s_m[b][f][j + 1], wv = s_m[b][f][j - 1];
+          const double nn = s_m[sn][f][j], so = s_m[ss][f][j];
+          const double ne = s_m[sn][f][j + 1], nw = s_m[sn][f][j - 1];
+          const double se = s_m[ss][f][j + 1], sw = s_m[ss][f][j - 1];
+          gx[f] = (1.0 / 3.0) * (e - wv) + (1.0 / 12.0) * ((ne - nw) + (se - sw));
+          gy[f] = (1.0 / 3.0) * (nn - so) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
+        }
+        // P' in the concentrations C_m (eq. VariableTransform), where the
+        // energy of eq. LandauFE is a sum of independent terms: for each m
+        // the bulk part C f_m'(C) - f_m(C) = kappa_m/2 C^2 (1-C)(1-3C) and the
+        // gradient part alpha^2 kappa_m (dC dC - (|grad C|^2/2 + C lap C) I)
+        const double rho = 1.0 + ctr[0];
+        const double Cm[3] = {0.5 * (rho + ctr[1] - ctr[2]), 0.5 * (rho - ctr[1] - ctr[2]), ctr[2]};
+        const double Xm[3] = {0.5 * (gx[0] + gx[1] - gx[2]), 0.5 * (gx[0] - gx[1] - gx[2]), gx[2]};
+        const double Ym[3] = {0.5 * (gy[0] + gy[1] - gy[2]), 0.5 * (gy[0] - gy[1] - gy[2]), gy[2]};
+        const double Lm[3] = {0.5 * (lap[0] + lap[1] - lap[2]), 0.5 * (lap[0] - lap[1] - lap[2]), lap[2]};
+        const double km[3] = {P.k1, P.k2, P.k3};
+        double pb = 0.0, dd = 0.0, cl = 0.0, xy = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          const double C = Cm[m];
+          pb += km[m] * (C * C * (1.0 - C) * (1.0 - 3.0 * C));
+          dd += km[m] * (Xm[m] * Xm[m] - Ym[m] * Ym[m]);
+          cl += km[m] * (C * Lm[m]);
+          xy += km[m] * (Xm[m] * Ym[m]);
+        }
+        const double iso = 0.5 * pb - P.a2 * cl;
+        s_u[sl][0][j] = iso + 0.5 * P.a2 * dd;
+        s_p[sl][0][j] = P.a2 * xy;
+        s_p[sl][1][j] = iso - 0.5 * P.a2 * dd;
+        s_p[sl][2][j] = P.kc * (ctr[2] - Ipre);
+      } else {
+        s_u[sl][0][j] = mr;
+      }
       s_u[sl][1][j] = mp;
       s_u[sl][2][j] = ms;
     }
@@ -289,21 +338,44 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
       // moments of row cy were stored two iterations ago (slot (k-2)%3 = a)
       const double d = s_m[a][0][j], phi = s_m[a][1][j], psi = s_m[a][2][j];
       const double jx = s_j[a][0][j], jy = s_j[a][1][j];
-      // grad mu = 3 sum_i w_i c_i mu(x + c_i)
-      double gx[3], gy[3];
+      double Fx, Fy;
+      if constexpr (FORM == 1) {
+        // -div P' - psi grad kappa_c (psi - I); the divergence of a tensor
+        // column by the same stencil as a gradient, 3 sum_i w_i c_i P(x + c_i)
+        double gx[4], gy[4];
+        const double* fld[4][3] = {{s_u[ss][0], s_u[b][0], s_u[sn][0]},
+                                   {s_p[ss][0], s_p[b][0], s_p[sn][0]},
+                                   {s_p[ss][1], s_p[b][1], s_p[sn][1]},
+                                   {s_p[ss][2], s_p[b][2], s_p[sn][2]}};
 #pragma unroll
-      for (int f = 0; f < 3; f++) {
-        const double e = s_u[b][f][j + 1], wv = s_u[b][f][j - 1];
-        const double nn = s_u[sn][f][j], so = s_u[ss][f][j];
-        const double ne = s_u[sn][f][j + 1], nw = s_u[sn][f][j - 1];
-        const double se = s_u[ss][f][j + 1], sw = s_u[ss][f][j - 1];
-        gx[f] = (1.0 / 3.0) * (e - wv) + (1.0 / 12.0) * ((ne - nw) + (se - sw));
-        gy[f] = (1.0 / 3.0) * (nn - so) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
+        for (int f = 0; f < 4; f++) {
+          const double *rs = fld[f][0], *rc = fld[f][1], *rn = fld[f][2];
+          const double e = rc[j + 1], wv = rc[j - 1];
+          const double nn = rn[j], so = rs[j];
+          const double ne = rn[j + 1], nw = rn[j - 1];
+          const double se = rs[j + 1], sw = rs[j - 1];
+          gx[f] = (1.0 / 3.0) * (e - wv) + (1.0 / 12.0) * ((ne - nw) + (se - sw));
+          gy[f] = (1.0 / 3.0) * (nn - so) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
+        }
+        Fx = -(gx[0] + gy[1]) - psi * gx[3];
+        Fy = -(gx[1] + gy[2]) - psi * gy[3];
+      } else {
+        // grad mu = 3 sum_i w_i c_i mu(x + c_i)
+        double gx[3], gy[3];
+#pragma unroll
+        for (int f = 0; f < 3; f++) {
+          const double e = s_u[b][f][j + 1], wv = s_u[b][f][j - 1];
+          const double nn = s_u[sn][f][j], so = s_u[ss][f][j];
+          const double ne = s_u[sn][f][j + 1], nw = s_u[sn][f][j - 1];
+          const double se = s_u[ss][f][j + 1], sw = s_u[ss][f][j - 1];
+          gx[f] = (1.0 / 3.0) * (e - wv) + (1.0 / 12.0) * ((ne - nw) + (se - sw));
+          gy[f] = (1.0 / 3.0) * (nn - so) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
+        }
+        const double rho = 1.0 + d;
+        // thermodynamic force, eq. ForceFE with eq. GradPT (potential form)
+        Fx = -(rho * gx[0] + phi * gx[1] + psi * gx[2]);
+        Fy = -(rho * gy[0] + phi * gy[1] + psi * gy[2]);
       }
-      const double rho = 1.0 + d;
-      // thermodynamic force, eq. ForceFE with eq. GradPT (potential form)
-      double Fx = -(rho * gx[0] + phi * gx[1] + psi * gx[2]);
-      double Fy = -(rho * gy[0] + phi * gy[1] + psi * gy[2]);
       const long long node = (long long)cy * P.nx + x;
       if (cact) {
         Fx += from_fix(fb0);
@@ -371,7 +443,7 @@ __device__ __forceinline__ bool region_active(const LBParams& P, const int* __re
 }
 
 // The fused step over the whole lattice: one (strip, segment) per workgroup.
-template <class St, typename R, int BX, int NS, int WPE>
+template <class St, typename R, int BX, int NS, int WPE, int FORM = 0>
 __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
                                                   const int* __restrict__ tflag,
                                                   const int* __restrict__ tstate,
@@ -384,7 +456,8 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
   // even segments march up, odd ones down: neighbouring segments then read
   // the rows they share at the same time (both at their start or both at
   // their end)
-  lb2d_run<St, R, BX, NS>(src, dst, P, strip, y0, y1, (sgm & 1) ? -1 : 1, tflag, tstate, Ifield, fib, force);
+  lb2d_run<St, R, BX, NS, FORM>(src, dst, P, strip, y0, y1, (sgm & 1) ? -1 : 1, tflag, tstate, Ifield, fib,
+                                force);
 }
 
 // The same step in two passes: mode 1 takes the (strip, segment) regions

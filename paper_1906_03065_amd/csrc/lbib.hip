@@ -183,6 +183,7 @@ struct lbib_sim {
   int ring = 3;           // rows in the fused kernel's register ring (4: prefetch)
   int overlap = 0;        // 2D: lattice regions away from the membranes beside the
                           // membrane kernels (0 off, 1 on)
+  int force_form = 0;     // D2Q9: force of eq. ForceFE, 0 potential form, 1 divergence form
   lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
   // optional per-phase timing with HIP events on the stream
   int timing = 0;  // bit mask of timed phases
@@ -433,19 +434,23 @@ struct Engine2D final : lbib_sim {
   // bandwidth with each other and with the membrane kernels
   bool split_step() const { return K > 0 && overlap > 0; }
 
-  // kernel variant for the current (bx, ring)
-  const void* lb_kernel() const {
+  // kernel variant for the current (bx, ring, force form)
+  template <int WPE3, int FORM>
+  const void* lb_kernel_f() const {
     if (ring == 4) {
-      if (bx == 128) return (const void*)&k_lb2d<St, R, 128, 4, 2>;
-      if (bx == 192) return (const void*)&k_lb2d<St, R, 192, 4, 2>;
-      if (bx == 256) return (const void*)&k_lb2d<St, R, 256, 4, 2>;
-      return (const void*)&k_lb2d<St, R, 64, 4, 2>;
+      if (bx == 128) return (const void*)&k_lb2d<St, R, 128, 4, 2, FORM>;
+      if (bx == 192) return (const void*)&k_lb2d<St, R, 192, 4, 2, FORM>;
+      if (bx == 256) return (const void*)&k_lb2d<St, R, 256, 4, 2, FORM>;
+      return (const void*)&k_lb2d<St, R, 64, 4, 2, FORM>;
     }
-    if (bx == 128) return (const void*)&k_lb2d<St, R, 128, 3, 3>;
-    if (bx == 192) return (const void*)&k_lb2d<St, R, 192, 3, 3>;
-    if (bx == 256) return (const void*)&k_lb2d<St, R, 256, 3, 3>;
-    return (const void*)&k_lb2d<St, R, 64, 3, 3>;
+    if (bx == 128) return (const void*)&k_lb2d<St, R, 128, 3, WPE3, FORM>;
+    if (bx == 192) return (const void*)&k_lb2d<St, R, 192, 3, WPE3, FORM>;
+    if (bx == 256) return (const void*)&k_lb2d<St, R, 256, 3, WPE3, FORM>;
+    return (const void*)&k_lb2d<St, R, 64, 3, WPE3, FORM>;
   }
+  // the divergence form keeps three more fields in LDS, which leaves room
+  // for two waves per SIMD: its register budget is sized for that
+  const void* lb_kernel() const { return force_form ? lb_kernel_f<2, 1>() : lb_kernel_f<3, 0>(); }
 
   // rows per workgroup: with seg = 0 (automatic), the whole lattice is cut
   // into exactly as many (strip, segment) workgroups as can be resident at
@@ -487,7 +492,10 @@ struct Engine2D final : lbib_sim {
     // (lanes, ring depth, waves per SIMD) variants of the fused kernel
 #define LB_LAUNCH(BXV, NSV, WPEV)                                                                  \
   do {                                                                                             \
-    if (mode == 0)                                                                                 \
+    if (mode == 0 && force_form == 1)                                                              \
+      hipLaunchKernelGGL((k_lb2d<St, R, BXV, NSV, 2, 1>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, If, \
+                         fib, frc);                                                                \
+    else if (mode == 0)                                                                            \
       hipLaunchKernelGGL((k_lb2d<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, If, \
                          fib, frc);                                                                \
     else                                                                                           \
@@ -826,19 +834,22 @@ struct BatchEngine2D final : lbib_sim {
     return align_up((size_t)n * sizeof(BMember<St>)) + align_up((size_t)std::max(kmax, 1) * sizeof(int2)) +
            align_up((size_t)(n + 1) * 4) + align_up((size_t)NCLS * n * 4) + align_up((size_t)NCLS * (n + 1) * 4);
   }
-  const void* lb_kernel(int c) const {
+  template <int WPE3, int FORM>
+  const void* lb_kernel_f(int c) const {
     const int bx = cls_bx[c];
     if (cls_ring[c] == 4) {
-      if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 4, 2>;
-      if (bx == 192) return (const void*)&kb_lb2d<St, R, 192, 4, 2>;
-      if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 4, 2>;
-      return (const void*)&kb_lb2d<St, R, 64, 4, 2>;
+      if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 4, 2, FORM>;
+      if (bx == 192) return (const void*)&kb_lb2d<St, R, 192, 4, 2, FORM>;
+      if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 4, 2, FORM>;
+      return (const void*)&kb_lb2d<St, R, 64, 4, 2, FORM>;
     }
-    if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 3, 3>;
-    if (bx == 192) return (const void*)&kb_lb2d<St, R, 192, 3, 3>;
-    if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 3, 3>;
-    return (const void*)&kb_lb2d<St, R, 64, 3, 3>;
+    if (bx == 128) return (const void*)&kb_lb2d<St, R, 128, 3, WPE3, FORM>;
+    if (bx == 192) return (const void*)&kb_lb2d<St, R, 192, 3, WPE3, FORM>;
+    if (bx == 256) return (const void*)&kb_lb2d<St, R, 256, 3, WPE3, FORM>;
+    return (const void*)&kb_lb2d<St, R, 64, 3, WPE3, FORM>;
   }
+  // the divergence form's extra LDS ring leaves room for two waves per SIMD
+  const void* lb_kernel(int c) const { return force_form ? lb_kernel_f<2, 1>(c) : lb_kernel_f<3, 0>(c); }
   int resident(const void* k, int threads) const {
     int per_cu = 0, ncu = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -953,8 +964,15 @@ struct BatchEngine2D final : lbib_sim {
       const int* cmc = at<int>(off_cm) + c * n;
       const int* bp = at<int>(off_bpre) + c * (n + 1);
       const BMember<St>* Tc = T;
-#define KB_LAUNCH(BXV, NSV, WPEV) \
-  hipLaunchKernelGGL((kb_lb2d<St, R, BXV, NSV, WPEV>), dim3(lgrid[c]), dim3(BXV), 0, stream, Tc, cmc, bp, ncm[c], parity)
+#define KB_LAUNCH(BXV, NSV, WPEV)                                                                    \
+  do {                                                                                               \
+    if (force_form == 1)                                                                             \
+      hipLaunchKernelGGL((kb_lb2d<St, R, BXV, NSV, 2, 1>), dim3(lgrid[c]), dim3(BXV), 0, stream, Tc, cmc, bp, \
+                         ncm[c], parity);                                                            \
+    else                                                                                             \
+      hipLaunchKernelGGL((kb_lb2d<St, R, BXV, NSV, WPEV>), dim3(lgrid[c]), dim3(BXV), 0, stream, Tc, cmc, bp, \
+                         ncm[c], parity);                                                            \
+  } while (0)
       if (cls_ring[c] == 4) {
         if (cls_bx[c] == 128) KB_LAUNCH(128, 4, 2);
         else if (cls_bx[c] == 192) KB_LAUNCH(192, 4, 2);
@@ -1318,7 +1336,16 @@ int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
 
 int lbib_set_overlap(lbib_sim* s, int on) {
   if (!s || s->is_batch() || on < -1 || on > 1) return LBIB_EINVAL;
+  if (on > 0 && s->force_form != 0) return LBIB_EINVAL;  // one lattice pass only
   s->overlap = on > 0 ? 1 : 0;
+  return LBIB_OK;
+}
+
+int lbib_set_force_form(lbib_sim* s, int form) {
+  if (!s || s->owner || s->D != 2 || form < 0 || form > 1) return LBIB_EINVAL;
+  if (form == 1 && s->overlap) return LBIB_EINVAL;
+  if (s->force_form != form && s->is_batch()) s->mark_dirty();  // new launch plan and graphs
+  s->force_form = form;
   return LBIB_OK;
 }
 

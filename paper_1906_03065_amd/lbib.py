@@ -69,6 +69,7 @@ SIGNATURES = [
     ("lbib_timing_read", C.c_int, [_vp, _dp, C.c_int, _ip]),
     ("lbib_set_launch", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
     ("lbib_set_overlap", C.c_int, [_vp, C.c_int]),
+    ("lbib_set_force_form", C.c_int, [_vp, C.c_int]),
     ("lbib_get_launch", C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     ("lbib_steps_done", C.c_longlong, [_vp]),
     ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
@@ -170,6 +171,8 @@ class Sim:
                                               _vp(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         self.mem_sizes = []
+        if int(p.get("force_form", 0)):
+            self.set_force_form(int(p["force_form"]))
 
     @classmethod
     def _member(cls, batch, h, p: dict):
@@ -287,6 +290,12 @@ class Sim:
         -1 lets the library choose (currently 0)."""
         _chk("lbib_set_overlap", lib().lbib_set_overlap(self.h, int(on)))
 
+    def set_force_form(self, form: int):
+        """D2Q9: 0 (the default) the potential form of the thermodynamic force,
+        1 its divergence form (minus the divergence of the non-ideal pressure
+        tensor, plus the coupling term)."""
+        _chk("lbib_set_force_form", lib().lbib_set_force_form(self.h, int(form)))
+
     def get_launch(self):
         a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         _chk("lbib_get_launch", lib().lbib_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c),
@@ -324,6 +333,9 @@ class Batch:
         self.torch = torch
         self.device = torch.device(device)
         n = len(params)
+        forms = {int(p.get("force_form", 0)) for p in params}
+        if len(forms) > 1:
+            raise LbibError("lbib_batch_create", EINVAL)  # one force form per batch
         membranes = membranes or [()] * n
         arr = (Params * n)(*[make_params(p, "fp32", membranes=m) for p, m in zip(params, membranes)])
         self._prms = arr
@@ -340,6 +352,13 @@ class Batch:
             mh = _vp()
             _chk("lbib_batch_member", lib().lbib_batch_member(self.h, k, C.byref(mh)))
             self.members.append(Sim._member(self, mh, params[k]))
+        if forms.pop():
+            self.set_force_form(1)
+
+    def set_force_form(self, form: int):
+        """Force form of every member (see Sim.set_force_form); the next step
+        captures the batch's graphs again."""
+        _chk("lbib_set_force_form", lib().lbib_set_force_form(self.h, int(form)))
 
     def __len__(self):
         return len(self.members)
