@@ -41,11 +41,13 @@ def base_params(nx, ny, nz=1, lattice=0, wall_y=0, wall_z=0, kappa=(0.02, 0.02, 
                 kappa_c=0.01, tau=1.0, tau_phi=1.0, tau_psi=1.0, mobility=None, gamma=1.0,
                 r_cut=0.0) -> dict:
     """Parameter dictionary.  ``mobility`` M sets Gamma = M/(tau - 1/2) for both
-    order parameters (eq. RelaxationTimes); otherwise ``gamma`` is used."""
+    order parameters (eq. RelaxationTimes), or a pair (M_phi, M_psi) sets each
+    (Sec. 2.5 names M_phi = 3 M_psi); otherwise ``gamma`` is used."""
     gphi = gpsi = gamma
     if mobility is not None:
-        gphi = mobility / (tau_phi - 0.5)
-        gpsi = mobility / (tau_psi - 0.5)
+        m_phi, m_psi = (mobility, mobility) if np.isscalar(mobility) else mobility
+        gphi = m_phi / (tau_phi - 0.5)
+        gpsi = m_psi / (tau_psi - 0.5)
     return dict(lattice=lattice, nx=int(nx), ny=int(ny), nz=int(nz), wall_y=int(wall_y),
                 wall_z=int(wall_z), tau=float(tau), tau_phi=float(tau_phi), tau_psi=float(tau_psi),
                 gamma_phi=float(gphi), gamma_psi=float(gpsi),
@@ -173,6 +175,28 @@ def c2(seed=SEED_BASE + 1, n=2048, n_caps=16, with_fields=True):
         C2 = 1.0 - C1 - C3
         w["fields"] = fields_from_C(C1, C2, C3, 1e-4, seed)
     return w
+
+
+def mode_decay(mode, nx=96, ny=4, mobility=(0.3, 0.1), kappa=(0.05, 0.05, 0.08), alpha=1.0, tau_phi=0.8,
+               tau_psi=1.3, amp=1e-5):
+    """A uniform bulk phase with a small sinusoidal perturbation along x, one
+    wavelength over the periodic box, for the decay rates of the order
+    parameters (Sec. 2.5 mobilities): mode "phi" perturbs phi in the C3 bulk,
+    mode "psi" perturbs psi in the C1 bulk (at fixed rho and phi).  No
+    membrane, no coupling."""
+    p = base_params(nx, ny, wall_y=0, kappa=kappa, alpha=alpha, kappa_c=0.0, tau_phi=tau_phi,
+                    tau_psi=tau_psi, mobility=mobility)
+    x, _ = _grid2(nx, ny)
+    s = amp * np.sin(2.0 * np.pi * x / nx)
+    rho = np.ones((ny, nx))
+    if mode == "phi":
+        phi, psi = s, np.ones((ny, nx))
+    elif mode == "psi":
+        phi, psi = np.ones((ny, nx)), s
+    else:
+        raise ValueError(mode)
+    return dict(params=p, fields=dict(rho=rho, phi=phi, psi=psi), membranes=[],
+                name=f"mode_decay_{mode}_{nx}x{ny}")
 
 
 def flat(nx=4, ny=64, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_y=1, seed=None):

@@ -77,3 +77,51 @@ def lens_angles(c3, y0, margin=4.0):
     _, yu, ru = circ(P[P[:, 1] > y0 + margin])
     _, yd, rd = circ(P[P[:, 1] < y0 - margin])
     return np.degrees(np.arccos((y0 - yu) / ru)), np.degrees(np.arccos((yd - y0) / rd))
+
+
+def mode_amplitude(f, mode):
+    """Amplitude of the sin(2 pi x / nx) component of phi = C1 - C2 (mode
+    "phi") or psi = C3 (mode "psi") on the first row."""
+    q = (f["c1"] - f["c2"]) if mode == "phi" else f["c3"]
+    nx = q.shape[1]
+    return 2.0 * float(np.mean(q[0] * np.sin(2.0 * np.pi * np.arange(nx) / nx)))
+
+
+def decay_rate(sim, mode, steps=3600, every=450, skip=2):
+    """Exponential decay rate per step of a mode_decay workload's perturbation,
+    fitted to its amplitude every `every` steps after the first `skip`."""
+    t, a = [], []
+    for n in range(0, steps + 1, every):
+        sim.step(n - sim.steps_done)
+        t.append(n)
+        a.append(abs(mode_amplitude(sim.fields(), mode)))
+    return -float(np.polyfit(t[skip:], np.log(a[skip:]), 1)[0])
+
+
+def ch_rate(p, mode, density_response=True):
+    """Decay rate of a small sin(k x) perturbation in a bulk phase from the
+    linearised Cahn-Hilliard equation dq/dt = M lap mu_q (Sec. 2.5), with
+    M = Gamma (tau - 1/2) and the chemical potentials of the Landau energy:
+    about C = 0 or 1, d/dC [C (1 - C)(1 - 2C)] = 1, so each concentration's
+    b_m = kappa_m (1 + alpha^2 K) dC_m, where K = 2 (1 - cos k) is the
+    isotropic Laplacian stencil's eigenvalue for a wave along x.
+      phi in the C3 bulk: dC1 = -dC2 = dphi/2, mu_phi = (b1 - b2)/2 gives
+      rate = M_phi K (kappa1 + kappa2)/4 (1 + alpha^2 K); with kappa1 =
+      kappa2 no other field is driven.
+      psi in the C1 bulk (phi fixed, kappa1 = kappa2): dC1 = dC2 =
+      (drho - dpsi)/2, so mu_rho = A (drho - dpsi) with A = (kappa1 +
+      kappa2)/4 (1 + alpha^2 K); the fluid balances it with its pressure,
+      c_s^2 grad drho = -grad mu_rho, i.e. drho = 3 A dpsi / (1 + 3 A), and
+      mu_psi = b3 - (b1 + b2)/2 = [kappa3 (1 + alpha^2 K) + A / (1 + 3 A)] dpsi.
+    density_response=False drops the pressure balance (drho = 0)."""
+    nx = p["nx"]
+    K = 2.0 * (1.0 - np.cos(2.0 * np.pi / nx))
+    k1, k2, k3 = p["kappa"]
+    a2 = p["alpha"] ** 2
+    if mode == "phi":
+        M = p["gamma_phi"] * (p["tau_phi"] - 0.5)
+        return M * K * (k1 + k2) / 4.0 * (1.0 + a2 * K)
+    M = p["gamma_psi"] * (p["tau_psi"] - 0.5)
+    A = (k1 + k2) / 4.0 * (1.0 + a2 * K)
+    extra = A / (1.0 + 3.0 * A) if density_response else A
+    return M * K * (k3 * (1.0 + a2 * K) + extra)
