@@ -108,6 +108,21 @@ int lbib_add_membrane(lbib_sim* s, int n_nodes, const double* X, int n_elems, co
    that is not positive and finite. */
 int lbib_set_rest(lbib_sim* s, int id, const double* rest);
 
+/* Strain law of 2D ring id (the paper's law and the two hyperelastic laws it
+   names as alternatives).  Per segment the strain energy is W(lam) times the
+   rest length, lam = length / rest length:
+     0 (default)  ks/2 (lam - 1)^2, eq. DiscreteSE
+     1            ks/8 (lam - 1/lam)^2, the neo-Hookean membrane law
+                  G/2 (l1^2 + l2^2 + (l1 l2)^-2 - 3) at plane strain (l2 = 1)
+                  with G = ks/4
+     2            ks/8 (lam^2 - 1)^2, the Skalak law G/4 (I1^2 + 2 I1 - 2 I2
+                  + C I2^2) at plane strain with G (1 + C) = ks/2
+   All three have the same small-strain stiffness ks; the forces are minus the
+   energy's gradient and the energies enter lbib_energy's E_s.  Takes effect
+   at the next step.  Synchronises.  LBIB_EINVAL for another law, an unknown
+   id, a batch handle, or a law other than 0 on a D3Q19 mesh. */
+int lbib_set_membrane_law(lbib_sim* s, int id, int law);
+
 /* Initial macroscopic fields (host, N doubles each; uz may be NULL in 2D and
    ux, uy may be NULL for a fluid at rest).  Builds the equilibrium
    populations of eq. EDF, with the chemical potentials of Appendix A taken

@@ -88,6 +88,10 @@ def lib():
         L.orc_collide.argtypes = [C.POINTER(Params), _dp, _dp, C.c_double, C.c_double, _dp]
         L.orc_grad_lap.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_ring_forces.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.orc_ring_forces_law.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_int, _dp, _dp,
+                                          _dp]
+        L.orc_set_membrane_law.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.orc_set_rest.argtypes = [C.c_void_p, C.c_int, _dp]
         L.orc_mesh_forces.argtypes = [C.c_int, _dp, C.c_int, _ip, _dp, C.c_double, C.c_double,
                                       _dp, _dp, _dp]
         L.orc_coupling.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
@@ -173,6 +177,17 @@ class Sim:
             raise ValueError(f"orc_add_membrane failed ({r})")
         self.mem_sizes.append(n)
         return r
+
+    def set_membrane_law(self, id: int, law: int):
+        """Strain law of ring id: 0 eq. DiscreteSE, 1 neo-Hookean, 2 Skalak."""
+        if lib().orc_set_membrane_law(self.h, int(id), int(law)):
+            raise ValueError("orc_set_membrane_law failed")
+
+    def set_rest(self, id: int, rest):
+        """Rest lengths of ring id, one per segment l -> l+1."""
+        rest = _f64(rest).reshape(-1)
+        if rest.size != self.mem_sizes[id] or lib().orc_set_rest(self.h, int(id), _d(rest)):
+            raise ValueError("orc_set_rest failed")
 
     def set_fields(self, rho, phi, psi, u=None):
         rho, phi, psi = (_f64(a).reshape(-1) for a in (rho, phi, psi))
@@ -302,13 +317,14 @@ def collide(p: dict, pops, F, mu_phi, mu_psi):
     return out[:q], out[q:2 * q], out[2 * q:]
 
 
-def ring_forces(X, rest, kappa_s, kappa_b):
+def ring_forces(X, rest, kappa_s, kappa_b, law=0):
     X = _f64(X).reshape(-1, 2)
     n = X.shape[0]
     rest = _f64(rest).reshape(-1)
     F = np.empty((n, 2))
     es, eb = C.c_double(), C.c_double()
-    r = lib().orc_ring_forces(n, _d(X), _d(rest), kappa_s, kappa_b, _d(F), C.byref(es), C.byref(eb))
+    r = lib().orc_ring_forces_law(n, _d(X), _d(rest), kappa_s, kappa_b, int(law), _d(F), C.byref(es),
+                                  C.byref(eb))
     if r:
         raise ValueError("orc_ring_forces failed")
     return F, es.value, eb.value

@@ -48,6 +48,7 @@ typedef struct {
   int* edge;      /* 2 per edge (3D)                            */
   int* etri;      /* 2 per edge: the adjacent triangles (3D)    */
   double ks, kb;
+  int law;        /* strain law of a 2D ring (orc_set_membrane_law)  */
 } mem_t;
 
 struct orc_sim {
@@ -352,21 +353,55 @@ int orc_interp(const orc_sim* s, int n, const double* X, const double* v, double
 /* DiscreteArcLength, DiscreteSF, DiscreteBF.                          */
 /* Markers l = 0..n-1 form a closed ring; segment l joins l and l+1.   */
 /* ------------------------------------------------------------------ */
+/* Strain energy per unit rest length of a segment stretched by lam, and its
+   derivative dW/dlam (the segment's tension).  law 0: eq. DiscreteSE,
+   ks/2 (lam - 1)^2.  Laws 1 and 2 (READING: the paper names neo-Hookean and
+   Skalak membranes without formulas): the membrane laws per unit reference
+   area with the second principal stretch fixed at 1 (a 2D ring is the
+   section of a membrane under plane strain), scaled to the same small-strain
+   modulus ks:
+     neo-Hookean  G/2 (l1^2 + l2^2 + 1/(l1 l2)^2 - 3), G = ks/4
+                  -> ks/8 (lam - 1/lam)^2
+     Skalak       G/4 (I1^2 + 2 I1 - 2 I2 + C I2^2), I1 = l1^2 + l2^2 - 2,
+                  I2 = (l1 l2)^2 - 1, G (1 + C) = ks/2
+                  -> ks/8 (lam^2 - 1)^2 (C only scales it at plane strain) */
+static void strain_law(int law, double ks, double lam, double* W, double* T) {
+  if (law == 1) {
+    double q = lam - 1.0 / lam;
+    *W = ks / 8.0 * q * q;
+    *T = ks / 4.0 * q * (1.0 + 1.0 / (lam * lam));
+  } else if (law == 2) {
+    double q = lam * lam - 1.0;
+    *W = ks / 8.0 * q * q;
+    *T = ks / 2.0 * q * lam;
+  } else {
+    double q = lam - 1.0;
+    *W = 0.5 * ks * q * q;
+    *T = ks * q;
+  }
+}
+
 int orc_ring_forces(int n, const double* X, const double* rest, double ks, double kb, double* F,
                     double* E_s, double* E_b) {
-  if (n < 3) return -1;
+  return orc_ring_forces_law(n, X, rest, ks, kb, 0, F, E_s, E_b);
+}
+
+int orc_ring_forces_law(int n, const double* X, const double* rest, double ks, double kb, int law,
+                        double* F, double* E_s, double* E_b) {
+  if (n < 3 || law < 0 || law > 2) return -1;
   double es = 0.0, eb = 0.0;
   for (int l = 0; l < 2 * n; l++) F[l] = 0.0;
-  /* strain: E_s = ks/2 sum (len_l/ds_l - 1)^2 ds_l */
+  /* strain: E_s = sum_l W(len_l/ds_l) ds_l */
   for (int l = 0; l < n; l++) {
     int m = (l + 1) % n;
     double dx = X[2 * m] - X[2 * l], dy = X[2 * m + 1] - X[2 * l + 1];
     double len = sqrt(dx * dx + dy * dy);
     double ds = rest[l];
-    double strain = len / ds - 1.0;
-    es += 0.5 * ks * strain * strain * ds;
-    /* dE/dX_m = ks strain e_l, dE/dX_l = -ks strain e_l */
-    double gx = ks * strain * dx / len, gy = ks * strain * dy / len;
+    double W, T;
+    strain_law(law, ks, len / ds, &W, &T);
+    es += W * ds;
+    /* dE/dX_m = T e_l, dE/dX_l = -T e_l (e_l the unit vector l -> m) */
+    double gx = T * dx / len, gy = T * dy / len;
     F[2 * m] -= gx;
     F[2 * m + 1] -= gy;
     F[2 * l] += gx;
@@ -1139,7 +1174,7 @@ static void one_step(orc_sim* s) {
       double* X2 = (double*)malloc(sizeof(double) * 2 * M->n);
       double* F2 = (double*)malloc(sizeof(double) * 2 * M->n);
       for (int l = 0; l < M->n; l++) { X2[2 * l] = M->X[3 * l]; X2[2 * l + 1] = M->X[3 * l + 1]; }
-      orc_ring_forces(M->n, X2, M->rest, M->ks, M->kb, F2, NULL, NULL);
+      orc_ring_forces_law(M->n, X2, M->rest, M->ks, M->kb, M->law, F2, NULL, NULL);
       for (int l = 0; l < M->n; l++) { Fm[3 * l] = F2[2 * l]; Fm[3 * l + 1] = F2[2 * l + 1]; }
       free(X2);
       free(F2);
@@ -1324,6 +1359,22 @@ int orc_get_fields(const orc_sim* s, double* rho, double* c1, double* c2, double
   return 0;
 }
 
+int orc_set_membrane_law(orc_sim* s, int id, int law) {
+  if (!s || id < 0 || id >= s->nmem || law < 0 || law > 2) return -1;
+  if (s->D == 3 && law != 0) return -1; /* the laws are defined for 2D rings */
+  s->mem[id].law = law;
+  return 0;
+}
+
+int orc_set_rest(orc_sim* s, int id, const double* rest) {
+  if (!s || !rest || id < 0 || id >= s->nmem || s->D != 2) return -1;
+  mem_t* M = &s->mem[id];
+  for (int j = 0; j < M->nedge; j++)
+    if (!(rest[j] > 0.0) || !isfinite(rest[j])) return -1;
+  for (int j = 0; j < M->nedge; j++) M->rest[j] = rest[j];
+  return 0;
+}
+
 int orc_get_membrane(const orc_sim* s, int id, double* X, double* U, double* F) {
   if (!s || id < 0 || id >= s->nmem) return -1;
   const mem_t* M = &s->mem[id];
@@ -1387,7 +1438,7 @@ int orc_energy(orc_sim* s, orc_energies* out) {
     if (D == 2) {
       double* X2 = (double*)malloc(sizeof(double) * 2 * M->n);
       for (int l = 0; l < M->n; l++) { X2[2 * l] = M->X[3 * l]; X2[2 * l + 1] = M->X[3 * l + 1]; }
-      orc_ring_forces(M->n, X2, M->rest, M->ks, M->kb, F, &es, &eb);
+      orc_ring_forces_law(M->n, X2, M->rest, M->ks, M->kb, M->law, F, &es, &eb);
       free(X2);
     } else {
       orc_mesh_forces(M->n, M->X, M->ntri, M->tri, M->rest, M->ks, M->kb, F, &es, &eb);

@@ -75,6 +75,13 @@ int      orc_set_threads(int n);   /* OpenMP threads for node loops; returns the
 int orc_add_membrane(orc_sim* s, int n_nodes, const double* X, int n_tris, const int* tris,
                      double kappa_s, double kappa_b);
 
+/* Strain law of membrane id (2D rings): 0 eq. DiscreteSE (default), 1
+ * neo-Hookean, 2 Skalak, both reduced to plane strain at the same
+ * small-strain modulus.  Rest lengths of ring id, per segment l -> l+1
+ * (2D only).                                                              */
+int orc_set_membrane_law(orc_sim* s, int id, int law);
+int orc_set_rest(orc_sim* s, int id, const double* rest);
+
 /* Macroscopic initial fields (N each; uz may be NULL in 2D).  Builds the
  * equilibrium populations, using the membranes added so far for I.          */
 int orc_set_fields(orc_sim* s, const double* rho, const double* phi, const double* psi,
@@ -111,6 +118,9 @@ int orc_grad_lap(const orc_sim* s, const double* q, double* grad /*N*d*/, double
 /* 2D ring membrane energies and forces F = -dE/dX (strain + bending) */
 int orc_ring_forces(int n, const double* X, const double* rest, double kappa_s, double kappa_b,
                     double* F, double* E_s, double* E_b);
+/* the same with the strain law of orc_set_membrane_law */
+int orc_ring_forces_law(int n, const double* X, const double* rest, double kappa_s, double kappa_b,
+                        int law, double* F, double* E_s, double* E_b);
 /* 3D mesh membrane energies and forces */
 int orc_mesh_forces(int n, const double* X, int n_tris, const int* tris, const double* rest_edge,
                     double kappa_s, double kappa_b, double* F, double* E_s, double* E_b);

@@ -39,6 +39,7 @@ struct MemDev {
   int* mid;           // membrane id of every marker
   double* ks;         // K
   double* kb;         // K
+  int* law;           // K, strain law of each 2D ring (0 eq. DiscreteSE, 1 neo-Hookean, 2 Skalak)
   double* mbox;       // 8 per membrane: lo xyz, hi xyz, orientation (+-1), spare
   int* status;        // [0] force/marker out of range, [1] lattice too small / too many membranes
   float4* stab;       // 2D, per step: segment l -> l+1 as (start - box centre, edge) in FP32
@@ -708,6 +709,30 @@ __device__ __forceinline__ void bend_grad(double ax, double ay, double bx, doubl
   gby = c1 * tby - c2 * by / lb;
 }
 
+// Strain energy W per unit rest length of a ring segment stretched by lam
+// and its tension dW/dlam.  0: eq. DiscreteSE, ks/2 (lam - 1)^2.  1 and 2:
+// the neo-Hookean and Skalak membrane laws with the second principal stretch
+// held at 1 (plane strain, of which a 2D ring is the section), with moduli
+// giving the same small-strain stiffness ks: ks/8 (lam - 1/lam)^2 and
+// ks/8 (lam^2 - 1)^2.
+__device__ __forceinline__ double seg_tension(int law, double ks, double lam) {
+  if (law == 1) return 0.25 * ks * (lam - 1.0 / lam) * (1.0 + 1.0 / (lam * lam));
+  if (law == 2) return 0.5 * ks * lam * (lam * lam - 1.0);
+  return ks * (lam - 1.0);
+}
+__device__ __forceinline__ double seg_energy(int law, double ks, double lam) {
+  if (law == 1) {
+    const double q = lam - 1.0 / lam;
+    return 0.125 * ks * q * q;
+  }
+  if (law == 2) {
+    const double q = lam * lam - 1.0;
+    return 0.125 * ks * q * q;
+  }
+  const double q = lam - 1.0;
+  return 0.5 * ks * q * q;
+}
+
 __device__ __forceinline__ void memforce2d_run(const MemDev& md, int g, double& Fxo, double& Fyo) {
   const int m = md.mid[g];
   const int b = md.moff[m], n = md.moff[m + 1] - b;
@@ -715,17 +740,19 @@ __device__ __forceinline__ void memforce2d_run(const MemDev& md, int g, double& 
   auto P = [&](int k, int a) { return md.X[3 * (b + ((l + k) % n + n) % n) + a]; };
   auto rest = [&](int k) { return md.rest[b + ((l + k) % n + n) % n]; };
   const double ks = md.ks[m], kbm = md.kb[m];
+  const int law = md.law[m];
   double Fx = 0, Fy = 0;
-  // strain, eq. DiscreteSF: segments l-1 -> l and l -> l+1
+  // strain, eq. DiscreteSF: segments l-1 -> l and l -> l+1, each pulling
+  // with its tension along itself
   {
     const double ex = P(1, 0) - P(0, 0), ey = P(1, 1) - P(0, 1);
     const double len = sqrt(ex * ex + ey * ey);
-    const double s = ks * (len / rest(0) - 1.0) / len;
+    const double s = seg_tension(law, ks, len / rest(0)) / len;
     Fx += s * ex;
     Fy += s * ey;
     const double fx = P(0, 0) - P(-1, 0), fy = P(0, 1) - P(-1, 1);
     const double lf = sqrt(fx * fx + fy * fy);
-    const double sf = ks * (lf / rest(-1) - 1.0) / lf;
+    const double sf = seg_tension(law, ks, lf / rest(-1)) / lf;
     Fx -= sf * fx;
     Fy -= sf * fy;
   }

@@ -155,8 +155,7 @@ __global__ void k_memenergy2d(MemDev md, double* __restrict__ out) {
   const int lp = b + (l + 1) % n, lm = b + (l + n - 1) % n;
   const double ex = md.X[3 * lp] - md.X[3 * g], ey = md.X[3 * lp + 1] - md.X[3 * g + 1];
   const double len = sqrt(ex * ex + ey * ey);
-  const double st = len / md.rest[g] - 1.0;
-  out[2 * g] = 0.5 * md.ks[m] * st * st * md.rest[g];
+  out[2 * g] = seg_energy(md.law[m], md.ks[m], len / md.rest[g]) * md.rest[g];
   double gax, gay, gbx, gby, e;
   bend_grad(ex, ey, md.X[3 * g] - md.X[3 * lm], md.X[3 * g + 1] - md.X[3 * lm + 1], md.kb[m], gax, gay,
             gbx, gby, e);

@@ -59,7 +59,7 @@ struct Layout {
   size_t pops[2];       // population buffers A, B
   size_t pop_bytes;     // bytes of one buffer
   size_t Ifield, fib, force, tflag, tlist, tstate, stage, part;
-  size_t X, U, F, Facc, rest, moff, mid, ks, kb, mbox, status, memE, stab, sinv;
+  size_t X, U, F, Facc, rest, moff, mid, ks, kb, law, mbox, status, memE, stab, sinv;
   // 3D: moment field and triangle meshes
   size_t mom, tri, toff, edge, erest, eoff, emem, tadj, vtoff, vt, fn, vn, ttab, ctab, coff;
   int maxCl;
@@ -134,6 +134,7 @@ Layout make_layout(const lbib_params* p) {
   L.mid = c.take((size_t)M * 4);
   L.ks = c.take((size_t)K * 8);
   L.kb = c.take((size_t)K * 8);
+  L.law = c.take((size_t)K * 4);
   L.mbox = c.take((size_t)K * 8 * 8);
   L.status = c.take(64);
   L.memE = c.take(64);
@@ -255,6 +256,7 @@ struct lbib_sim {
     m.mid = at<int>(L.mid);
     m.ks = at<double>(L.ks);
     m.kb = at<double>(L.kb);
+    m.law = at<int>(L.law);
     m.mbox = at<double>(L.mbox);
     m.status = at<int>(L.status);
     m.stab = at<float4>(L.stab);
@@ -1220,6 +1222,8 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
   HIPCHK(hipMemcpyAsync(s->ws + s->L.mid + (size_t)off * 4, mid.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(s->ws + s->L.ks + (size_t)s->K * 8, &ks, 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(s->ws + s->L.kb + (size_t)s->K * 8, &kb, 8, hipMemcpyHostToDevice, st));
+  const int law0 = 0;
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.law + (size_t)s->K * 4, &law0, 4, hipMemcpyHostToDevice, st));
   s->moff.push_back(off + n);
   HIPCHK(hipMemcpyAsync(s->ws + s->L.moff, s->moff.data(), s->moff.size() * 4, hipMemcpyHostToDevice, st));
   if (s->D == 3) {
@@ -1338,6 +1342,14 @@ int lbib_set_overlap(lbib_sim* s, int on) {
   if (!s || s->is_batch() || on < -1 || on > 1) return LBIB_EINVAL;
   if (on > 0 && s->force_form != 0) return LBIB_EINVAL;  // one lattice pass only
   s->overlap = on > 0 ? 1 : 0;
+  return LBIB_OK;
+}
+
+int lbib_set_membrane_law(lbib_sim* s, int id, int law) {
+  if (!s || s->is_batch() || id < 0 || id >= s->K || law < 0 || law > 2) return LBIB_EINVAL;
+  if (s->D != 2 && law != 0) return LBIB_EINVAL;
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.law + (size_t)id * 4, &law, 4, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
   return LBIB_OK;
 }
 

@@ -76,6 +76,7 @@ SIGNATURES = [
     ("lbib_strerror", C.c_char_p, [C.c_int]),
     ("lbib_destroy", None, [_vp]),
     ("lbib_set_rest", C.c_int, [_vp, C.c_int, _dp]),
+    ("lbib_set_membrane_law", C.c_int, [_vp, C.c_int, C.c_int]),
     ("lbib_batch_workspace_bytes", C.c_int, [C.c_int, _vp, C.POINTER(C.c_size_t)]),
     ("lbib_batch_create", C.c_int, [C.c_int, _vp, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     ("lbib_batch_member", C.c_int, [_vp, C.c_int, C.POINTER(_vp)]),
@@ -221,6 +222,10 @@ class Sim:
         if rest is not None:
             self.set_rest(mid.value, rest)
         return mid.value
+
+    def set_membrane_law(self, i: int, law: int):
+        """Strain law of ring i: 0 eq. DiscreteSE, 1 neo-Hookean, 2 Skalak."""
+        _chk("lbib_set_membrane_law", lib().lbib_set_membrane_law(self.h, int(i), int(law)))
 
     def set_rest(self, i: int, rest):
         r = np.ascontiguousarray(rest, dtype=np.float64).reshape(-1)
@@ -432,7 +437,9 @@ class Batch:
         b = cls([w["params"] for w in ws], [w["membranes"] for w in ws], device=device, stream=stream)
         for m, w in zip(b.members, ws):
             for mem in w["membranes"]:
-                m.add_membrane(mem["X"], mem.get("tris"), mem["kappa_s"], mem["kappa_b"], mem.get("rest"))
+                i = m.add_membrane(mem["X"], mem.get("tris"), mem["kappa_s"], mem["kappa_b"], mem.get("rest"))
+                if mem.get("law", 0):
+                    m.set_membrane_law(i, mem["law"])
             f = w["fields"]
             m.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
         return b
@@ -515,7 +522,9 @@ def from_workload(w: dict, storage="fp32", device="cuda:0", **kw) -> Sim:
     """Create a GPU simulation from a workloads.* dictionary."""
     s = Sim(w["params"], storage=storage, membranes=w["membranes"], device=device, **kw)
     for m in w["membranes"]:
-        s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"], m.get("rest"))
+        i = s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"], m.get("rest"))
+        if m.get("law", 0):
+            s.set_membrane_law(i, m["law"])
     f = w["fields"]
     s.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
     return s

@@ -199,6 +199,20 @@ def mode_decay(mode, nx=96, ny=4, mobility=(0.3, 0.1), kappa=(0.05, 0.05, 0.08),
                 name=f"mode_decay_{mode}_{nx}x{ny}")
 
 
+def prestressed_ring(law=0, n=64, R=12.0, n_markers=64, kappa_s=0.05, lam0=1.25, kappa=(1e-4, 1e-4, 1e-4)):
+    """A ring of markers on a circle of radius R in a uniform fluid (C1, no
+    coupling) whose rest lengths are the chords divided by lam0, so that it
+    starts stretched by lam0 and pulls inward; strain law `law` (0 eq.
+    DiscreteSE, 1 neo-Hookean, 2 Skalak).  Small kappa_m keep the non-ideal
+    pressure negligible against the ring's pressure jump."""
+    p = base_params(n, n, kappa=kappa, kappa_c=0.0, mobility=0.1)
+    X = circle_markers(n / 2.0, n / 2.0, R, n_markers)
+    rest = np.linalg.norm(np.roll(X, -1, axis=0) - X, axis=1) / lam0
+    f = dict(rho=np.ones((n, n)), phi=np.ones((n, n)), psi=np.zeros((n, n)))
+    mem = [dict(X=X, tris=None, kappa_s=kappa_s, kappa_b=0.0, rest=rest, law=int(law))]
+    return dict(params=p, fields=f, membranes=mem, name=f"prestressed_ring_law{law}_{n}x{n}")
+
+
 def flat(nx=4, ny=64, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_y=1, seed=None):
     """Flat C1/C2 interface at y = (ny-1)/2, C1 below; no membrane."""
     p = base_params(nx, ny, wall_y=wall_y, kappa=kappa, alpha=alpha, kappa_c=0.0, mobility=mobility)

@@ -14,7 +14,11 @@ def normwise(a, b):
 def run_oracle(orc, w):
     s = orc.Sim(w["params"])
     for m in w["membranes"]:
-        s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"])
+        i = s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"])
+        if m.get("rest") is not None:
+            s.set_rest(i, m["rest"])
+        if m.get("law", 0):
+            s.set_membrane_law(i, m["law"])
     f = w["fields"]
     s.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
     return s
@@ -125,3 +129,29 @@ def ch_rate(p, mode, density_response=True):
     A = (k1 + k2) / 4.0 * (1.0 + a2 * K)
     extra = A / (1.0 + 3.0 * A) if density_response else A
     return M * K * (k3 * (1.0 + a2 * K) + extra)
+
+
+def ring_law_tension(law, ks, lam):
+    """dW/dlam of the ring strain laws, from the general membrane laws at
+    plane strain: neo-Hookean G/2 (l1^2 + l2^2 + (l1 l2)^-2 - 3) with G = ks/4,
+    Skalak G/4 (I1^2 + 2 I1 - 2 I2 + C I2^2) with G (1 + C) = ks/2, and the
+    paper's ks/2 (lam - 1)^2, differentiated by hand at l2 = 1."""
+    if law == 1:
+        return ks / 4.0 * (lam - lam ** -3)
+    if law == 2:
+        return ks / 2.0 * (lam ** 3 - lam)
+    return ks * (lam - 1.0)
+
+
+def ring_laplace(sim, w, n_markers_mem=0):
+    """(pressure jump across a prestressed ring measured between the box
+    centre and corner, T(lam)/R from its current mean radius)."""
+    f = sim.fields()
+    n = w["params"]["nx"]
+    m = w["membranes"][0]
+    X = sim.membrane(0)["X"][:, :2]
+    Rm = float(np.linalg.norm(X - n / 2.0, axis=1).mean())
+    R0 = float(np.linalg.norm(m["X"] - n / 2.0, axis=1).mean())
+    lam = Rm / R0 * float(np.mean(np.linalg.norm(np.roll(m["X"], -1, axis=0) - m["X"], axis=1) / m["rest"]))
+    dp = (f["rho"][n // 2, n // 2] - f["rho"][0, 0]) / 3.0
+    return dp, ring_law_tension(m["law"], m["kappa_s"], lam) / Rm
