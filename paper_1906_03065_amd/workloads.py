@@ -400,20 +400,21 @@ TAYLOR_MODULI = ((1e-3, 1e-4), (1e-3, 1e-2), (1e-2, 1e-4), (1e-2, 1e-2), (1e-1, 
 
 
 def taylor2d(kappa3, kappa_s, kappa_b, symmetric=True, R=20.0, n_markers=160, alpha=2.0, kappa_c=1e-2,
-             mobility=0.1, seed=SEED_BASE + 7, offset=(0.0, 0.0)):
+             mobility=0.1, seed=SEED_BASE + 7, offset=(0.0, 0.0), u0=None):
     """Capsule at a fluid-fluid interface as in Sec. 4.1: an initially
     circular capsule of radius R at the centre of a 12R x 6R box periodic in
     both directions, on a flat C1/C2 interface (C1 below), alpha 2, kappa_c
     1e-2; kappa_1 = kappa_2 = 8e-3 (symmetric) or kappa_1 = 8e-3, kappa_2 =
     2e-3 (asymmetric).  The band is 12 alpha wide, so that the band of a
     deformed capsule fits in the 6R-high box.  `offset` moves the capsule
-    and the interface off the lattice's symmetry lines."""
+    and the interface off the lattice's symmetry lines; `u0` gives every
+    fluid an initial horizontal velocity (the moving frames of Sec. 4.1)."""
     kappa = (8e-3, 8e-3 if symmetric else 2e-3, float(kappa3))
     nx, ny = int(12 * R), int(6 * R)
     centre = (nx / 2.0 + offset[0], (ny - 1) / 2.0 + offset[1])
     w = capsule_at_interface(nx=nx, ny=ny, R=R, n_markers=n_markers, kappa=kappa, centre=centre,
                              alpha=alpha, kappa_c=kappa_c, kappa_s=kappa_s, kappa_b=kappa_b, wall_y=0,
-                             mobility=mobility, seed=seed, r_cut=12.0 * alpha)
+                             mobility=mobility, seed=seed, r_cut=12.0 * alpha, u0=u0)
     w["name"] = f"taylor_{'sym' if symmetric else 'asym'}_k3_{kappa3:g}_ks_{kappa_s:g}_kb_{kappa_b:g}"
     return w
 
