@@ -117,10 +117,16 @@ int lbib_set_rest(lbib_sim* s, int id, const double* rest);
                   with G = ks/4
      2            ks/8 (lam^2 - 1)^2, the Skalak law G/4 (I1^2 + 2 I1 - 2 I2
                   + C I2^2) at plane strain with G (1 + C) = ks/2
-   All three have the same small-strain stiffness ks; the forces are minus the
-   energy's gradient and the energies enter lbib_energy's E_s.  Takes effect
-   at the next step.  Synchronises.  LBIB_EINVAL for another law, an unknown
-   id, a batch handle, or a law other than 0 on a D3Q19 mesh. */
+   All three have the same small-strain stiffness ks.  On a D3Q19 mesh, law 0
+   is the edge-spring law and laws 1 and 2 replace the springs by the
+   membrane laws per triangle: each flat triangle maps linearly from its rest
+   shape (its three rest edge lengths, lbib_set_rest) to its current one, with
+   I1 = l1^2 + l2^2 and J = l1 l2 = area / rest area, energy rest area x
+   G/2 (I1 + J^-2 - 3) (neo-Hookean) or G/4 ((I1-2)^2 + 2 (I1-2) - 2 (J^2-1)
+   + (J^2-1)^2) (Skalak, C = 1), shear modulus G = ks; bending is unchanged.
+   The forces are minus the energy's gradient and the energies enter
+   lbib_energy's E_s.  Takes effect at the next step.  Synchronises.
+   LBIB_EINVAL for another law, an unknown id or a batch handle. */
 int lbib_set_membrane_law(lbib_sim* s, int id, int law);
 
 /* Initial macroscopic fields (host, N doubles each; uz may be NULL in 2D and

@@ -91,6 +91,8 @@ def lib():
         L.orc_ring_forces_law.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, C.c_int, _dp, _dp,
                                           _dp]
         L.orc_set_membrane_law.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.orc_mesh_forces_law.argtypes = [C.c_int, _dp, C.c_int, _ip, _dp, C.c_double, C.c_double, C.c_int,
+                                          _dp, _dp, _dp]
         L.orc_set_rest.argtypes = [C.c_void_p, C.c_int, _dp]
         L.orc_mesh_forces.argtypes = [C.c_int, _dp, C.c_int, _ip, _dp, C.c_double, C.c_double,
                                       _dp, _dp, _dp]
@@ -184,9 +186,10 @@ class Sim:
             raise ValueError("orc_set_membrane_law failed")
 
     def set_rest(self, id: int, rest):
-        """Rest lengths of ring id, one per segment l -> l+1."""
+        """Rest lengths of membrane id: 2D one per segment l -> l+1; 3D one
+        per edge in order of first appearance over the triangles' edges."""
         rest = _f64(rest).reshape(-1)
-        if rest.size != self.mem_sizes[id] or lib().orc_set_rest(self.h, int(id), _d(rest)):
+        if (self.D == 2 and rest.size != self.mem_sizes[id]) or lib().orc_set_rest(self.h, int(id), _d(rest)):
             raise ValueError("orc_set_rest failed")
 
     def set_fields(self, rho, phi, psi, u=None):
@@ -330,14 +333,14 @@ def ring_forces(X, rest, kappa_s, kappa_b, law=0):
     return F, es.value, eb.value
 
 
-def mesh_forces(X, tris, rest_edge, kappa_s, kappa_b):
+def mesh_forces(X, tris, rest_edge, kappa_s, kappa_b, law=0):
     X = _f64(X).reshape(-1, 3)
     t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
     rest_edge = _f64(rest_edge).reshape(-1)
     F = np.empty((X.shape[0], 3))
     es, eb = C.c_double(), C.c_double()
-    r = lib().orc_mesh_forces(X.shape[0], _d(X), t.shape[0], t.ctypes.data_as(_ip), _d(rest_edge),
-                              kappa_s, kappa_b, _d(F), C.byref(es), C.byref(eb))
+    r = lib().orc_mesh_forces_law(X.shape[0], _d(X), t.shape[0], t.ctypes.data_as(_ip), _d(rest_edge),
+                                  kappa_s, kappa_b, int(law), _d(F), C.byref(es), C.byref(eb))
     if r:
         raise ValueError("orc_mesh_forces failed")
     return F, es.value, eb.value

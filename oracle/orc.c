@@ -23,6 +23,8 @@
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
+#include <complex.h>
+#undef I /* complex.h's imaginary unit; written _Complex_I below */
 #endif
 
 #define MAXQ 19
@@ -48,7 +50,7 @@ typedef struct {
   int* edge;      /* 2 per edge (3D)                            */
   int* etri;      /* 2 per edge: the adjacent triangles (3D)    */
   double ks, kb;
-  int law;        /* strain law of a 2D ring (orc_set_membrane_law)  */
+  int law;        /* strain law (orc_set_membrane_law)                */
 } mem_t;
 
 struct orc_sim {
@@ -515,8 +517,56 @@ static void add_normal_grad(const double* X, const int* tri, int t, const double
   }
 }
 
+/* Hyperelastic triangle laws of a 3D mesh (READING: the paper names
+   neo-Hookean and Skalak membranes as alternatives, without formulas).  A
+   flat triangle maps linearly from its rest shape (given by the rest lengths
+   a_k of the edges opposite its vertices k) to its current shape, with right
+   Cauchy-Green invariants I1 = l1^2 + l2^2 = sum_k cot(theta_k) / (2 A0)
+   |edge_k|^2 (theta_k the rest angle at vertex k, edge_k the current edge
+   opposite it) and J = l1 l2 = A / A0.  Energy per rest area, shear modulus G = ks:
+     law 1 neo-Hookean  G/2 (I1 + 1/J^2 - 3)
+     law 2 Skalak       G/4 ((I1-2)^2 + 2 (I1-2) - 2 (J^2-1) + C (J^2-1)^2), C = 1
+   The triangle's energy is A0 W.  Evaluated in complex arithmetic so that
+   its derivatives come from the complex step (exact to round-off). */
+static double complex tri_law_energy(int law, double G, const double complex* P[3], const double a[3]) {
+  const double a2[3] = {a[0] * a[0], a[1] * a[1], a[2] * a[2]};
+  const double A0 = 0.25 * sqrt(2.0 * (a2[0] * a2[1] + a2[1] * a2[2] + a2[2] * a2[0]) - a2[0] * a2[0] -
+                                a2[1] * a2[1] - a2[2] * a2[2]);
+  double complex I1 = 0.0;
+  for (int k = 0; k < 3; k++) {
+    const double complex* u = P[(k + 1) % 3];
+    const double complex* v = P[(k + 2) % 3];
+    double complex l2 = 0.0;
+    for (int d = 0; d < 3; d++) l2 += (v[d] - u[d]) * (v[d] - u[d]);
+    const double cot = (a2[(k + 1) % 3] + a2[(k + 2) % 3] - a2[k]) / (4.0 * A0);
+    I1 += cot / (2.0 * A0) * l2;
+  }
+  double complex e1[3], e2[3];
+  for (int d = 0; d < 3; d++) {
+    e1[d] = P[1][d] - P[0][d];
+    e2[d] = P[2][d] - P[0][d];
+  }
+  const double complex nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2],
+                       nz = e1[0] * e2[1] - e1[1] * e2[0];
+  const double complex J = 0.5 * csqrt(nx * nx + ny * ny + nz * nz) / A0;
+  double complex W;
+  if (law == 1) {
+    W = 0.5 * G * (I1 + 1.0 / (J * J) - 3.0);
+  } else {
+    const double complex i1 = I1 - 2.0, k2 = J * J - 1.0;
+    W = 0.25 * G * (i1 * i1 + 2.0 * i1 - 2.0 * k2 + 1.0 * k2 * k2);
+  }
+  return A0 * W;
+}
+
 int orc_mesh_forces(int n, const double* X, int ntri, const int* tri, const double* rest_edge,
                     double ks, double kb, double* F, double* E_s, double* E_b) {
+  return orc_mesh_forces_law(n, X, ntri, tri, rest_edge, ks, kb, 0, F, E_s, E_b);
+}
+
+int orc_mesh_forces_law(int n, const double* X, int ntri, const int* tri, const double* rest_edge,
+                        double ks, double kb, int law, double* F, double* E_s, double* E_b) {
+  if (law < 0 || law > 2) return -1;
   int *edge = NULL, *etri = NULL;
   int ne = mesh_edges(n, ntri, tri, &edge, &etri);
   if (ne < 0) return -1;
@@ -528,11 +578,13 @@ int orc_mesh_forces(int n, const double* X, int ntri, const int* tri, const doub
     double len = sqrt(dot3(d, d));
     double l0 = rest_edge[j];
     double strain = len / l0 - 1.0;
-    es += 0.5 * ks * strain * strain * l0;
-    for (int k = 0; k < 3; k++) {
-      double gk = ks * strain * d[k] / len;
-      G[3 * b + k] += gk;
-      G[3 * a + k] -= gk;
+    if (law == 0) {
+      es += 0.5 * ks * strain * strain * l0;
+      for (int k = 0; k < 3; k++) {
+        double gk = ks * strain * d[k] / len;
+        G[3 * b + k] += gk;
+        G[3 * a + k] -= gk;
+      }
     }
     /* dihedral term: 1 - cos th = 1 - n1.n2/(|n1||n2|) */
     double n1[3], n2[3];
@@ -549,6 +601,32 @@ int orc_mesh_forces(int n, const double* X, int ntri, const int* tri, const doub
     }
     add_normal_grad(X, tri, etri[2 * j], d1, G);
     add_normal_grad(X, tri, etri[2 * j + 1], d2, G);
+  }
+  if (law != 0) {
+    /* rest length of the edge opposite each triangle vertex */
+    double* ta = (double*)malloc(sizeof(double) * 3 * (size_t)ntri);
+    for (int j = 0; j < ne; j++)
+      for (int side = 0; side < 2; side++) {
+        const int t = etri[2 * j + side];
+        for (int k = 0; k < 3; k++)
+          if (tri[3 * t + k] != edge[2 * j] && tri[3 * t + k] != edge[2 * j + 1]) ta[3 * t + k] = rest_edge[j];
+      }
+    const double h = 1e-20;
+    for (int t = 0; t < ntri; t++) {
+      double complex p[3][3];
+      const double complex* P[3] = {p[0], p[1], p[2]};
+      for (int k = 0; k < 3; k++)
+        for (int d = 0; d < 3; d++) p[k][d] = X[3 * tri[3 * t + k] + d];
+      es += creal(tri_law_energy(law, ks, P, ta + 3 * t));
+      for (int k = 0; k < 3; k++)
+        for (int d = 0; d < 3; d++) {
+          const double complex keep = p[k][d];
+          p[k][d] = keep + h * _Complex_I;
+          G[3 * tri[3 * t + k] + d] += cimag(tri_law_energy(law, ks, P, ta + 3 * t)) / h;
+          p[k][d] = keep;
+        }
+    }
+    free(ta);
   }
   for (int k = 0; k < 3 * n; k++) F[k] = -G[k];
   free(G);
@@ -1179,7 +1257,7 @@ static void one_step(orc_sim* s) {
       free(X2);
       free(F2);
     } else {
-      orc_mesh_forces(M->n, M->X, M->ntri, M->tri, M->rest, M->ks, M->kb, Fm, NULL, NULL);
+      orc_mesh_forces_law(M->n, M->X, M->ntri, M->tri, M->rest, M->ks, M->kb, M->law, Fm, NULL, NULL);
     }
     for (int l = 0; l < M->n; l++)
       for (int a = 0; a < 3; a++) {
@@ -1361,13 +1439,12 @@ int orc_get_fields(const orc_sim* s, double* rho, double* c1, double* c2, double
 
 int orc_set_membrane_law(orc_sim* s, int id, int law) {
   if (!s || id < 0 || id >= s->nmem || law < 0 || law > 2) return -1;
-  if (s->D == 3 && law != 0) return -1; /* the laws are defined for 2D rings */
   s->mem[id].law = law;
   return 0;
 }
 
 int orc_set_rest(orc_sim* s, int id, const double* rest) {
-  if (!s || !rest || id < 0 || id >= s->nmem || s->D != 2) return -1;
+  if (!s || !rest || id < 0 || id >= s->nmem) return -1;
   mem_t* M = &s->mem[id];
   for (int j = 0; j < M->nedge; j++)
     if (!(rest[j] > 0.0) || !isfinite(rest[j])) return -1;
@@ -1441,7 +1518,7 @@ int orc_energy(orc_sim* s, orc_energies* out) {
       orc_ring_forces_law(M->n, X2, M->rest, M->ks, M->kb, M->law, F, &es, &eb);
       free(X2);
     } else {
-      orc_mesh_forces(M->n, M->X, M->ntri, M->tri, M->rest, M->ks, M->kb, F, &es, &eb);
+      orc_mesh_forces_law(M->n, M->X, M->ntri, M->tri, M->rest, M->ks, M->kb, M->law, F, &es, &eb);
     }
     free(F);
     out->E_s += es;

@@ -75,10 +75,12 @@ int      orc_set_threads(int n);   /* OpenMP threads for node loops; returns the
 int orc_add_membrane(orc_sim* s, int n_nodes, const double* X, int n_tris, const int* tris,
                      double kappa_s, double kappa_b);
 
-/* Strain law of membrane id (2D rings): 0 eq. DiscreteSE (default), 1
- * neo-Hookean, 2 Skalak, both reduced to plane strain at the same
- * small-strain modulus.  Rest lengths of ring id, per segment l -> l+1
- * (2D only).                                                              */
+/* Strain law of membrane id: 0 eq. DiscreteSE (2D) or edge springs (3D,
+ * the default), 1 neo-Hookean, 2 Skalak; 2D rings take them at plane strain
+ * with the same small-strain modulus, 3D meshes per triangle with shear
+ * modulus kappa_s (Skalak C = 1).  Rest lengths of membrane id: 2D, per
+ * segment l -> l+1; 3D, per edge in order of first appearance over the
+ * triangles' edges (v_k, v_k+1).                                          */
 int orc_set_membrane_law(orc_sim* s, int id, int law);
 int orc_set_rest(orc_sim* s, int id, const double* rest);
 
@@ -121,7 +123,9 @@ int orc_ring_forces(int n, const double* X, const double* rest, double kappa_s, 
 /* the same with the strain law of orc_set_membrane_law */
 int orc_ring_forces_law(int n, const double* X, const double* rest, double kappa_s, double kappa_b,
                         int law, double* F, double* E_s, double* E_b);
-/* 3D mesh membrane energies and forces */
+/* 3D mesh membrane energies and forces; _law: with the strain law above */
+int orc_mesh_forces_law(int n, const double* X, int n_tris, const int* tris, const double* rest_edge,
+                        double kappa_s, double kappa_b, int law, double* F, double* E_s, double* E_b);
 int orc_mesh_forces(int n, const double* X, int n_tris, const int* tris, const double* rest_edge,
                     double kappa_s, double kappa_b, double* F, double* E_s, double* E_b);
 /* coupling field I (N) and coupling forces on the markers of every membrane,

@@ -29,6 +29,7 @@ struct MeshDev {
   double* erest;  // rest length per edge
   int* eoff;      // K+1 edge offsets
   int* tadj;      // 3 per triangle: the triangle across edge (v_k, v_k+1)
+  int* tedge;     // 3 per triangle: the edge opposite vertex k
   int* vtoff;     // M+1: vertex -> incident triangles (CSR)
   int* vt;
   double* fn;     // 3 per triangle: unit face normal (area vector direction)
@@ -867,15 +868,18 @@ __global__ void k_memedge3d(MemDev md, MeshDev mh, const int* __restrict__ emem)
   const int a = mh.edge[4 * e], b = mh.edge[4 * e + 1], t1 = mh.edge[4 * e + 2], t2 = mh.edge[4 * e + 3];
   const double* pa = md.X + 3 * a;
   const double* pb = md.X + 3 * b;
-  // spring: E = ks/2 (l/l0 - 1)^2 l0
-  double dvec[3];
-  sub3(pb, pa, dvec);
-  const double len = sqrt(dot3d(dvec, dvec));
-  const double s = ks * (len / mh.erest[e] - 1.0) / len;
-  double fb[3] = {-s * dvec[0], -s * dvec[1], -s * dvec[2]};
-  double fa[3] = {-fb[0], -fb[1], -fb[2]};
-  acc_force(md.Facc, a, fa);
-  acc_force(md.Facc, b, fb);
+  // spring: E = ks/2 (l/l0 - 1)^2 l0 (meshes with a triangle law instead
+  // take their strain energy from k_memtri3d)
+  if (md.law[m] == 0) {
+    double dvec[3];
+    sub3(pb, pa, dvec);
+    const double len = sqrt(dot3d(dvec, dvec));
+    const double s = ks * (len / mh.erest[e] - 1.0) / len;
+    double fb[3] = {-s * dvec[0], -s * dvec[1], -s * dvec[2]};
+    double fa[3] = {-fb[0], -fb[1], -fb[2]};
+    acc_force(md.Facc, a, fa);
+    acc_force(md.Facc, b, fb);
+  }
   if (kb == 0.0) return;
   // dihedral: E = kb (1 - n1.n2 / (|n1| |n2|))
   const int* v1 = mh.tri + 3 * t1;
@@ -915,6 +919,87 @@ __global__ void k_memedge3d(MemDev md, MeshDev mh, const int* __restrict__ emem)
   acc_force(md.Facc, v2[2], g2);
 }
 
+// Hyperelastic triangle laws: a flat triangle maps linearly from its rest
+// shape (the rest lengths a_k of the edges opposite its vertices) to its
+// current shape.  Invariants I1 = l1^2 + l2^2 = sum_k q_k |e_k|^2 with
+// q_k = cot(rest angle k) / (2 A0), and J = l1 l2 = A / A0.  Energy A0 W
+// with shear modulus G = ks: neo-Hookean W = G/2 (I1 + J^-2 - 3), Skalak
+// W = G/4 ((I1-2)^2 + 2 (I1-2) - 2 (J^2-1) + C (J^2-1)^2), C = 1.
+// Returns the energy; with f != nullptr also the forces -dE/dp_k.
+__device__ __forceinline__ double tri_law(int law, double G, const double* p0, const double* p1,
+                                          const double* p2, const double* a, double (*f)[3]) {
+  const double a2[3] = {a[0] * a[0], a[1] * a[1], a[2] * a[2]};
+  const double A0 = 0.25 * sqrt(2.0 * (a2[0] * a2[1] + a2[1] * a2[2] + a2[2] * a2[0]) - a2[0] * a2[0] -
+                                a2[1] * a2[1] - a2[2] * a2[2]);
+  const double* P[3] = {p0, p1, p2};
+  double ev[3][3], q[3], I1 = 0.0;  // ev[k]: edge opposite vertex k, from vertex k+1 to k+2
+  for (int k = 0; k < 3; k++) {
+    sub3(P[(k + 2) % 3], P[(k + 1) % 3], ev[k]);
+    q[k] = (a2[(k + 1) % 3] + a2[(k + 2) % 3] - a2[k]) / (8.0 * A0 * A0);
+    I1 += q[k] * dot3d(ev[k], ev[k]);
+  }
+  double e1[3], e2[3], n[3];
+  sub3(p1, p0, e1);
+  sub3(p2, p0, e2);
+  cross3d(e1, e2, n);
+  const double ln = sqrt(dot3d(n, n));
+  const double J = 0.5 * ln / A0;
+  double W, WI, WJ;  // W and its derivatives in I1 and J
+  if (law == 1) {
+    W = 0.5 * G * (I1 + 1.0 / (J * J) - 3.0);
+    WI = 0.5 * G;
+    WJ = -G / (J * J * J);
+  } else {
+    const double i1 = I1 - 2.0, k2 = J * J - 1.0;
+    W = 0.25 * G * (i1 * i1 + 2.0 * i1 - 2.0 * k2 + k2 * k2);
+    WI = 0.5 * G * (i1 + 1.0);
+    WJ = G * J * (k2 - 1.0);
+  }
+  if (f) {
+    // d|e_k|^2: +2 e_k at vertex k+2, -2 e_k at vertex k+1
+    for (int k = 0; k < 3; k++)
+      for (int d = 0; d < 3; d++) f[k][d] = 0.0;
+    for (int k = 0; k < 3; k++)
+      for (int d = 0; d < 3; d++) {
+        const double g = 2.0 * A0 * WI * q[k] * ev[k][d];
+        f[(k + 2) % 3][d] -= g;
+        f[(k + 1) % 3][d] += g;
+      }
+    // dJ = dA / A0, dA/dn = n / (2 |n|); times A0 cancels
+    double dsdn[3];
+    for (int d = 0; d < 3; d++) dsdn[d] = WJ * n[d] / (2.0 * ln);
+    double g0[3], g1[3], g2[3];
+    area_grad(p0, p1, p2, dsdn, g0, g1, g2);
+    for (int d = 0; d < 3; d++) {
+      f[0][d] -= g0[d];
+      f[1][d] -= g1[d];
+      f[2][d] -= g2[d];
+    }
+  }
+  return A0 * W;
+}
+
+// one thread per triangle of every mesh with a triangle law
+__global__ void k_memtri3d(MemDev md, MeshDev mh) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= mh.T) return;
+  int lo = 0, hi = md.K - 1;  // mesh of triangle t: toff[m] <= t < toff[m + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mh.toff[mid] <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int law = md.law[lo];
+  if (law == 0) return;
+  const int* v = mh.tri + 3 * t;
+  const double a[3] = {mh.erest[mh.tedge[3 * t]], mh.erest[mh.tedge[3 * t + 1]], mh.erest[mh.tedge[3 * t + 2]]};
+  double f[3][3];
+  tri_law(law, md.ks[lo], md.X + 3 * v[0], md.X + 3 * v[1], md.X + 3 * v[2], a, f);
+  for (int k = 0; k < 3; k++) acc_force(md.Facc, v[k], f[k]);
+}
+
 // total force per marker from the accumulators
 __global__ void k_memforce3d(MemDev md) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -937,11 +1022,24 @@ __global__ void k_memenergy3d(MemDev md, MeshDev mh, const int* __restrict__ eme
   if (e >= mh.E) return;
   const int m = emem[e];
   const int a = mh.edge[4 * e], b = mh.edge[4 * e + 1], t1 = mh.edge[4 * e + 2], t2 = mh.edge[4 * e + 3];
-  double dvec[3];
-  sub3(md.X + 3 * b, md.X + 3 * a, dvec);
-  const double len = sqrt(dot3d(dvec, dvec));
-  const double st = len / mh.erest[e] - 1.0;
-  out[2 * e] = 0.5 * md.ks[m] * st * st * mh.erest[e];
+  if (md.law[m] == 0) {
+    double dvec[3];
+    sub3(md.X + 3 * b, md.X + 3 * a, dvec);
+    const double len = sqrt(dot3d(dvec, dvec));
+    const double st = len / mh.erest[e] - 1.0;
+    out[2 * e] = 0.5 * md.ks[m] * st * st * mh.erest[e];
+  } else {
+    // a third of each adjacent triangle's energy (every triangle has three edges)
+    double es = 0.0;
+    for (int side = 0; side < 2; side++) {
+      const int t = side ? t2 : t1;
+      const int* v = mh.tri + 3 * t;
+      const double ar[3] = {mh.erest[mh.tedge[3 * t]], mh.erest[mh.tedge[3 * t + 1]],
+                            mh.erest[mh.tedge[3 * t + 2]]};
+      es += tri_law(md.law[m], md.ks[m], md.X + 3 * v[0], md.X + 3 * v[1], md.X + 3 * v[2], ar, nullptr);
+    }
+    out[2 * e] = es / 3.0;
+  }
   out[2 * e + 1] = md.kb[m] * (1.0 - dot3d(mh.fn + 3 * t1, mh.fn + 3 * t2));
 }
 

@@ -61,7 +61,7 @@ struct Layout {
   size_t Ifield, fib, force, tflag, tlist, tstate, stage, part;
   size_t X, U, F, Facc, rest, moff, mid, ks, kb, law, mbox, status, memE, stab, sinv;
   // 3D: moment field and triangle meshes
-  size_t mom, tri, toff, edge, erest, eoff, emem, tadj, vtoff, vt, fn, vn, ttab, ctab, coff;
+  size_t mom, tri, toff, edge, erest, eoff, emem, tadj, tedge, vtoff, vt, fn, vn, ttab, ctab, coff;
   int maxCl;
   int maxT, maxE;
   size_t total;
@@ -149,6 +149,7 @@ Layout make_layout(const lbib_params* p) {
   L.eoff = c.take(d3 ? (size_t)(K + 1) * 4 : 0);
   L.emem = c.take((size_t)L.maxE * 4);
   L.tadj = c.take((size_t)L.maxT * 3 * 4);
+  L.tedge = c.take((size_t)L.maxT * 3 * 4);
   L.vtoff = c.take(d3 ? (size_t)(M + 1) * 4 : 0);
   L.vt = c.take((size_t)L.maxT * 3 * 4);
   L.fn = c.take((size_t)L.maxT * 3 * 8);
@@ -185,6 +186,7 @@ struct lbib_sim {
   int overlap = 0;        // 2D: lattice regions away from the membranes beside the
                           // membrane kernels (0 off, 1 on)
   int force_form = 0;     // D2Q9: force of eq. ForceFE, 0 potential form, 1 divergence form
+  bool any_law = false;   // D3Q19: a mesh has a triangle strain law (the triangle pass runs)
   lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
   // optional per-phase timing with HIP events on the stream
   int timing = 0;  // bit mask of timed phases
@@ -278,6 +280,7 @@ struct lbib_sim {
     h.fn = at<double>(L.fn);
     h.vn = at<double>(L.vn);
     h.coff = at<int>(L.coff);
+    h.tedge = at<int>(L.tedge);
     h.T = ntri;
     h.E = nedge;
     return h;
@@ -717,6 +720,8 @@ struct Engine3D final : lbib_sim {
       t0 = tbeg(2);
       hipLaunchKernelGGL(k_memedge3d, dim3((nedge + 255) / 256), dim3(256), 0, stream, md, mh,
                          (const int*)at<int>(L.emem));
+      if (any_law)
+        hipLaunchKernelGGL(k_memtri3d, dim3((ntri + 255) / 256), dim3(256), 0, stream, md, mh);
       hipLaunchKernelGGL(k_memforce3d, dim3(mb), dim3(256), 0, stream, md);
       hipLaunchKernelGGL(k_spread3d, dim3(mb64), dim3(256), 0, stream, md, at<long long>(L.fib), p.nx,
                          p.ny, p.nz, p.wall_y, p.wall_z);
@@ -1182,7 +1187,7 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
   const int off = s->M;
   hipStream_t st = s->stream;
   MeshTopo mt;
-  std::vector<int> tri_g, edge_g, tadj_g, vtoff_g, vt_g, emem;
+  std::vector<int> tri_g, edge_g, tadj_g, tedge_g, vtoff_g, vt_g, emem;
   std::vector<double> erest;
   if (s->D == 3) {
     int rc = mesh_topology(n, n_elems, conn, mt);
@@ -1207,6 +1212,18 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
                            (X3[3 * b + 2] - X3[3 * a + 2]) * (X3[3 * b + 2] - X3[3 * a + 2]));
       if (!(erest[e] > 0)) return LBIB_EINVAL;
     }
+    // each triangle's edges, by the vertex opposite them (the triangle laws)
+    tedge_g.assign((size_t)3 * n_elems, -1);
+    for (int e = 0; e < ne; e++)
+      for (int side = 2; side < 4; side++) {
+        const int t = mt.edge[4 * e + side];
+        for (int k = 0; k < 3; k++) {
+          const int v = conn[3 * t + k];
+          if (v != mt.edge[4 * e] && v != mt.edge[4 * e + 1]) tedge_g[3 * t + k] = s->nedge + e;
+        }
+      }
+    for (int q = 0; q < 3 * n_elems; q++)
+      if (tedge_g[q] < 0) return LBIB_EINVAL;
     emem.assign(ne, s->K);
     const int vbase = s->vtoff.back();
     vtoff_g.resize(n);
@@ -1231,6 +1248,7 @@ int lbib_add_membrane(lbib_sim* s, int n, const double* X, int n_elems, const in
     char* w = s->ws;
     HIPCHK(hipMemcpyAsync(w + s->L.tri + (size_t)s->ntri * 12, tri_g.data(), tri_g.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w + s->L.tadj + (size_t)s->ntri * 12, tadj_g.data(), tadj_g.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w + s->L.tedge + (size_t)s->ntri * 12, tedge_g.data(), tedge_g.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w + s->L.edge + (size_t)s->nedge * 16, edge_g.data(), edge_g.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w + s->L.erest + (size_t)s->nedge * 8, erest.data(), erest.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(w + s->L.emem + (size_t)s->nedge * 4, emem.data(), emem.size() * 4, hipMemcpyHostToDevice, st));
@@ -1347,9 +1365,9 @@ int lbib_set_overlap(lbib_sim* s, int on) {
 
 int lbib_set_membrane_law(lbib_sim* s, int id, int law) {
   if (!s || s->is_batch() || id < 0 || id >= s->K || law < 0 || law > 2) return LBIB_EINVAL;
-  if (s->D != 2 && law != 0) return LBIB_EINVAL;
   HIPCHK(hipMemcpyAsync(s->ws + s->L.law + (size_t)id * 4, &law, 4, hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
+  if (law != 0) s->any_law = true;
   return LBIB_OK;
 }
 

@@ -319,6 +319,23 @@ def capsule3d(n=64, R=10.0, subdiv=3, kappa=(0.02, 0.02, 0.02), alpha=1.0, kappa
                 name=f"capsule3d_{n}")
 
 
+def prestressed_mesh(law=1, n=40, R=10.0, subdiv=3, kappa_s=0.02, lam0=1.2, kappa=(1e-4, 1e-4, 1e-4)):
+    """An icosphere mesh of radius R in a uniform fluid (C1, no coupling,
+    periodic n^3 box) whose edge rest lengths are its edge lengths / lam0, so
+    that it starts stretched equibiaxially by lam0; strain law `law`.  The
+    rest lengths are listed per edge in (lower vertex, higher vertex) order."""
+    # no coupling: a narrow band keeps the mesh's band inside the period
+    p = base_params(n, n, n, lattice=1, kappa=kappa, kappa_c=0.0, mobility=0.1, r_cut=3.0)
+    V, F = icosphere(subdiv)
+    X = V * R + np.array([n / 2.0 + 0.3, n / 2.0 + 0.2, n / 2.0 + 0.1])
+    keys = sorted({(min(int(t[k]), int(t[(k + 1) % 3])), max(int(t[k]), int(t[(k + 1) % 3])))
+                   for t in F for k in range(3)})
+    rest = np.array([np.linalg.norm(X[a] - X[b]) / lam0 for a, b in keys])
+    f = dict(rho=np.ones((n, n, n)), phi=np.ones((n, n, n)), psi=np.zeros((n, n, n)))
+    mem = [dict(X=X, tris=F, kappa_s=kappa_s, kappa_b=0.0, rest=rest, law=int(law))]
+    return dict(params=p, fields=f, membranes=mem, name=f"prestressed_mesh_law{law}_{n}")
+
+
 def drop3d(nx=24, ny=22, nz=20, R=6.0, wall_y=0, wall_z=1, kappa=(0.02, 0.03, 0.025), alpha=1.0,
            mobility=0.1, tau=1.0, tau_phi=1.0, tau_psi=1.0, u0=None, perturb=1e-4,
            seed=SEED_BASE + 4):

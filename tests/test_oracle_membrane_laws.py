@@ -131,3 +131,76 @@ def test_prestressed_ring_laplace_law(law):
     o.step(6000)
     dp, pred = ring_laplace(o, w)
     assert dp == pytest.approx(pred, rel=3e-3), (dp, pred)
+
+
+# ---- 3D meshes: the laws per triangle, shear modulus KS, Skalak C = 1 ----
+
+def _mesh(subdiv=1, R=6.0):
+    V, T = W.icosphere(subdiv)
+    return R * V, T
+
+
+def _edge_rest(V, T):
+    """Rest lengths in the oracle's edge order (first appearance over the
+    triangles' edges (v_k, v_k+1)), from the rest configuration V."""
+    seen, rest = {}, []
+    for t in T:
+        for k in range(3):
+            a, b = int(t[k]), int(t[(k + 1) % 3])
+            key = (min(a, b), max(a, b))
+            if key not in seen:
+                seen[key] = len(rest)
+                rest.append(np.linalg.norm(V[a] - V[b]))
+    return np.array(rest)
+
+
+def _energy_by_svd(V0, X, T, law):
+    """Sum over triangles of A0 W(l1, l2): the principal stretches l1, l2
+    are the singular values of the in-plane linear map from the rest
+    triangle to the current one, and W the general membrane law."""
+    E = 0.0
+    for t in T:
+        P0, P = V0[t], X[t]
+        E0 = np.stack([P0[1] - P0[0], P0[2] - P0[0]], axis=1)  # 3 x 2
+        E1 = np.stack([P[1] - P[0], P[2] - P[0]], axis=1)
+        M = E1 @ np.linalg.pinv(E0)                              # maps the rest plane onto the current one
+        s = np.linalg.svd(M, compute_uv=False)[:2]
+        A0 = 0.5 * np.linalg.norm(np.cross(E0[:, 0], E0[:, 1]))
+        w = w_neo_hookean(s[0], s[1], KS) if law == 1 else w_skalak(s[0], s[1], KS, 1.0)
+        E += A0 * w
+    return E
+
+
+@pytest.mark.parametrize("law", [1, 2])
+def test_mesh_laws_against_principal_stretches(law):
+    """Equibiaxial scaling and an anisotropic, sheared deformation of an
+    icosphere: the oracle's energy equals the SVD-based sum."""
+    V0, T = _mesh()
+    rest = _edge_rest(V0, T)
+    g = np.random.default_rng(7)
+    A = np.array([[1.3, 0.2, 0.0], [0.0, 0.9, 0.1], [0.05, 0.0, 1.1]])
+    for X in (1.2 * V0, V0 @ A.T, V0 @ A.T + g.normal(0, 0.05, V0.shape)):
+        _, es, _ = O.mesh_forces(X, T, rest, KS, 0.0, law=law)
+        assert es == pytest.approx(_energy_by_svd(V0, X, T, law), rel=1e-10)
+    # at rest the neo-Hookean and Skalak energies vanish
+    assert abs(O.mesh_forces(V0, T, rest, KS, 0.0, law=law)[1]) < 1e-12
+
+
+@pytest.mark.parametrize("law", [1, 2])
+def test_mesh_law_forces_are_minus_energy_gradient(law):
+    V0, T = _mesh()
+    rest = _edge_rest(V0, T)
+    g = np.random.default_rng(8)
+    X = 1.1 * V0 + g.normal(0, 0.1, V0.shape)
+    F, _, _ = O.mesh_forces(X, T, rest, KS, 1e-3, law=law)
+    h = 1e-6
+    for v in range(0, len(V0), 5):
+        for a in range(3):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[v, a] += h
+            Xm[v, a] -= h
+            ep = sum(O.mesh_forces(Xp, T, rest, KS, 1e-3, law=law)[1:])
+            em = sum(O.mesh_forces(Xm, T, rest, KS, 1e-3, law=law)[1:])
+            assert F[v, a] == pytest.approx(-(ep - em) / (2 * h), rel=1e-6, abs=1e-11)
+    # a closed membrane's internal forces sum to zero
+    np.testing.assert_allclose(F.sum(0), 0.0, atol=1e-13)
