@@ -108,7 +108,7 @@ int lbib_add_membrane(lbib_sim* s, int n_nodes, const double* X, int n_elems, co
    that is not positive and finite. */
 int lbib_set_rest(lbib_sim* s, int id, const double* rest);
 
-/* Strain law of 2D ring id (the paper's law and the two hyperelastic laws it
+/* Strain law of membrane id (the paper's law and the two hyperelastic laws it
    names as alternatives).  Per segment the strain energy is W(lam) times the
    rest length, lam = length / rest length:
      0 (default)  ks/2 (lam - 1)^2, eq. DiscreteSE
