@@ -69,7 +69,12 @@ def cpu_baseline(w, budget_s: float, note: str = ""):
 
     oracle.build(force=False)
     threads = oracle.set_threads(0)
-    s = oracle.Sim(w["params"])
+    # the same coupling band as the library's run (the oracle's r_cut <= 0
+    # would mean no band at all)
+    po = dict(w["params"])
+    if po.get("r_cut", 0.0) <= 0.0:
+        po["r_cut"] = 17.0 * po.get("alpha", 1.0)
+    s = oracle.Sim(po)
     for m in w["membranes"]:
         s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"])
     f = w["fields"]

@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("gamma_phi", C.c_double), ("gamma_psi", C.c_double),
                 ("kappa1", C.c_double), ("kappa2", C.c_double), ("kappa3", C.c_double),
                 ("alpha", C.c_double), ("kappa_c", C.c_double), ("r_cut", C.c_double),
-                ("force_form", C.c_int)]
+                ("force_form", C.c_int), ("fext", C.c_double * 3)]
 
 
 class Energy(C.Structure):
@@ -123,7 +123,8 @@ def make_params(p: dict) -> Params:
                   float(p.get("gamma_phi", 1.0)), float(p.get("gamma_psi", 1.0)),
                   float(p["kappa"][0]), float(p["kappa"][1]), float(p["kappa"][2]),
                   float(p.get("alpha", 1.0)), float(p.get("kappa_c", 0.0)), float(p.get("r_cut", 0.0)),
-                  int(p.get("force_form", 0)))
+                  int(p.get("force_form", 0)),
+                  (C.c_double * 3)(*[float(v) for v in (list(p.get("fext", ())) + [0.0, 0.0, 0.0])[:3]]))
 
 
 def pressure_tensor(p: dict, q, g, l, D: int = 2):

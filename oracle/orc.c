@@ -644,9 +644,10 @@ orc_sim* orc_create(const orc_params* p) {
   if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
   if (p->tau <= 0.5 || p->tau_phi <= 0.5 || p->tau_psi <= 0.5 || p->alpha <= 0.0) return NULL;
   if (p->force_form < 0 || p->force_form > 1 || (p->force_form == 1 && p->lattice != 0)) return NULL;
+  for (int a = 0; a < 3; a++)
+    if (!isfinite(p->fext[a])) return NULL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   s->p = *p;
-  if (s->p.r_cut <= 0.0) s->p.r_cut = 17.0 * s->p.alpha;
   if (lat_make(p->lattice, &s->L)) { free(s); return NULL; }
   s->D = s->L.D;
   s->nx = p->nx;
@@ -757,7 +758,8 @@ int orc_add_membrane(orc_sim* s, int n, const double* X, int ntri, const int* tr
 /* fluid 3).  The force on a marker follows -dE_c/dX_l: the derivative */
 /* of d moves the closest point, split over the closest element's      */
 /* vertices with its barycentric weights.  Several membranes add their */
-/* profiles.  Beyond r_cut from the membrane I is exactly 0 or 1.      */
+/* profiles.  With a band (r_cut > 0) I is exactly 0 or 1 beyond r_cut */
+/* from the membrane; without one it follows eq. Iprofile everywhere.  */
 /* ------------------------------------------------------------------ */
 
 /* closest point on segment AB to P: returns squared distance, t in [0,1] */
@@ -853,12 +855,19 @@ static inline double near_image(double v, double c, int n, int periodic) {
   return v + n * floor((c - v) / n + 0.5);
 }
 
+/* distance from a membrane's bounding box within which nodes are searched:
+   the band r_cut, or without a band 40 alpha, where (1 + tanh(d/2 alpha))/2
+   already rounds to exactly 0 or 1 in FP64 (tanh(x) is 1.0 for x > 19.1) */
+static double search_reach(const orc_sim* s) {
+  return s->p.r_cut > 0.0 ? s->p.r_cut : 40.0 * s->p.alpha;
+}
+
 /* geometry of node n relative to membrane M: minimum-image position P and
-   whether it lies in the membrane's bounding box grown by r_cut + 1 */
+   whether it lies in the membrane's bounding box grown by the search reach + 1 */
 static int node_position(const orc_sim* s, long n, const double* lo, const double* hi,
                          const double* cen, double* P) {
   const int D = s->D;
-  const double rc = s->p.r_cut;
+  const double rc = search_reach(s);
   const int per[3] = {1, !s->p.wall_y, !s->p.wall_z};
   const int dims[3] = {s->nx, s->ny, s->nz};
   long r = n;
@@ -922,7 +931,9 @@ static int elem_vertex(const mem_t* M, int D, int elem, int k) {
 static void coupling_profile(orc_sim* s, const double* psi, double* I, double* Fc_all, double* E_c,
                              int want_force) {
   const int D = s->D;
-  const double rc = s->p.r_cut, al = s->p.alpha;
+  /* rc: the band, or no band at all (beyond the search reach the profile
+     is exactly 0 or 1 and its derivative below FP64 resolution) */
+  const double rc = s->p.r_cut > 0.0 ? s->p.r_cut : INFINITY, al = s->p.alpha;
   const long N = s->N;
   memset(I, 0, sizeof(double) * (size_t)N);
   /* pass 1: I = sum over membranes of (1 + tanh(d/2 alpha))/2 */
@@ -1275,7 +1286,7 @@ static void one_step(orc_sim* s) {
     }
   }
 
-  /* 5. force f = f_FE + f_IB (eq. ForcingTermLBE, f_ext = 0), with
+  /* 5. force f = f_FE + f_IB + f_ext (eq. ForcingTermLBE), with
         f_FE = -rho grad mu_rho - phi grad mu_phi - psi grad mu_psi'
         (potential form) or -div p' - psi grad kappa_c (psi - I)
         (divergence form) */
@@ -1290,7 +1301,7 @@ static void one_step(orc_sim* s) {
     for (long n = 0; n < N; n++) {
       for (int a = 0; a < 3; a++) s->force[3 * n + a] = 0.0;
       for (int a = 0; a < 2; a++)
-        s->force[3 * n + a] = F2[2 * n + a] - s->psi[n] * gc[2 * n + a] + s->fib[3 * n + a];
+        s->force[3 * n + a] = F2[2 * n + a] - s->psi[n] * gc[2 * n + a] + s->fib[3 * n + a] + s->p.fext[a];
     }
     free(F2);
     free(cp);
@@ -1307,7 +1318,7 @@ static void one_step(orc_sim* s) {
       for (int a = 0; a < 3; a++) s->force[3 * n + a] = 0.0;
       for (int a = 0; a < D; a++)
         s->force[3 * n + a] = -s->rho[n] * g0[n * D + a] - s->phi[n] * g1[n * D + a] -
-                              s->psi[n] * g2[n * D + a] + s->fib[3 * n + a];
+                              s->psi[n] * g2[n * D + a] + s->fib[3 * n + a] + s->p.fext[a];
     }
     free(g0);
     free(g1);

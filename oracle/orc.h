@@ -33,11 +33,16 @@ typedef struct {
   double kappa_c;                   /* membrane coupling, eq. CouplingE           */
   double r_cut;           /* coupling band: beyond this distance from a membrane
                              the profile I is exactly 0 or 1 and the node adds
-                             no coupling force.  <= 0 selects 17*alpha.           */
+                             no coupling force.  <= 0: no band, the profile of
+                             eq. Iprofile everywhere (it is searched within
+                             40*alpha of a membrane's box, where the FP64 tanh
+                             is already exactly +-1).                          */
   int force_form;         /* free-energy force of eq. ForceFE: 0 potential form
                              -rho grad mu_rho - phi grad mu_phi - psi grad mu_psi',
                              1 divergence form -div p' - psi grad kappa_c(psi - I)
                              with the pressure tensor of Appendix A (D2Q9 only)  */
+  double fext[3];         /* uniform external force density f_ext of eq.
+                             ForcingTermLBE (zero in the paper's runs)           */
 } orc_params;
 
 /* energies and conserved sums, all FP64 */

@@ -213,6 +213,32 @@ def prestressed_ring(law=0, n=64, R=12.0, n_markers=64, kappa_s=0.05, lam0=1.25,
     return dict(params=p, fields=f, membranes=mem, name=f"prestressed_ring_law{law}_{n}x{n}")
 
 
+def shear_wave(ny=128, nx=4, U=1e-4, tau=1.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1):
+    """A single bulk phase (C1 = 1) on a periodic nx x ny lattice carrying a
+    small shear wave u_x = U sin(2 pi y / ny), u_y = 0: the wave decays at
+    nu k^2 with the kinematic viscosity nu of eq. RelaxationTimes."""
+    p = base_params(nx, ny, wall_y=0, kappa=kappa, alpha=alpha, kappa_c=0.0, tau=tau, mobility=mobility)
+    _, y = _grid2(nx, ny)
+    one = np.ones((ny, nx))
+    f = fields_from_C(one, 0.0 * one, 0.0 * one)
+    f["u"] = [U * np.sin(2.0 * np.pi * y / ny), 0.0 * one]
+    return dict(params=p, fields=f, membranes=[], name=f"shear_wave_{nx}x{ny}_tau{tau:g}")
+
+
+def forced_fluid(n=8, fext=(1e-5, -5e-6), tau=1.0, R=2.0, n_markers=12, kappa=(0.02, 0.02, 0.02)):
+    """A single bulk phase (C1 = 1) at rest on a periodic n x n lattice under
+    a uniform external force density f_ext (eq. ForcingTermLBE), with a
+    force-free ring of markers (no stiffness, no coupling) carried by the
+    fluid."""
+    p = base_params(n, n, wall_y=0, kappa=kappa, kappa_c=0.0, tau=tau, mobility=0.1)
+    p["fext"] = [float(v) for v in fext]
+    one = np.ones((n, n))
+    mem = [dict(X=circle_markers(n / 2.0 + 0.3, n / 2.0 - 0.2, R, n_markers), tris=None, kappa_s=0.0,
+                kappa_b=0.0)]
+    return dict(params=p, fields=fields_from_C(one, 0.0 * one, 0.0 * one), membranes=mem,
+                name=f"forced_fluid_{n}x{n}_tau{tau:g}")
+
+
 def flat(nx=4, ny=64, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_y=1, seed=None):
     """Flat C1/C2 interface at y = (ny-1)/2, C1 below; no membrane."""
     p = base_params(nx, ny, wall_y=wall_y, kappa=kappa, alpha=alpha, kappa_c=0.0, mobility=mobility)

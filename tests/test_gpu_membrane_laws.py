@@ -6,7 +6,7 @@ own laws equal to single runs, and the argument rules."""
 import numpy as np
 import pytest
 
-from helpers import compare, marker_err, ring_laplace, run_gpu, run_oracle
+from helpers import compare, marker_err, oracle_params, ring_laplace, run_gpu, run_oracle
 from paper_1906_03065_amd import lbib
 from paper_1906_03065_amd import workloads as W
 
@@ -118,7 +118,7 @@ def test_fp64_parity_mesh_laws(orc, law):
     m = w["membranes"][0]
     X, T = m["X"], np.asarray(m["tris"])
     length = {k: np.linalg.norm(X[k[0]] - X[k[1]]) / 1.1 for k in _edge_keys_sorted(T)}
-    o = orc.Sim(w["params"])
+    o = orc.Sim(oracle_params(w["params"]))
     o.add_membrane(X, T, m["kappa_s"], m["kappa_b"])
     o.set_rest(0, [length[k] for k in _edge_keys_first_seen(T)])
     o.set_membrane_law(0, law)

@@ -141,6 +141,33 @@ def test_coupling_profile_matches_circle(orc):
     np.testing.assert_allclose(Ec, 0.5 * 0.01 * (I ** 2).sum(), rtol=1e-13)
 
 
+def test_coupling_profile_without_band(orc):
+    """r_cut <= 0: no band, eq. Iprofile everywhere.  Between 18 and 30
+    lattice units outside a fine ring the profile is the tanh tail of the
+    circle distance (relative error of the order of the polygon's sag over
+    alpha); with a band of 17 the same nodes are exactly 0, and inside the
+    band both agree exactly."""
+    n, R, c, N = 256, 6.0, (40.3, 39.6), 80
+    p0 = W.base_params(N, N, kappa=(0.02,) * 3, alpha=1.0, kappa_c=0.01, r_cut=0.0)
+    p17 = dict(p0, r_cut=17.0)
+    X = W.circle_markers(c[0], c[1], R, n)
+    out = []
+    for p in (p0, p17):
+        s = orc.Sim(p)
+        s.add_membrane(X, None, 0.0, 0.0)
+        out.append(s.coupling(np.zeros((N, N)))[0])
+    I0, I17 = out
+    y, x = np.meshgrid(np.arange(float(N)), np.arange(float(N)), indexing="ij")
+    d = R - np.hypot(x - c[0], y - c[1])
+    tail = (d < -18.0) & (d > -30.0)
+    ref = W.tanh_profile(d, 1.0)
+    assert tail.sum() > 1000
+    assert np.all(I0[tail] > 0.0) and np.all(I17[tail] == 0.0)
+    assert np.abs(I0[tail] / ref[tail] - 1.0).max() < 3.0 * R * (1 - np.cos(np.pi / n))
+    band = d > -16.5
+    assert np.array_equal(I0[band], I17[band])
+
+
 def test_coupling_profiles_add(orc):
     """Several membranes: their profiles add (each capsule encloses fluid 3)."""
     p = W.base_params(60, 30, kappa=(0.02,) * 3, alpha=1.0, kappa_c=0.01)
