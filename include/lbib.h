@@ -51,9 +51,12 @@ typedef enum {
 
 enum { LBIB_D2Q9 = 0, LBIB_D3Q19 = 1 };
 /* population storage.  FP32/FP64 keep f_i - w_i, g_i and h_i (Sec. 3.1 EDF:
-   f is near its weight, g and h moving populations near zero).  The 16-bit
-   forms keep the moving populations in half or bfloat16 with the rest
-   populations f_0, g_0, h_0 in FP32. */
+   f is near its weight, g and h moving populations near zero); FP32 keeps
+   the rest populations g_0 and h_0 (which carry phi and psi) in FP64.  The
+   16-bit forms keep the moving populations in half or bfloat16 (scaled by
+   2^10), f_0 - w_0 in FP32 and g_0, h_0 in FP64; each moving population's
+   rounding goes into its node's rest population, so every set's mass is
+   conserved. */
 enum { LBIB_FP32 = 0, LBIB_FP16 = 1, LBIB_BF16 = 2, LBIB_FP64 = 3 };
 
 typedef struct {
@@ -170,9 +173,13 @@ int lbib_check(lbib_sim* s);
 int lbib_device_view(lbib_sim* s, int field, void** dev_ptr, size_t* elems);
 
 /* Checkpoint: lbib_save(s, NULL, &bytes) reports the size; with a buffer of
-   at least that size it writes populations, markers and the step counter.
+   at least that size it writes a header (a tag, the step counter, the marker
+   and membrane counts, nx, ny, nz, Q, the storage format, the force form and
+   the population bytes), then the populations and the markers' X, U, F.
    lbib_load restores a checkpoint taken from a simulation created with the
-   same parameters and membranes.  Both synchronise. */
+   same parameters and membranes; LBIB_EINVAL (and the handle unchanged) when
+   any header word but the step counter differs from the handle's, or the
+   buffer is shorter than the checkpoint.  Both synchronise. */
 int lbib_save(lbib_sim* s, void* host_buf, size_t* bytes);
 int lbib_load(lbib_sim* s, const void* host_buf, size_t bytes);
 
@@ -229,6 +236,16 @@ int lbib_set_overlap(lbib_sim* s, int on);
    D3Q19 simulations, batch members, and form = 1 while lbib_set_overlap is
    on. */
 int lbib_set_force_form(lbib_sim* s, int form);
+
+/* Uniform external force density f_ext of eq. ForcingTermLBE (Sec. 3.1),
+   added to the force of every node in every following step (the paper's
+   runs have f_ext = 0, the default).  It enters the exact-difference forcing
+   and the velocities of eqs. VelCorrection and ActualFluidVel like the other
+   forces, so a uniform fluid gains f_ext of momentum per step.  fz must be 0
+   for D2Q9.  Works on a simulation or a batch member (the batch then
+   rebuilds its tables at the next step).  LBIB_EINVAL for non-finite values,
+   fz != 0 in 2D, or a batch handle. */
+int lbib_set_external_force(lbib_sim* s, double fx, double fy, double fz);
 
 /* Number of completed steps. */
 long long lbib_steps_done(const lbib_sim* s);

@@ -37,6 +37,7 @@ struct LBParams {
   double inv_tau, inv_tau_phi, inv_tau_psi;  // 1/tau (eq. RelaxationTimes)
   double gphi, gpsi;                         // Gamma_phi, Gamma_psi (eq. EDF)
   double k1, k2, k3, a2, kc;                 // kappa_m, alpha^2, kappa_c
+  double fext[3];                            // uniform external force density (eq. ForcingTermLBE)
   int nx, ny, nz, wall_y, wall_z;
   long long N;
   int ntx, nty, tile;                        // tile grid of the membrane maps
@@ -376,6 +377,8 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
         Fx = -(rho * gx[0] + phi * gx[1] + psi * gx[2]);
         Fy = -(rho * gy[0] + phi * gy[1] + psi * gy[2]);
       }
+      Fx += P.fext[0];  // f_ext of eq. ForcingTermLBE
+      Fy += P.fext[1];
       const long long node = (long long)cy * P.nx + x;
       if (cact) {
         Fx += from_fix(fb0);

@@ -310,7 +310,8 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
       }
       const double rho = 1.0 + d;
       double F[3];
-      for (int a3 = 0; a3 < 3; a3++) F[a3] = -(rho * gr[0][a3] + phi * gr[1][a3] + psi * gr[2][a3]);
+      for (int a3 = 0; a3 < 3; a3++)  // plus f_ext of eq. ForcingTermLBE
+        F[a3] = -(rho * gr[0][a3] + phi * gr[1][a3] + psi * gr[2][a3]) + P.fext[a3];
       if (cact) {
         for (int a3 = 0; a3 < 3; a3++) {
           F[a3] += from_fix(fb[a3]);

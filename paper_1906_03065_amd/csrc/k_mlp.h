@@ -29,7 +29,7 @@ enum { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
 
 // C[i][j] = sum_r P[i*sPi + r*sPr] * Q[j*sQj + r*sQr], i < M, j < N, r < R.
 //   EPI_BIAS:       C += bias[j]
-//   EPI_BIAS_GELU:  Z = C + bias[j] stored to Zout, C = GELU(Z)
+//   EPI_BIAS_GELU:  Z = C + bias[j] stored to Zout (unless null), C = GELU(Z)
 //   EPI_GELU_GRAD:  C *= GELU'(Zin[i][j])
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ P, int sPi, int sPr,
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ P, int s
       if (EPI == EPI_BIAS) c += bias[j];
       if (EPI == EPI_BIAS_GELU) {
         const float z = c + bias[j];
-        Zout[o] = z;
+        if (Zout) Zout[o] = z;  // kept for the backward pass; a forward-only call passes null
         c = gelu(z);
       }
       if (EPI == EPI_GELU_GRAD) c *= gelu_grad(Zin[o]);

@@ -73,7 +73,7 @@ long long pop_bytes_per_node(int Q, int storage) {
   switch (storage) {
     case LBIB_FP32: return (3LL * Q - 2) * 4 + 2 * 8;  // FP32 with FP64 g_0, h_0
     case LBIB_FP64: return 3LL * Q * 8;
-    default: return 3LL * (Q - 1) * 2 + 3LL * 4;       // 16-bit moving + FP32 rest
+    default: return 3LL * (Q - 1) * 2 + 4 + 2 * 8;     // 16-bit moving, FP32 f_0, FP64 g_0, h_0
   }
 }
 
@@ -186,6 +186,7 @@ struct lbib_sim {
   int overlap = 0;        // 2D: lattice regions away from the membranes beside the
                           // membrane kernels (0 off, 1 on)
   int force_form = 0;     // D2Q9: force of eq. ForceFE, 0 potential form, 1 divergence form
+  double fext[3] = {0, 0, 0};  // uniform external force density (eq. ForcingTermLBE)
   bool any_law = false;   // D3Q19: a mesh has a triangle strain law (the triangle pass runs)
   lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
   // optional per-phase timing with HIP events on the stream
@@ -317,14 +318,15 @@ PlainStore<double, 9> make_store<PlainStore<double, 9>>(char* base, long long N)
 }
 template <>
 Split16Store<__half, 9> make_store<Split16Store<__half, 9>>(char* base, long long N) {
-  size_t mov = align_up((size_t)(3LL * 8 * N * 2));
-  return Split16Store<__half, 9>{reinterpret_cast<__half*>(base), reinterpret_cast<float*>(base + mov), N};
+  const size_t mov = align_up((size_t)(3LL * 8 * N * 2)), r0 = align_up((size_t)(N * 4));
+  return Split16Store<__half, 9>{reinterpret_cast<__half*>(base), reinterpret_cast<float*>(base + mov),
+                                  reinterpret_cast<double*>(base + mov + r0), N};
 }
 template <>
 Split16Store<__hip_bfloat16, 9> make_store<Split16Store<__hip_bfloat16, 9>>(char* base, long long N) {
-  size_t mov = align_up((size_t)(3LL * 8 * N * 2));
-  return Split16Store<__hip_bfloat16, 9>{reinterpret_cast<__hip_bfloat16*>(base),
-                                         reinterpret_cast<float*>(base + mov), N};
+  const size_t mov = align_up((size_t)(3LL * 8 * N * 2)), r0 = align_up((size_t)(N * 4));
+  return Split16Store<__hip_bfloat16, 9>{reinterpret_cast<__hip_bfloat16*>(base), reinterpret_cast<float*>(base + mov),
+                                  reinterpret_cast<double*>(base + mov + r0), N};
 }
 
 template <>
@@ -338,18 +340,19 @@ PlainStore<double, 19> make_store<PlainStore<double, 19>>(char* base, long long 
 }
 template <>
 Split16Store<__half, 19> make_store<Split16Store<__half, 19>>(char* base, long long N) {
-  size_t mov = align_up((size_t)(3LL * 18 * N * 2));
-  return Split16Store<__half, 19>{reinterpret_cast<__half*>(base), reinterpret_cast<float*>(base + mov), N};
+  const size_t mov = align_up((size_t)(3LL * 18 * N * 2)), r0 = align_up((size_t)(N * 4));
+  return Split16Store<__half, 19>{reinterpret_cast<__half*>(base), reinterpret_cast<float*>(base + mov),
+                                  reinterpret_cast<double*>(base + mov + r0), N};
 }
 template <>
 Split16Store<__hip_bfloat16, 19> make_store<Split16Store<__hip_bfloat16, 19>>(char* base, long long N) {
-  size_t mov = align_up((size_t)(3LL * 18 * N * 2));
-  return Split16Store<__hip_bfloat16, 19>{reinterpret_cast<__hip_bfloat16*>(base),
-                                          reinterpret_cast<float*>(base + mov), N};
+  const size_t mov = align_up((size_t)(3LL * 18 * N * 2)), r0 = align_up((size_t)(N * 4));
+  return Split16Store<__hip_bfloat16, 19>{reinterpret_cast<__hip_bfloat16*>(base), reinterpret_cast<float*>(base + mov),
+                                  reinterpret_cast<double*>(base + mov + r0), N};
 }
 
 // lattice parameters shared by both engines
-void fill_params(LBParams& P, const lbib_params& p, const Layout& L, long long N, int seg) {
+void fill_params(LBParams& P, const lbib_params& p, const Layout& L, long long N, int seg, const double* fext) {
   P.inv_tau = (1.0 / p.tau);
   P.inv_tau_phi = (1.0 / p.tau_phi);
   P.inv_tau_psi = (1.0 / p.tau_psi);
@@ -360,6 +363,7 @@ void fill_params(LBParams& P, const lbib_params& p, const Layout& L, long long N
   P.k3 = p.kappa[2];
   P.a2 = p.alpha * p.alpha;
   P.kc = p.kappa_c;
+  for (int a = 0; a < 3; a++) P.fext[a] = fext[a];
   P.nx = p.nx;
   P.ny = p.ny;
   P.nz = p.lattice == LBIB_D3Q19 ? p.nz : 1;
@@ -380,7 +384,7 @@ struct Engine2D final : lbib_sim {
   LBParams P{};
   St store(int which) const { return make_store<St>(ws + L.pops[which], N); }
 
-  void setup() override { fill_params(P, p, L, N, seg); }
+  void setup() override { fill_params(P, p, L, N, seg, fext); }
 
   CoupArgs coup_args(int want_force) const {
     CoupArgs c;
@@ -613,7 +617,7 @@ struct Engine3D final : lbib_sim {
   int ntilex() const { return (p.nx + T3 - 1) / T3; }
   int ntiley() const { return (p.ny + T3 - 1) / T3; }
 
-  void setup() override { fill_params(P, p, L, N, seg); }
+  void setup() override { fill_params(P, p, L, N, seg, fext); }
 
   Moments3 mom3() const {
     Moments3 m;
@@ -1371,6 +1375,18 @@ int lbib_set_membrane_law(lbib_sim* s, int id, int law) {
   return LBIB_OK;
 }
 
+int lbib_set_external_force(lbib_sim* s, double fx, double fy, double fz) {
+  if (!s || s->is_batch() || !std::isfinite(fx) || !std::isfinite(fy) || !std::isfinite(fz) ||
+      (s->D == 2 && fz != 0.0))
+    return LBIB_EINVAL;
+  s->fext[0] = fx;
+  s->fext[1] = fy;
+  s->fext[2] = fz;
+  s->setup();
+  if (s->owner) s->owner->mark_dirty();  // the batch copies the member's parameters
+  return LBIB_OK;
+}
+
 int lbib_set_force_form(lbib_sim* s, int form) {
   if (!s || s->owner || s->D != 2 || form < 0 || form > 1) return LBIB_EINVAL;
   if (form == 1 && s->overlap) return LBIB_EINVAL;
@@ -1526,23 +1542,38 @@ int lbib_device_view(lbib_sim* s, int field, void** ptr, size_t* elems) {
   return LBIB_EINVAL;
 }
 
+// checkpoint header: a tag and the parameters a checkpoint must match
+namespace {
+constexpr long long CKPT_TAG = 0x31504b4342494c42LL;  // "BLIBCKP1" read as little-endian bytes
+constexpr int CKPT_WORDS = 12;
+void ckpt_header(const lbib_sim* s, long long* h) {
+  const int form = s->owner ? s->owner->force_form : s->force_form;
+  const long long v[CKPT_WORDS] = {CKPT_TAG, s->steps, (long long)s->M, (long long)s->K, s->p.nx, s->p.ny,
+                                   s->p.nz, (long long)s->Q, (long long)s->p.storage, (long long)form,
+                                   (long long)s->L.pop_bytes, 0};
+  for (int k = 0; k < CKPT_WORDS; k++) h[k] = v[k];
+}
+}  // namespace
+
 int lbib_save(lbib_sim* s, void* buf, size_t* bytes) {
   if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || !bytes) return LBIB_EINVAL;
   if (!s->ready) return LBIB_ESTATE;
-  const size_t need = 16 + s->L.pop_bytes + (size_t)s->M * 24 * 3;
+  const size_t H = CKPT_WORDS * 8;
+  const size_t need = H + s->L.pop_bytes + (size_t)s->M * 24 * 3;
   if (!buf) {
     *bytes = need;
     return LBIB_OK;
   }
   if (*bytes < need) return LBIB_ENOMEM;
   char* o = (char*)buf;
-  long long hdr[2] = {s->steps, (long long)s->M};
-  memcpy(o, hdr, 16);
-  HIPCHK(hipMemcpyAsync(o + 16, s->ws + s->L.pops[s->cur], s->L.pop_bytes, hipMemcpyDeviceToHost, s->stream));
+  long long hdr[CKPT_WORDS];
+  ckpt_header(s, hdr);
+  memcpy(o, hdr, H);
+  HIPCHK(hipMemcpyAsync(o + H, s->ws + s->L.pops[s->cur], s->L.pop_bytes, hipMemcpyDeviceToHost, s->stream));
   const size_t offs[3] = {s->L.X, s->L.U, s->L.F};
   for (int k = 0; k < 3; k++)
-    HIPCHK(hipMemcpyAsync(o + 16 + s->L.pop_bytes + (size_t)k * s->M * 24, s->ws + offs[k],
+    HIPCHK(hipMemcpyAsync(o + H + s->L.pop_bytes + (size_t)k * s->M * 24, s->ws + offs[k],
                           (size_t)s->M * 24, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   *bytes = need;
@@ -1552,19 +1583,25 @@ int lbib_save(lbib_sim* s, void* buf, size_t* bytes) {
 int lbib_load(lbib_sim* s, const void* buf, size_t bytes) {
   if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s || !buf) return LBIB_EINVAL;
-  const size_t need = 16 + s->L.pop_bytes + (size_t)s->M * 24 * 3;
+  const size_t H = CKPT_WORDS * 8;
+  const size_t need = H + s->L.pop_bytes + (size_t)s->M * 24 * 3;
   if (bytes < need) return LBIB_EINVAL;
   const char* o = (const char*)buf;
-  long long hdr[2];
-  memcpy(hdr, o, 16);
-  if (hdr[1] != s->M) return LBIB_EINVAL;
-  HIPCHK(hipMemcpyAsync(s->ws + s->L.pops[s->cur], o + 16, s->L.pop_bytes, hipMemcpyHostToDevice, s->stream));
+  long long hdr[CKPT_WORDS], want[CKPT_WORDS];
+  memcpy(hdr, o, H);
+  ckpt_header(s, want);
+  // every word but the step count must match: tag, markers, membranes,
+  // lattice size, Q, storage, force form and population bytes
+  for (int k = 0; k < CKPT_WORDS; k++)
+    if (k != 1 && hdr[k] != want[k]) return LBIB_EINVAL;
+  if (hdr[1] < 0) return LBIB_EINVAL;
+  HIPCHK(hipMemcpyAsync(s->ws + s->L.pops[s->cur], o + H, s->L.pop_bytes, hipMemcpyHostToDevice, s->stream));
   const size_t offs[3] = {s->L.X, s->L.U, s->L.F};
   for (int k = 0; k < 3; k++)
-    HIPCHK(hipMemcpyAsync(s->ws + offs[k], o + 16 + s->L.pop_bytes + (size_t)k * s->M * 24,
+    HIPCHK(hipMemcpyAsync(s->ws + offs[k], o + H + s->L.pop_bytes + (size_t)k * s->M * 24,
                           (size_t)s->M * 24, hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
-  s->steps = hdr[0];
+  s->steps = hdr[1];
   s->ready = true;
   if (s->owner) s->owner->mark_dirty();
   return LBIB_OK;
@@ -1590,8 +1627,15 @@ int lbib_debug_poke(lbib_sim* s, int field, long long idx, double value) {
       size_t off = 0;
       long long lim = (3LL * s->Q - 2) * s->N;
       if (s->p.storage == LBIB_FP16 || s->p.storage == LBIB_BF16) {
-        off = align_up((size_t)(3LL * (s->Q - 1) * s->N * 2));  // FP32 rest planes
+        // the rest planes: f_0 - w_0 (FP32, idx < N), then g_0 and h_0 (FP64)
+        off = align_up((size_t)(3LL * (s->Q - 1) * s->N * 2));
         lim = 3 * s->N;
+        if (idx >= s->N && idx < lim) {
+          HIPCHK(hipMemcpyAsync(base + off + align_up((size_t)(s->N * 4)) + (idx - s->N) * 8, &value, 8,
+                                hipMemcpyHostToDevice, s->stream));
+          HIPCHK(hipStreamSynchronize(s->stream));
+          return LBIB_OK;
+        }
       }
       if (idx < 0 || idx >= lim) return LBIB_EINVAL;
       float v = (float)value;
@@ -1788,20 +1832,23 @@ void mlp_split(T* p, T*& W1, T*& b1, T*& W2, T*& b2, T*& W3, T*& b3) {
 
 dim3 gemm_grid(int M, int N) { return dim3((N + 63) / 64, (M + 63) / 64); }
 
+// the three layers on stream st; Z1, Z2 (pre-activations, for the backward
+// pass) may be null
+void mlp_forward_raw(const float* prm, const float* X, int B, float* Y, float* Z1, float* A1, float* Z2,
+                     float* A2, hipStream_t st) {
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+  mlp_split(prm, W1, b1, W2, b2, W3, b3);
+  hipLaunchKernelGGL(k_gemm<EPI_BIAS_GELU>, gemm_grid(B, MLP_H), dim3(256), 0, st, X, MLP_IN, 1, W1, MLP_IN, 1, B,
+                     MLP_H, MLP_IN, b1, (const float*)nullptr, Z1, A1);
+  hipLaunchKernelGGL(k_gemm<EPI_BIAS_GELU>, gemm_grid(B, MLP_H), dim3(256), 0, st, (const float*)A1, MLP_H, 1, W2,
+                     MLP_H, 1, B, MLP_H, MLP_H, b2, (const float*)nullptr, Z2, A2);
+  hipLaunchKernelGGL(k_gemm<EPI_BIAS>, gemm_grid(B, MLP_OUT), dim3(256), 0, st, (const float*)A2, MLP_H, 1, W3,
+                     MLP_H, 1, B, MLP_OUT, MLP_H, b3, (const float*)nullptr, (float*)nullptr, Y);
+}
+
 void mlp_forward(lbib_mlp* h, const float* X, int B, float* Y) {
-  float *W1, *b1, *W2, *b2, *W3, *b3;
-  mlp_split(h->at<float>(h->off_p), W1, b1, W2, b2, W3, b3);
-  float *Z1 = h->at<float>(h->off_z1), *A1 = h->at<float>(h->off_a1);
-  float *Z2 = h->at<float>(h->off_z2), *A2 = h->at<float>(h->off_a2);
-  hipLaunchKernelGGL(k_gemm<EPI_BIAS_GELU>, gemm_grid(B, MLP_H), dim3(256), 0, h->stream, X, MLP_IN, 1,
-                     (const float*)W1, MLP_IN, 1, B, MLP_H, MLP_IN, (const float*)b1, (const float*)nullptr, Z1,
-                     A1);
-  hipLaunchKernelGGL(k_gemm<EPI_BIAS_GELU>, gemm_grid(B, MLP_H), dim3(256), 0, h->stream, (const float*)A1,
-                     MLP_H, 1, (const float*)W2, MLP_H, 1, B, MLP_H, MLP_H, (const float*)b2,
-                     (const float*)nullptr, Z2, A2);
-  hipLaunchKernelGGL(k_gemm<EPI_BIAS>, gemm_grid(B, MLP_OUT), dim3(256), 0, h->stream, (const float*)A2, MLP_H,
-                     1, (const float*)W3, MLP_H, 1, B, MLP_OUT, MLP_H, (const float*)b3, (const float*)nullptr,
-                     (float*)nullptr, Y);
+  mlp_forward_raw(h->at<float>(h->off_p), X, B, Y, h->at<float>(h->off_z1), h->at<float>(h->off_a1),
+                  h->at<float>(h->off_z2), h->at<float>(h->off_a2), h->stream);
 }
 
 // forward + loss partials + gradient into off_g

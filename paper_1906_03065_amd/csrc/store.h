@@ -116,40 +116,49 @@ struct MixStore {
   static constexpr long long bytes_per_node() { return float_planes() * 4 + 2 * 8; }
 };
 
-// 16-bit moving populations with FP32 rest populations.  Moving values are
-// multiplied by a fixed power of two before rounding so that typical
-// magnitudes (1e-6 .. 1e-2) stay clear of the half subnormal range; bf16 uses
-// the same scale (its exponent range makes it harmless).
+// 16-bit moving populations; the rest population f_0 - w_0 in FP32 and g_0,
+// h_0 in FP64, as in the mixed format.  Moving values are multiplied by a
+// fixed power of two before rounding so that typical magnitudes (1e-6 ..
+// 1e-2) stay clear of the half subnormal range; bf16 uses the same scale
+// (its exponent range makes it harmless).  The collision adds each moving
+// population's rounding to the rest population of its node and set, so
+// every set's mass survives the rounding.  g_0 and h_0 are O(1) (they carry
+// phi and psi), and an FP32 rest population near 1 would drop additions
+// below half its ulp every step, a steady drift of the order parameters'
+// totals; in FP64 those additions are kept.
 //   mov[(set * (Q-1) + i - 1) * N + node]   i = 1..Q-1
-//   rst[set * N + node]                      i = 0
+//   r0[node]                                 f_0 - w_0
+//   r12[(set - 1) * N + node]                g_0 (set 1), h_0 (set 2)
 template <typename H, int Q>
 struct Split16Store {
   H* mov;
-  float* rst;
+  float* r0;
+  double* r12;
   long long N;
   static constexpr float kScale = 1024.0f;
   static constexpr float kInv = 1.0f / 1024.0f;
   template <typename R>
   __device__ __forceinline__ R load(int set, int i, long long node) const {
-    if (i == 0) return (R)rst[(long long)set * N + node];
+    if (i == 0) return (R)rest(set, node);
     return (R)(to_float(mov[((long long)(set * (Q - 1) + i - 1)) * N + node]) * kInv);
   }
   __device__ __forceinline__ double rest(int set, long long node) const {
-    return (double)rst[(long long)set * N + node];
+    return set == 0 ? (double)r0[node] : r12[(long long)(set - 1) * N + node];
   }
   template <typename R>
   __device__ __forceinline__ void store(int set, int i, long long node, R v) const {
     if (i == 0)
-      rst[(long long)set * N + node] = (float)v;
+      store_rest(set, node, (double)v);
     else
       mov[((long long)(set * (Q - 1) + i - 1)) * N + node] = from_float((float)v * kScale);
   }
   __device__ __forceinline__ void store_rest(int set, long long node, double v) const {
-    rst[(long long)set * N + node] = (float)v;
+    if (set == 0)
+      r0[node] = (float)v;
+    else
+      r12[(long long)(set - 1) * N + node] = v;
   }
-  // the value a moving population reads back as after a store; the collision
-  // adds the difference to the rest population of the same node and set, so
-  // every set's mass survives the rounding exactly (up to FP32)
+  // the value a moving population reads back as after a store
   static constexpr bool kQuantized = true;
   template <typename R>
   __device__ __forceinline__ R quantize(R v) const {
@@ -159,7 +168,7 @@ struct Split16Store {
   __device__ static __forceinline__ float to_float(__hip_bfloat16 h) { return __bfloat162float(h); }
   __device__ static __forceinline__ H from_float(float f);
   static constexpr long long bytes_per_node() {
-    return 3LL * (Q - 1) * (long long)sizeof(H) + 3LL * 4;
+    return 3LL * (Q - 1) * (long long)sizeof(H) + 4 + 2 * 8;
   }
 };
 

@@ -70,6 +70,7 @@ SIGNATURES = [
     ("lbib_set_launch", C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.c_int]),
     ("lbib_set_overlap", C.c_int, [_vp, C.c_int]),
     ("lbib_set_force_form", C.c_int, [_vp, C.c_int]),
+    ("lbib_set_external_force", C.c_int, [_vp, C.c_double, C.c_double, C.c_double]),
     ("lbib_get_launch", C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     ("lbib_steps_done", C.c_longlong, [_vp]),
     ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
@@ -174,6 +175,8 @@ class Sim:
         self.mem_sizes = []
         if int(p.get("force_form", 0)):
             self.set_force_form(int(p["force_form"]))
+        if any(p.get("fext", ())):
+            self.set_external_force(*p["fext"])
 
     @classmethod
     def _member(cls, batch, h, p: dict):
@@ -301,6 +304,10 @@ class Sim:
         tensor, plus the coupling term)."""
         _chk("lbib_set_force_form", lib().lbib_set_force_form(self.h, int(form)))
 
+    def set_external_force(self, fx=0.0, fy=0.0, fz=0.0):
+        """Uniform external force density f_ext of eq. ForcingTermLBE."""
+        _chk("lbib_set_external_force", lib().lbib_set_external_force(self.h, float(fx), float(fy), float(fz)))
+
     def get_launch(self):
         a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         _chk("lbib_get_launch", lib().lbib_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c),
@@ -357,6 +364,8 @@ class Batch:
             mh = _vp()
             _chk("lbib_batch_member", lib().lbib_batch_member(self.h, k, C.byref(mh)))
             self.members.append(Sim._member(self, mh, params[k]))
+            if any(params[k].get("fext", ())):
+                self.members[-1].set_external_force(*params[k]["fext"])
         if forms.pop():
             self.set_force_form(1)
 

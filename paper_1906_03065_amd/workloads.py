@@ -225,12 +225,13 @@ def shear_wave(ny=128, nx=4, U=1e-4, tau=1.0, kappa=(0.02, 0.02, 0.02), alpha=1.
     return dict(params=p, fields=f, membranes=[], name=f"shear_wave_{nx}x{ny}_tau{tau:g}")
 
 
-def forced_fluid(n=8, fext=(1e-5, -5e-6), tau=1.0, R=2.0, n_markers=12, kappa=(0.02, 0.02, 0.02)):
+def forced_fluid(n=24, fext=(1e-5, -5e-6), tau=1.0, R=2.0, n_markers=12, kappa=(0.02, 0.02, 0.02)):
     """A single bulk phase (C1 = 1) at rest on a periodic n x n lattice under
     a uniform external force density f_ext (eq. ForcingTermLBE), with a
     force-free ring of markers (no stiffness, no coupling) carried by the
-    fluid."""
-    p = base_params(n, n, wall_y=0, kappa=kappa, kappa_c=0.0, tau=tau, mobility=0.1)
+    fluid.  The coupling band is 1 (there is no coupling), so the ring's
+    tile band fits the small periodic box."""
+    p = base_params(n, n, wall_y=0, kappa=kappa, kappa_c=0.0, tau=tau, mobility=0.1, r_cut=1.0)
     p["fext"] = [float(v) for v in fext]
     one = np.ones((n, n))
     mem = [dict(X=circle_markers(n / 2.0 + 0.3, n / 2.0 - 0.2, R, n_markers), tris=None, kappa_s=0.0,

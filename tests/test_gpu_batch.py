@@ -71,6 +71,37 @@ def test_batch_equals_single_runs(graph):
         assert b[k].steps_done == 60
 
 
+@pytest.mark.parametrize("form", [0, 1])
+def test_batch_members_vs_oracle(orc, form):
+    """An uneven FP32 batch (one member in each size class: lattice widths
+    96, 200 and 300, tau != 1 in one of them) stepped 500 times, in the
+    potential (form 0) or divergence (form 1) force form: every member
+    against the FP64 oracle, field by field, within the FP32 bar of 1e-5,
+    and its markers within 1e-4."""
+    from helpers import compare, marker_err, run_oracle
+
+    ws = [W.capsule_at_interface(nx=96, ny=88, R=14.0, n_markers=110, kappa=(0.02, 0.03, 0.015), seed=31),
+          W.capsule_at_interface(nx=200, ny=72, R=12.5, n_markers=98, kappa=(0.03, 0.02, 0.025), tau=0.8,
+                                 tau_phi=1.3, seed=32, kappa_s=0.05, kappa_b=1e-3),
+          W.capsule_at_interface(nx=300, ny=64, R=11.0, n_markers=88, centre=(83.4, 31.7), seed=33)]
+    for w in ws:
+        w["params"]["force_form"] = form
+    b = lbib.Batch.from_workloads(ws)
+    assert sorted(b.get_launch(c)["members"] for c in range(3)) == [1, 1, 1]
+    b.step(500)
+    b.synchronize()
+    for k, w in enumerate(ws):
+        o = run_oracle(orc, w)
+        o.step(500)
+        errs = compare(b[k], o)
+        dx = marker_err(b[k], o, 1)
+        print(f"form {form} member {k} {w['params']['nx']}x{w['params']['ny']}",
+              {q: f"{v:.2e}" for q, v in errs.items()}, f"markers {dx:.2e}", flush=True)
+        for q, v in errs.items():
+            assert v <= 1e-5, (k, q, v)
+        assert dx < 1e-4, (k, dx)
+
+
 def test_batch_launch_shapes_bitwise():
     """Other lanes per workgroup, rows per item and ring depths per size
     class change nothing in the results."""

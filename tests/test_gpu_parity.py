@@ -3,7 +3,7 @@ inputs, element by element over whole fields (D2Q9)."""
 import numpy as np
 import pytest
 
-from helpers import compare, marker_err, normwise, run_gpu, run_oracle
+from helpers import compare, marker_err, normwise, rho_dev_err, run_gpu, run_oracle
 from paper_1906_03065_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -27,6 +27,46 @@ def test_fp64_parity_c1(orc):
         for k, v in errs.items():
             assert v < 1e-9, (n, k, v)
         assert marker_err(g, o, 1) < 1e-9
+
+
+def test_fp64_parity_c1_no_band_2000_steps(orc):
+    """The C1 workload for its full 2000 steps against the oracle's profile
+    of eq. Iprofile with no band at all.  The library runs with a band of
+    40 alpha, beyond which (1 + tanh(d/2 alpha))/2 is exactly 0 or 1 in FP64,
+    so the truncation is below FP64 resolution: fields and markers agree to
+    round-off at steps 0, 1, 10, 1000 and 2000; rho is also measured against
+    its own variation (max |rho - mean rho|)."""
+    o = run_oracle(orc, W.c1(), untruncated=True)
+    g = run_gpu(W.c1(r_cut=40.0), "fp64")
+    for n in (0, 1, 10, 1000, 2000):
+        o.step(n - o.steps_done)
+        g.step(n - g.steps_done)
+        errs = compare(g, o)
+        rd = rho_dev_err(g, o)
+        _report(f"fp64 c1 no band step {n} (rho_dev {rd:.2e})", errs)
+        for k, v in errs.items():
+            assert v < 1e-9, (n, k, v)
+        assert rd < 1e-7, (n, rd)
+        assert marker_err(g, o, 1) < 1e-9
+
+
+def test_fp32_parity_c1_default_band_vs_no_band(orc):
+    """The library at its defaults (FP32, band 17 alpha) against the oracle
+    with no band, after 1000 steps: within the FP32 bar of 1e-5.  The band's
+    own effect (the profile's tail beyond 17 alpha, e^-17 = 4e-8) is of
+    order 1e-7 in the velocities, far below it."""
+    w = W.c1()
+    o = run_oracle(orc, w, untruncated=True)
+    g = run_gpu(w, "fp32")
+    o.step(1000)
+    g.step(1000)
+    errs = compare(g, o)
+    rd = rho_dev_err(g, o)
+    _report(f"fp32 c1 default band vs no band step 1000 (rho_dev {rd:.2e})", errs)
+    for k, v in errs.items():
+        assert v <= 1e-5, (k, v)
+    assert rd < 1e-2, rd
+    assert marker_err(g, o, 1) < 1e-4
 
 
 def test_fp32_parity_c1_1000_steps(orc):
@@ -127,6 +167,30 @@ def test_determinism_and_checkpoint():
     for k in fa:
         assert np.array_equal(fa[k], fc[k]), k
     assert np.array_equal(a.membrane(0)["X"], c.membrane(0)["X"])
+
+
+def test_checkpoint_mismatch_refused():
+    """A checkpoint from a simulation of another lattice size, storage format
+    or force form (with the same marker count) is refused and the handle is
+    left as it was."""
+    from paper_1906_03065_amd import lbib
+
+    w = W.c1()
+    a = run_gpu(w, "fp32")
+    a.step(3)
+    blob = a.save()
+    others = [run_gpu(W.c1(nx=120), "fp32"), run_gpu(w, "fp16"), run_gpu(w, "fp32")]
+    others[2].set_force_form(1)
+    for b in others:
+        before = b.fields()["rho"].copy()
+        with pytest.raises(lbib.LbibError) as e:
+            b.load(blob)
+        assert e.value.code == lbib.EINVAL
+        assert b.steps_done == 0 and np.array_equal(b.fields()["rho"], before)
+    with pytest.raises(lbib.LbibError):
+        a.load(blob[:-8])  # truncated
+    a.load(blob)
+    assert a.steps_done == 3
 
 
 def test_failure_injection_nonfinite():
