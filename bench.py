@@ -18,8 +18,11 @@ the same 64 simulations stepped one after another.
 
 Prints one JSON line: whole-step MLUPS, the lattice update's HBM roofline
 fraction (algorithmic bytes / kernel time from HIP events on the library's
-stream over the timed region) and the CPU oracle's rate on a bounded sample
-of the same workload.
+stream over the timed region; 216 B per update for D2Q9 FP32, the bytes the
+storage format actually moves reported beside it) and the CPU oracle's rate
+on a bounded sample of the same workload, on all host threads and on one.
+D2Q9 runs take the divergence form of the force (the library's default)
+unless --force-form 0 asks for the potential form.
 """
 import argparse
 import json
@@ -34,7 +37,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lb2d_d2q9_2048_traffic.json")
 
 
-def measured_traffic(storage: str, size: int):
+def measured_traffic(storage: str, size: int, force_form: int):
     """HBM bytes per fused-kernel launch from the committed rocprofv3 counter
     runs (FETCH_SIZE, WRITE_SIZE scaled by a plain copy), or None when the
     kernel sources changed since they were taken or the workload differs."""
@@ -48,51 +51,90 @@ def measured_traffic(storage: str, size: int):
                    for f in ("k_lb.h", "store.h"))
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
-    if storage != "fp32" or size != 2048:
+    if storage != "fp32" or size != 2048 or force_form != rec.get("force_form", 0):
         return None
     return rec["traffic_bytes_per_launch"]
 
 
-def bytes_per_lup(storage: str, Q: int = 9) -> int:
+def alg_bytes_per_lup(storage: str, Q: int = 9) -> int:
     """Algorithmic bytes per lattice update: the three population sets read
-    once and written once."""
+    once and written once, 4 bytes per population in FP32, 8 in FP64, and 2
+    per moving population plus 4 per rest population in the 16-bit formats
+    (216 B for D2Q9 FP32, 456 B for D3Q19 FP32)."""
     if storage == "fp32":
-        return 2 * ((3 * Q - 2) * 4 + 2 * 8)  # FP32 planes, FP64 g_0 and h_0
+        return 2 * 3 * Q * 4
     if storage == "fp64":
         return 2 * 3 * Q * 8
-    return 2 * (3 * (Q - 1) * 2 + 3 * 4)  # 16-bit moving + FP32 rest populations
+    return 2 * (3 * (Q - 1) * 2 + 3 * 4)
 
 
-def cpu_baseline(w, budget_s: float, note: str = ""):
-    """The oracle as it stands, on the given lattice, for about budget_s."""
+def stored_bytes_per_lup(storage: str, Q: int = 9) -> int:
+    """Bytes per lattice update the storage format actually moves: the FP32
+    format keeps g_0 and h_0 in FP64 (232 B for D2Q9), the 16-bit formats
+    keep f_0 in FP32 and g_0, h_0 in FP64 (136 B for D2Q9)."""
+    if storage == "fp32":
+        return 2 * ((3 * Q - 2) * 4 + 2 * 8)
+    if storage == "fp64":
+        return 2 * 3 * Q * 8
+    return 2 * (3 * (Q - 1) * 2 + 4 + 2 * 8)
+
+
+def host_info() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def cpu_baseline(w, budget_s: float, note: str = "", single_s: float = 8.0):
+    """The oracle as it stands, on the given lattice, for about budget_s on
+    all the host threads it uses, then for about single_s on one thread."""
     import oracle
 
     oracle.build(force=False)
-    threads = oracle.set_threads(0)
     # the same coupling band as the library's run (the oracle's r_cut <= 0
     # would mean no band at all)
     po = dict(w["params"])
     if po.get("r_cut", 0.0) <= 0.0:
         po["r_cut"] = 17.0 * po.get("alpha", 1.0)
-    s = oracle.Sim(po)
-    for m in w["membranes"]:
-        s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"])
-    f = w["fields"]
-    s.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        s.step(1)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 200:
-            break
-    N = s.N
+
+    def timed(threads, budget):
+        used = oracle.set_threads(threads)
+        s = oracle.Sim(po)
+        for m in w["membranes"]:
+            s.add_membrane(m["X"], m.get("tris"), m["kappa_s"], m["kappa_b"])
+        f = w["fields"]
+        s.set_fields(f["rho"], f["phi"], f["psi"], f.get("u"))
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            s.step(1)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget or n >= 200:
+                break
+        return s.N * n / el / 1e6, n, el, used
+
     p = w["params"]
     dims = f"{p['nx']}x{p['ny']}" + (f"x{p['nz']}" if p.get("lattice", 0) == 1 else "")
-    return {"value": N * n / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+    v, n, el, threads = timed(0, budget_s)
+    v1, n1, el1, _ = timed(1, single_s)
+    oracle.set_threads(0)
+    return {"value": v, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{n} full steps of the {note or 'same'} {dims} workload "
-                      f"({el:.1f} s, FP64, {threads} OpenMP threads)"}
+                      f"({el:.1f} s, FP64, {threads} OpenMP threads)",
+            "single_thread": {"value": v1, "unit": "MLUPS", "cores": 1,
+                              "sample": f"{n1} full steps of the same ({el1:.1f} s, FP64, 1 thread)"},
+            "host": host_info()}
 
 
 def main():
@@ -114,8 +156,8 @@ def main():
     ap.add_argument("--overlap-steps", type=int, default=-1,
                     help="D2Q9: steps timed afterwards with the overlapped step order (default "
                          "steps/4; 0 skips them, e.g. for a profile of the single-stream kernel)")
-    ap.add_argument("--force-form", type=int, default=0, choices=[0, 1],
-                    help="D2Q9: thermodynamic force in potential (0, the default) or divergence (1) form")
+    ap.add_argument("--force-form", type=int, default=1, choices=[0, 1],
+                    help="D2Q9: thermodynamic force in divergence (1, the default) or potential (0) form")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (source + destination "
                          "traffic 2*MIB MiB per launch), --steps times, to scale counters")
@@ -148,11 +190,8 @@ def main():
     d3 = args.workload == "c3"
     size = args.size or (256 if d3 else 2048)
     w = W.c3(n=size) if d3 else W.c2(n=size)
-    if args.force_form:
-        if d3:
-            print("the divergence force form is a D2Q9 option", file=sys.stderr)
-            sys.exit(2)
-        w["params"]["force_form"] = 1
+    form = 0 if d3 else args.force_form  # D3Q19 has the potential form only
+    w["params"]["force_form"] = form
     g = lbib.from_workload(w, storage=args.storage, device="cuda:0")
     g.set_launch(args.block_x, args.seg, args.nxcd, args.ring)
     N = g.N
@@ -173,7 +212,9 @@ def main():
     el = t1 - t0
     mlups = N * args.steps / el / 1e6
     lb_ms = tm["lb"] / max(tm["steps"], 1)
-    bpl = bytes_per_lup(args.storage, 19 if d3 else 9)
+    Q = 19 if d3 else 9
+    bpl = alg_bytes_per_lup(args.storage, Q)
+    stored = stored_bytes_per_lup(args.storage, Q)
     achieved = bpl * N / (lb_ms * 1e-3) / 1e9
     out = {
         "metric": "MLUPS & % HBM roofline; wall time to equilibrium, warm-start vs plain",
@@ -194,19 +235,21 @@ def main():
                                 f"D2Q9 {size}x{size}, walls in y, 16 capsules "
                                 f"(R 24-64, {sum(len(m['X']) for m in w['membranes'])} markers), "
                                 f"flat C1/C2 interface, {args.storage} populations"),
-                   "force_form": "divergence" if args.force_form else "potential",
+                   "force_form": "divergence" if form else "potential",
                    "nodes": N, "capsules": len(w["membranes"]),
                    "markers": sum(len(m["X"]) for m in w["membranes"])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if d3 or args.force_form else measured_traffic(args.storage, size),
+                     "traffic": None if d3 else measured_traffic(args.storage, size, form),
                      "kernel": "k_mom3d + k_lb3d" if d3 else "k_lb2d", "kernel_ms": round(lb_ms, 5),
                      "bytes_per_lup": bpl,
+                     "stored_bytes_per_lup": stored,
+                     "achieved_stored": round(stored * N / (lb_ms * 1e-3) / 1e9, 1),
                      "kernel_share_of_step": round(lb_ms / (el * 1e3 / args.steps), 4),
                      "launch": g.get_launch()},
     }
     k2 = max(args.steps // 4, 1) if args.overlap_steps < 0 else args.overlap_steps
-    if not d3 and k2 > 0 and not args.force_form:
+    if not d3 and k2 > 0 and form == 0:
         # the same lattice with the regions away from the membranes on a second
         # stream beside the membrane kernels (a scheduling option, bitwise the
         # same results); the roofline above stays the single-stream kernel's
@@ -272,7 +315,7 @@ def bench_batch(args):
     el_seq = time.perf_counter() - t0
     mlups = NT * args.steps / el / 1e6
     mlups_seq = NT * args.steps / el_seq / 1e6
-    bpl = bytes_per_lup("fp32")
+    bpl = alg_bytes_per_lup("fp32")
     achieved = bpl * NT / (el / args.steps) / 1e9
     out = {
         "metric": "MLUPS & % HBM roofline; wall time to equilibrium, warm-start vs plain",

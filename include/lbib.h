@@ -217,20 +217,23 @@ int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* r
    on = -1 selects the library's choice, which is 0 (the passes share the
    memory bandwidth, so the gain is a few per cent).  No effect on D3Q19
    simulations.  Batch handles and members return LBIB_EINVAL, as do other
-   values of on, and on = 1 while the divergence force form is selected. */
+   values of on, and on = 1 while the divergence force form (the D2Q9
+   default) is selected: select the potential form first. */
 int lbib_set_overlap(lbib_sim* s, int on);
 
-/* D2Q9 form of the thermodynamic force of eq. ForceFE (Sec. 3.1).  form = 0
-   (the default): the potential form of eq. GradPT, -rho grad mu_rho -
-   phi grad mu_phi - psi grad mu_psi, with the coupling term of eq. CouplingE
-   inside mu_psi.  form = 1: the divergence form, -div P' - psi grad
-   kappa_c (psi - I), with P' the non-ideal part of the pressure tensor of
-   Appendix A (the bulk pressure sum_m C_m f_m' - f_m of eq. LandauFE plus
-   its gradient terms alpha^2 kappa_m (grad C_m grad C_m - (|grad C_m|^2/2 +
-   C_m lap C_m) I)).  Both use the isotropic stencils of the fused step; the
-   divergence form conserves the lattice momentum of the thermodynamic force
-   exactly, the potential form only to the discretisation error.  The two
-   agree to second order in the grid spacing.  Takes effect at the next
+/* D2Q9 form of the thermodynamic force of eq. ForceFE (Sec. 3.1).  form = 1
+   (the default): the divergence form, -div P' - psi grad kappa_c (psi - I),
+   with P' the non-ideal part of the pressure tensor of Appendix A (the bulk
+   pressure sum_m C_m f_m' - f_m of eq. LandauFE plus its gradient terms
+   alpha^2 kappa_m (grad C_m grad C_m - (|grad C_m|^2/2 + C_m lap C_m) I)).
+   form = 0: the potential form of eq. GradPT, -rho grad mu_rho - phi grad
+   mu_phi - psi grad mu_psi, with the coupling term of eq. CouplingE inside
+   mu_psi.  Both use the isotropic stencils of the fused step and agree to
+   second order in the grid spacing; the divergence form conserves the
+   lattice momentum of the thermodynamic force exactly, the potential form
+   only to the discretisation error, and on long runs (a liquid lens beyond
+   about 30 000 steps) the potential form grows a slow mirror-symmetric flow
+   that the divergence form does not have.  Takes effect at the next
    lbib_step.  On a batch handle the form applies to every member (the next
    step captures the batch's graphs again).  LBIB_EINVAL for other values,
    D3Q19 simulations, batch members, and form = 1 while lbib_set_overlap is

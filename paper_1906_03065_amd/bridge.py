@@ -22,7 +22,7 @@ from . import workloads as W
 
 def run_sweep(kappa1s=W.BRIDGE_KAPPA1, kappa_ss=W.BRIDGE_KAPPA_S, max_steps: int = 300000,
               every: int = 1000, window: int = 20000, tol: float = 1e-4, device="cuda:0", log: bool = True,
-              force_form: int = 0):
+              force_form: int = 1):
     """Step all (kappa_1, kappa_s) runs as one batch for max_steps steps.  A
     run counts as at equilibrium from the first check at which the aspect
     ratio of its left capsule has changed by less than tol over the last
@@ -78,7 +78,7 @@ def main():
     ap.add_argument("--max-steps", type=int, default=300000)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--window", type=int, default=20000)
-    ap.add_argument("--force-form", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--force-form", type=int, default=1, choices=[0, 1],
                     help="thermodynamic force: 0 potential form, 1 divergence form")
     ap.add_argument("--out", default="")
     args = ap.parse_args()

@@ -362,11 +362,19 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     const double rn16 = 7.5 * 1.41421356237309515, rn8 = 3.5 * 1.41421356237309515;
     const bool valid = (x < ca.nx) && (y < ca.ny);
     const double xt = tx * TILE2 + 0.5 * (TILE2 - 1), yt = ty * TILE2 + 0.5 * (TILE2 - 1);
+    // image of the tile centre nearest a membrane's box centre (cx, cy): the
+    // image of the tile's first node, since the nodes of a tile that does
+    // not split share one image.  (The nominal centre of a partial tile at
+    // the lattice edge can lie beyond the antipode while its nodes do not.)
+    auto tile_image = [&](double cx, double cy, double& pxt, double& pyt) {
+      pxt = xt + (near_image((double)(tx * TILE2), cx, ca.nx) - tx * TILE2);
+      pyt = ca.wall_y ? yt : yt + (near_image((double)(ty * TILE2), cy, ca.ny) - ty * TILE2);
+    };
     auto meets = [&](int m) {
       const double* bx = md.mbox + 8 * m;
       const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
-      const double pxt = near_image(xt, cx, ca.nx);
-      const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
+      double pxt, pyt;
+      tile_image(cx, cy, pxt, pyt);
       const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
       return split || !tile_misses(bx, pxt, pyt, hd, reach);
     };
@@ -401,8 +409,8 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       const int m = s_ml[slot];
       const double* bx = md.mbox + 8 * m;
       const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
-      const double pxt = near_image(xt, cx, ca.nx);
-      const double pyt = ca.wall_y ? yt : near_image(yt, cy, ca.ny);
+      double pxt, pyt;
+      tile_image(cx, cy, pxt, pyt);
       const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
       const int b = md.moff[m], n = md.moff[m + 1] - b;
       const double* X = md.X + 3 * b;

@@ -187,7 +187,10 @@ __device__ __forceinline__ TileGeo tile_geo(const double* bx, const double* ct, 
   g.inbox = valid;
   for (int a = 0; a < 3; a++) {
     const double cm = 0.5 * (bx[a] + bx[3 + a]);
-    g.pc[a] = near_img(ct[a], cm, dims[a], per[a]);
+    // the image of the tile's first node: the nodes of a tile that does not
+    // split share one image, while a partial tile's nominal centre can lie
+    // beyond the antipode
+    g.pc[a] = ct[a] + (near_img((double)t0[a], cm, dims[a], per[a]) - t0[a]);
     g.pp[a] = near_img((double)xi[a], cm, dims[a], per[a]);
     if (g.pc[a] + hd < bx[a] - reach || g.pc[a] - hd > bx[3 + a] + reach) g.miss = true;
     if (g.pp[a] < bx[a] - reach || g.pp[a] > bx[3 + a] + reach) g.inbox = false;

@@ -185,7 +185,7 @@ struct lbib_sim {
   int ring = 3;           // rows in the fused kernel's register ring (4: prefetch)
   int overlap = 0;        // 2D: lattice regions away from the membranes beside the
                           // membrane kernels (0 off, 1 on)
-  int force_form = 0;     // D2Q9: force of eq. ForceFE, 0 potential form, 1 divergence form
+  int force_form = 0;     // force of eq. ForceFE, 0 potential form, 1 divergence form (D2Q9, the default there)
   double fext[3] = {0, 0, 0};  // uniform external force density (eq. ForcingTermLBE)
   bool any_law = false;   // D3Q19: a mesh has a triangle strain law (the triangle pass runs)
   lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
@@ -1112,6 +1112,9 @@ int init_sim(lbib_sim* s, const lbib_params* p, const Layout& L, char* ws, hipSt
   s->N = (long long)p->nx * p->ny * p->nz;
   s->r_cut = p->r_cut > 0 ? p->r_cut : 17.0 * p->alpha;
   s->seg = 0;  // automatic: one resident round of workgroups
+  // D2Q9 starts in the divergence form of the thermodynamic force, which
+  // conserves the lattice momentum exactly (D3Q19 has the potential form only)
+  s->force_form = s->D == 2 ? 1 : 0;
   s->setup();
   // zero the maps, accumulators and counters (fill kernels would do as well;
   // memset is only used here, outside any step)

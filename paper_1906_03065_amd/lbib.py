@@ -173,8 +173,9 @@ class Sim:
                                               _vp(self.stream.cuda_stream), C.byref(h)))
         self.h = h
         self.mem_sizes = []
-        if int(p.get("force_form", 0)):
-            self.set_force_form(int(p["force_form"]))
+        if self.D == 2:
+            # the library's D2Q9 default is the divergence form (1)
+            self.set_force_form(int(p.get("force_form", 1)))
         if any(p.get("fext", ())):
             self.set_external_force(*p["fext"])
 
@@ -299,9 +300,9 @@ class Sim:
         _chk("lbib_set_overlap", lib().lbib_set_overlap(self.h, int(on)))
 
     def set_force_form(self, form: int):
-        """D2Q9: 0 (the default) the potential form of the thermodynamic force,
-        1 its divergence form (minus the divergence of the non-ideal pressure
-        tensor, plus the coupling term)."""
+        """D2Q9: 1 (the default) the divergence form of the thermodynamic
+        force (minus the divergence of the non-ideal pressure tensor, plus the
+        coupling term), 0 its potential form."""
         _chk("lbib_set_force_form", lib().lbib_set_force_form(self.h, int(form)))
 
     def set_external_force(self, fx=0.0, fy=0.0, fz=0.0):
@@ -345,7 +346,7 @@ class Batch:
         self.torch = torch
         self.device = torch.device(device)
         n = len(params)
-        forms = {int(p.get("force_form", 0)) for p in params}
+        forms = {int(p.get("force_form", 1)) for p in params}
         if len(forms) > 1:
             raise LbibError("lbib_batch_create", EINVAL)  # one force form per batch
         membranes = membranes or [()] * n
@@ -366,8 +367,7 @@ class Batch:
             self.members.append(Sim._member(self, mh, params[k]))
             if any(params[k].get("fext", ())):
                 self.members[-1].set_external_force(*params[k]["fext"])
-        if forms.pop():
-            self.set_force_form(1)
+        self.set_force_form(forms.pop())
 
     def set_force_form(self, form: int):
         """Force form of every member (see Sim.set_force_form); the next step

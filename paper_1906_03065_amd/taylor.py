@@ -69,7 +69,7 @@ def case_list(stride: int = 1, which: str = "both"):
 
 
 def run_sweep(cases, max_steps: int = 100000, every: int = 1000, window: int = 20000, tol: float = 1e-4,
-              device="cuda:0", log: bool = True, force_form: int = 0):
+              device="cuda:0", log: bool = True, force_form: int = 1):
     """Step all cases as one batch for max_steps steps.  A run counts as at
     equilibrium from the first check at which its D has changed by less than
     tol over the last `window` steps; every run is measured to the end."""
@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--max-steps", type=int, default=100000)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--window", type=int, default=20000)
-    ap.add_argument("--force-form", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--force-form", type=int, default=1, choices=[0, 1])
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     if a.compare:

@@ -39,10 +39,15 @@ def rng(seed: int) -> np.random.Generator:
 
 def base_params(nx, ny, nz=1, lattice=0, wall_y=0, wall_z=0, kappa=(0.02, 0.02, 0.02), alpha=1.0,
                 kappa_c=0.01, tau=1.0, tau_phi=1.0, tau_psi=1.0, mobility=None, gamma=1.0,
-                r_cut=0.0) -> dict:
+                r_cut=0.0, force_form=None) -> dict:
     """Parameter dictionary.  ``mobility`` M sets Gamma = M/(tau - 1/2) for both
     order parameters (eq. RelaxationTimes), or a pair (M_phi, M_psi) sets each
-    (Sec. 2.5 names M_phi = 3 M_psi); otherwise ``gamma`` is used."""
+    (Sec. 2.5 names M_phi = 3 M_psi); otherwise ``gamma`` is used.
+    ``force_form``: the thermodynamic force of eq. ForceFE as the divergence
+    of the pressure tensor (1, the default on D2Q9) or in its potential form
+    (0, the only form on D3Q19)."""
+    if force_form is None:
+        force_form = 1 if lattice == 0 else 0
     gphi = gpsi = gamma
     if mobility is not None:
         m_phi, m_psi = (mobility, mobility) if np.isscalar(mobility) else mobility
@@ -52,7 +57,7 @@ def base_params(nx, ny, nz=1, lattice=0, wall_y=0, wall_z=0, kappa=(0.02, 0.02, 
                 wall_z=int(wall_z), tau=float(tau), tau_phi=float(tau_phi), tau_psi=float(tau_psi),
                 gamma_phi=float(gphi), gamma_psi=float(gpsi),
                 kappa=[float(k) for k in kappa], alpha=float(alpha), kappa_c=float(kappa_c),
-                r_cut=float(r_cut))
+                r_cut=float(r_cut), force_form=int(force_form))
 
 
 def tanh_profile(d, alpha):
@@ -309,7 +314,7 @@ def icosphere(subdiv: int):
 
 def capsule3d(n=64, R=10.0, subdiv=3, kappa=(0.02, 0.02, 0.02), alpha=1.0, kappa_c=0.01,
               kappa_s=0.01, kappa_b=1e-3, mobility=0.1, two=True, bridge=True, perturb=1e-4,
-              seed=SEED_BASE + 2, wall_z=1, r_cut=0.0, tau=1.0):
+              seed=SEED_BASE + 2, wall_z=1, r_cut=0.0, tau=1.0, shift=(0.0, 0.0, 0.0)):
     """D3Q19 box n^3 (periodic x, y; walls in z when wall_z): C2 below
     z0 = (n-1)/2, C1 above; two icosphere capsules of fluid 3 (radius R) side
     by side on the interface with a C2 bridge between them.  READING of the
@@ -324,6 +329,7 @@ def capsule3d(n=64, R=10.0, subdiv=3, kappa=(0.02, 0.02, 0.02), alpha=1.0, kappa
         centres = [(n / 2.0 - 1.25 * R + 0.3, yc, z0 + 0.15), (n / 2.0 + 1.25 * R + 0.3, yc, z0 + 0.15)]
     else:
         centres = [(n / 2.0 + 0.3, yc, z0 + 0.15)]
+    centres = [(c[0] + shift[0], c[1] + shift[1], c[2] + shift[2]) for c in centres]
     V, F = icosphere(subdiv)
     C3 = np.zeros(x.shape)
     mems = []

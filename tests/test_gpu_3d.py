@@ -82,6 +82,25 @@ def test_fp64_parity_capsule3d(orc):
         assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max()
 
 
+def test_fp64_parity_partial_tile_at_periodic_edge_3d(orc):
+    """36^3 (the last 8-wide tile in x and y holds 4 nodes), one capsule of
+    radius 6 centred at x = 17.2, band 8.9: the last tile's nodes lie
+    within half a period of the capsule but its nominal centre (35.5) does
+    not, so the tile must be placed by its nodes' image; its nodes at
+    x = 32 are in the band."""
+    w = W.capsule3d(n=36, R=6.0, subdiv=2, two=False, bridge=False, r_cut=8.9, shift=(-1.1, 0.0, 0.0))
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    for n in (1, 20):
+        o.step(n - o.steps_done)
+        g.step(n - g.steps_done)
+        errs = compare(g, o, D=3)
+        _report(f"fp64 capsule3d partial edge tile step {n}", errs)
+        for k, v in errs.items():
+            assert v < 1e-9, (n, k, v)
+        assert marker_err(g, o, 1) < 1e-10
+
+
 def test_fp64_energy_parity_capsule3d(orc):
     """Free-energy sums, coupling, strain and bending energies (FP64 on the
     GPU) agree with the oracle."""

@@ -1,7 +1,8 @@
 """The overlapped D2Q9 step (lattice regions away from the membranes on a
 second stream beside the membrane kernels, the rest after them in short
 pieces) against the single-stream step: every node is updated by the same
-arithmetic, so fields, markers and forces must agree bitwise."""
+arithmetic, so fields, markers and forces must agree bitwise.  The option
+exists for the potential form of the force only, so these runs select it."""
 import numpy as np
 import pytest
 
@@ -10,6 +11,11 @@ from paper_1906_03065_amd import lbib
 from paper_1906_03065_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+
+def _potential(w):
+    w["params"]["force_form"] = 0
+    return w
 
 
 def _state(g):
@@ -33,7 +39,7 @@ def _ragged():
                                tau=0.8, tau_phi=1.3, tau_psi=0.9, kappa=(0.02, 0.03, 0.015), seed=21)
     w["membranes"].append(dict(X=W.circle_markers(220.6, 100.1, 15.0, 120), tris=None, kappa_s=0.05,
                                kappa_b=1e-3))
-    return w
+    return _potential(w)
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp64", "fp16"])
@@ -54,7 +60,8 @@ def test_overlap_bitwise_ragged(storage):
 def test_overlap_bitwise_periodic_and_shapes():
     """Periodic in y (regions wrap), launch shapes varied on the overlapped
     side: 192 lanes with ring 4, then 64 lanes with short segments."""
-    w = W.capsule_at_interface(nx=256, ny=192, R=30.0, n_markers=236, centre=(128.0, 20.5), wall_y=0, seed=23)
+    w = _potential(W.capsule_at_interface(nx=256, ny=192, R=30.0, n_markers=236, centre=(128.0, 20.5), wall_y=0,
+                                          seed=23))
     ref = run_gpu(w, "fp32")
     ref.set_overlap(0)
     ref.step(40)
@@ -69,7 +76,7 @@ def test_overlap_bitwise_periodic_and_shapes():
 def test_overlap_full_size_c2():
     """The 2048 x 2048 benchmark lattice with the overlap on against the
     default single-stream step, five steps."""
-    w = W.c2()
+    w = _potential(W.c2())
     a = run_gpu(w, "fp32")
     b = run_gpu(w, "fp32")
     b.set_overlap(1)
@@ -84,6 +91,10 @@ def test_overlap_rejects_bad_values():
     for v in (2, -2):
         with pytest.raises(RuntimeError):
             g.set_overlap(v)
+    with pytest.raises(lbib.LbibError) as e:  # the divergence form (the default) has no overlap
+        g.set_overlap(1)
+    assert e.value.code == lbib.EINVAL
+    g.set_force_form(0)
     g.set_overlap(1)
     g.step(3)
     assert g.check() == 0

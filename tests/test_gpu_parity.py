@@ -180,7 +180,7 @@ def test_checkpoint_mismatch_refused():
     a.step(3)
     blob = a.save()
     others = [run_gpu(W.c1(nx=120), "fp32"), run_gpu(w, "fp16"), run_gpu(w, "fp32")]
-    others[2].set_force_form(1)
+    others[2].set_force_form(0)  # the potential form (the default is the divergence form)
     for b in others:
         before = b.fields()["rho"].copy()
         with pytest.raises(lbib.LbibError) as e:
@@ -239,6 +239,24 @@ def test_fp64_parity_band_near_period(orc, wall_y):
             assert v < 1e-9, (n, k, v)
         assert marker_err(g, o, 1) < 1e-9
     assert g.check() == 0
+
+
+def test_fp64_parity_partial_tile_at_periodic_edge(orc):
+    """72 columns (the last 16-wide tile holds 8), capsule centre at x =
+    35.3: the last tile's nodes are within 36 of the centre but its nominal
+    centre (x = 71.5) is not, so the tile must be placed by its nodes' image.
+    Band nodes at x = 64 must get the tanh tail of the profile."""
+    w = W.capsule_at_interface(nx=72, ny=66, R=12.0, n_markers=80, centre=(35.3, 32.6), tau=0.9, seed=21)
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    for n in (1, 80):
+        o.step(n - o.steps_done)
+        g.step(n - g.steps_done)
+        errs = compare(g, o)
+        _report(f"fp64 partial edge tile step {n}", errs)
+        for k, v in errs.items():
+            assert v < 1e-9, (n, k, v)
+        assert marker_err(g, o, 1) < 1e-9
 
 
 @pytest.mark.parametrize("r_cut", [4.0, 8.0])

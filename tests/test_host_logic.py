@@ -17,18 +17,23 @@ from paper_1906_03065_amd import workloads as W  # noqa: E402
 
 
 def test_bytes_per_lattice_update():
-    # D2Q9: 25 FP32 moving + 2 FP64 rest populations, read and written
-    assert bench.bytes_per_lup("fp32", 9) == 232
-    assert bench.bytes_per_lup("fp64", 9) == 432
-    assert bench.bytes_per_lup("fp16", 9) == 120
-    assert bench.bytes_per_lup("fp32", 19) == 2 * (55 * 4 + 16)
+    # algorithmic: the three population sets read and written once
+    assert bench.alg_bytes_per_lup("fp32", 9) == 216
+    assert bench.alg_bytes_per_lup("fp32", 19) == 456
+    assert bench.alg_bytes_per_lup("fp64", 9) == 432
+    assert bench.alg_bytes_per_lup("fp16", 9) == 120
+    # stored: FP32 keeps g_0, h_0 in FP64; 16-bit keeps f_0 in FP32, g_0, h_0 in FP64
+    assert bench.stored_bytes_per_lup("fp32", 9) == 232
+    assert bench.stored_bytes_per_lup("fp32", 19) == 2 * (55 * 4 + 16)
+    assert bench.stored_bytes_per_lup("fp16", 9) == 136
+    assert bench.stored_bytes_per_lup("bf16", 19) == 2 * (54 * 2 + 4 + 16)
 
 
 def test_traffic_record_only_for_its_workload():
-    t = bench.measured_traffic("fp32", 2048)
+    t = bench.measured_traffic("fp32", 2048, 1)
     assert t is None or 0.9e9 < t < 2e9
-    assert bench.measured_traffic("fp16", 2048) is None
-    assert bench.measured_traffic("fp32", 1024) is None
+    assert bench.measured_traffic("fp16", 2048, 1) is None
+    assert bench.measured_traffic("fp32", 1024, 1) is None
 
 
 def test_bench_refuses_several_gpus():
