@@ -337,6 +337,22 @@ int lbib_mlp_adam_step(lbib_mlp* h, const float* x_dev, const float* t_dev, int 
                        float beta2, float eps, double* loss);
 void lbib_mlp_destroy(lbib_mlp* h);
 
+/* Forward pass of the network without a workspace, for callers that cannot
+   allocate device memory (code under graph capture, serving loops, hosts
+   that forbid allocation): the same kernels and results as
+   lbib_mlp_forward.  params_dev holds the lbib_mlp_param_count() parameters
+   (device, the layout above), x_dev [B][6] and y_dev [B][32] are device
+   arrays owned by the caller.  The hidden activations go to a fixed device
+   array of the library, 2 x 4096 x 128 floats (4 MiB), which each GPU the
+   library runs on holds until the process ends; its address is looked up on
+   the first call made with that device current.  1 <= B <= 4096: LBIB_ENOMEM
+   for B > 4096, LBIB_EINVAL for B < 1 or a null pointer.  Enqueued on
+   hip_stream (NULL = the default stream); allocates nothing and does not
+   synchronise.  All calls on one GPU share the array (it keeps the last
+   call's activations): calls that overlap in time on one GPU race, so keep
+   them on one stream or otherwise ordered. */
+int lbib_mlp_forward_noalloc(const float* params_dev, const float* x_dev, int B, float* y_dev, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1990,3 +1991,47 @@ int lbib_mlp_adam_step(lbib_mlp* h, const float* x_dev, const float* t_dev, int 
 void lbib_mlp_destroy(lbib_mlp* h) { delete h; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// forward pass without a workspace, for callers that cannot allocate: the
+// hidden activations live in a fixed device array of the library.  The
+// array's name is a host-side stand-in in host code; its device address is
+// looked up once per device and only that address is passed to kernels.
+constexpr int MLP_NOALLOC_ROWS = 4096;
+static __device__ __align__(256) float scratch[2 * MLP_NOALLOC_ROWS * MLP_H];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};  // device address of scratch, per device
+
+// address of the current device's scratch (looked up on the first call made
+// with that device current)
+int scratch_address(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBIB_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return LBIB_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBIB_EHIP;
+    g_scratch[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return LBIB_OK;
+}
+}  // namespace
+
+extern "C" int lbib_mlp_forward_noalloc(const float* params_dev, const float* x_dev, int B, float* y_dev,
+                                        void* hip_stream) {
+  if (!params_dev || !x_dev || !y_dev || B < 1) return LBIB_EINVAL;
+  if (B > MLP_NOALLOC_ROWS) return LBIB_ENOMEM;
+  float* base = nullptr;
+  const int rc = scratch_address(&base);
+  if (rc) return rc;
+  // A1 and A2 are written in full before they are read: nothing to clear
+  float* A1 = base;
+  float* A2 = base + (size_t)MLP_NOALLOC_ROWS * MLP_H;
+  mlp_forward_raw(params_dev, x_dev, B, y_dev, nullptr, A1, nullptr, A2, (hipStream_t)hip_stream);
+  return hipGetLastError() == hipSuccess ? LBIB_OK : LBIB_EHIP;
+}

@@ -94,6 +94,7 @@ SIGNATURES = [
     ("lbib_mlp_adam_step", C.c_int, [_vp, _vp, _vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float,
                                      C.POINTER(C.c_double)]),
     ("lbib_mlp_destroy", None, [_vp]),
+    ("lbib_mlp_forward_noalloc", C.c_int, [_vp, _vp, C.c_int, _vp, _vp]),
 ]
 
 
@@ -525,6 +526,18 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+def mlp_forward_noalloc(params_dev, x_dev, y_dev, stream=None):
+    """lbib_mlp_forward_noalloc on torch tensors already on the device:
+    params_dev (float32, lbib_mlp_param_count()), x_dev [B][6], y_dev [B][32]
+    (contiguous float32).  Allocates nothing; returns nothing."""
+    import torch
+
+    st = stream if stream is not None else torch.cuda.current_stream(x_dev.device)
+    _chk("lbib_mlp_forward_noalloc", lib().lbib_mlp_forward_noalloc(
+        _vp(params_dev.data_ptr()), _vp(x_dev.data_ptr()), int(x_dev.shape[0]), _vp(y_dev.data_ptr()),
+        _vp(st.cuda_stream)))
 
 
 def from_workload(w: dict, storage="fp32", device="cuda:0", **kw) -> Sim:
