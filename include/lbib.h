@@ -240,6 +240,17 @@ int lbib_set_overlap(lbib_sim* s, int on);
    on. */
 int lbib_set_force_form(lbib_sim* s, int form);
 
+/* D2Q9 coupling-profile search (a scheduling knob; results are bitwise the
+   same either way).  on = 1 (the default): every node keeps, for up to two
+   membranes near it, the closest membrane segment found by the last full
+   search and a lower bound on the distance of all other segments; while the
+   markers have not moved enough to break that bound (the library tracks the
+   largest marker step of each membrane), the next step re-evaluates only
+   that segment and its two neighbours, exactly, instead of searching.
+   on = 0 searches every step.  On a batch handle it applies to every
+   member.  LBIB_EINVAL for other values or D3Q19 simulations. */
+int lbib_set_coupling_cache(lbib_sim* s, int on);
+
 /* Uniform external force density f_ext of eq. ForcingTermLBE (Sec. 3.1),
    added to the force of every node in every following step (the paper's
    runs have f_ext = 0, the default).  It enters the exact-difference forcing

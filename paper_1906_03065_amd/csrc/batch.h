@@ -69,7 +69,7 @@ __global__ __launch_bounds__(NT) void kb_tiles(const BMember<St>* T, const int2*
 
 // persistent: the active tiles of all members
 template <class St, typename R, int NT>
-__global__ __launch_bounds__(NT, 3) void kb_coupling2d(const BMember<St>* T, int n, int parity) {
+__global__ __launch_bounds__(NT, 2) void kb_coupling2d(const BMember<St>* T, int n, int parity) {
   __shared__ int s_pre[BATCH_MAX + 1];
   for (int i = threadIdx.x; i < n; i += NT) s_pre[i + 1] = T[i].tm.tstate[0];
   if (threadIdx.x == 0) s_pre[0] = 0;

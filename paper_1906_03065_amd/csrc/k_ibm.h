@@ -28,6 +28,18 @@ constexpr int COUP_THREADS = 256;  // one thread per node of a 16x16 tile
 constexpr int COUP_CHUNK = 512;    // segments examined per culling chunk
 constexpr int COUP_KEEP = 4;       // membranes per tile whose band data stays in LDS
 constexpr int COUP_ML = 64;        // membranes whose grown boxes may meet one tile
+constexpr int COUP_CACHE = 2;      // membranes per tile whose closest segment each node keeps
+// with the cache on, the candidate lists reach this much farther: every
+// segment left off a node's list is then at least this much farther than
+// its closest one, the room a cached entry has before the markers' drift
+// expires it
+constexpr float COUP_PAD = 1.0f;
+constexpr int COUP_WIN = 3;        // a cached entry re-evaluates its segment and 3 on each side
+// with the cache on, a tile, sub-tile or node is taken to lie beyond the
+// band without a search only this much farther out, so its entry outlasts
+// some drift; nearer nodes are searched and keep their closest segment
+constexpr float COUP_BEYOND = 0.5f;
+constexpr int COUP_FACC = 128;     // per-tile LDS accumulator of coupling forces, markers per slot
 
 struct MemDev {
   double* X;          // 3 per marker
@@ -40,7 +52,8 @@ struct MemDev {
   double* ks;         // K
   double* kb;         // K
   int* law;           // K, strain law of each 2D ring (0 eq. DiscreteSE, 1 neo-Hookean, 2 Skalak)
-  double* mbox;       // 8 per membrane: lo xyz, hi xyz, orientation (+-1), spare
+  double* mbox;       // 8 per membrane: lo xyz, hi xyz, orientation (+-1), drift: a bound on
+                      // the distance any marker has moved since the simulation started
   int* status;        // [0] force/marker out of range, [1] lattice too small / too many membranes
   float4* stab;       // 2D, per step: segment l -> l+1 as (start - box centre, edge) in FP32
   float* sinv;        // 2D, per step: 1 / |edge|^2
@@ -133,6 +146,13 @@ __device__ __forceinline__ void tiles_run(const MemDev& md, const TileMap& tm, i
     lo[a] = block_min<NT>(mn, sh);
     hi[a] = -block_min<NT>(-mx, sh);
   }
+  // largest step of the last marker update, |U| (each step adds it to the
+  // membrane's drift bound; a call between steps adds it again, which only
+  // loosens the bound)
+  double u2 = 0.0;
+  for (int l = b + tid; l < e; l += NT)
+    u2 = fmax(u2, md.U[3 * l] * md.U[3 * l] + md.U[3 * l + 1] * md.U[3 * l + 1] + md.U[3 * l + 2] * md.U[3 * l + 2]);
+  const double umax = sqrt(-block_min<NT>(-u2, sh));
   // orientation of a 2D ring from its signed area (shoelace sum)
   double area = 0.0;
   if (D == 2) {
@@ -148,6 +168,8 @@ __device__ __forceinline__ void tiles_run(const MemDev& md, const TileMap& tm, i
       md.mbox[8 * m + a] = lo[a];
       md.mbox[8 * m + 3 + a] = hi[a];
     }
+    // with room for the rounding of X + U
+    md.mbox[8 * m + 7] += umax * (1.0 + 1e-12) + 1e-12;
     md.mbox[8 * m + 6] = area >= 0.0 ? 1.0 : -1.0;
   }
   // 2D: this step's FP32 segment table, relative to the box centre
@@ -246,6 +268,15 @@ struct CoupArgs {
   int nx, ny, wall_y;
   double alpha, kappa_c, r_cut;
   int want_force;
+  // per node and cached membrane slot (COUP_CACHE x N): the membrane and
+  // closest segment of the last full search (key = m << 16 | segment, or
+  // m << 16 | 0xFFFE / 0xFFFD for a node beyond the band inside / outside;
+  // -1 none), and a lower bound (plus the membrane's drift at that time) on
+  // the distance of every segment more than COUP_WIN from the closest one
+  // (beyond the band: on the distance of the ring); null disables the cache
+  int* ckey;
+  float* clb;
+  long long N;
 };
 
 // inside test at the closest feature of a ring (markers X, n of them,
@@ -344,6 +375,8 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
   __shared__ float s_redf[NT / 64];
   __shared__ int s_ml[COUP_ML];  // membranes whose grown box meets the tile, ascending
   __shared__ int s_mn, s_wc[NT / 64];
+  __shared__ long long s_facc[COUP_FACC][2];  // coupling forces of one slot's markers, fixed point
+  __shared__ int s_base;
   __shared__ int b_seg[COUP_KEEP][NT];
   __shared__ double b_t[COUP_KEEP][NT];
   __shared__ double b_sd[COUP_KEEP][NT];
@@ -450,6 +483,133 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         }
         continue;
       }
+      double d2b = 1e300, tb = 0.0;
+      int sb = -1;
+      int side = -1;  // side of a node beyond the band (-1: not decided that way)
+      // Temporal coherence.  A node keeps its closest segment s of the last
+      // full search and a lower bound L on the distance of every segment
+      // more than COUP_WIN away from s along the ring.  No marker has moved
+      // farther than the membrane's drift since, and a segment's distance
+      // moves no more than its end points, so while the nearest of the
+      // segments within COUP_WIN of s (exact, in FP64, lowest index on ties)
+      // is nearer than L less the drift, it is the closest segment a full
+      // search would find.  A node beyond the
+      // band stays beyond it, on its side, while its distance bound less
+      // the drift exceeds r_cut.  The tile skips the search when every
+      // node is certified.
+      const bool cslot = ca.ckey != nullptr && slot < COUP_CACHE && n <= COUP_CHUNK && m < 32768;
+      const long long cix = (long long)slot * ca.N + ((long long)y * ca.nx + x);
+      bool cached = false;
+      if (cslot) {
+        bool ok = true;
+        if (inbox) {
+          const int key = ca.ckey[cix];
+          ok = key >= 0 && (key >> 16) == m;
+          if (ok) {
+            const double thr = (double)ca.clb[cix] - bx[7];
+            const int sk = key & 0xFFFF;
+            if (sk >= 0xFFF0) {
+              ok = thr > ca.r_cut;
+              side = sk == 0xFFFE ? 1 : 0;
+            } else {
+              // the kept segment and COUP_WIN on each side (lowest index on
+              // equal distances, whatever the order)
+#pragma unroll
+              for (int k = -COUP_WIN; k <= COUP_WIN; k++) {
+                const int q = ((sk + k) % n + n) % n, q1 = (q + 1 == n) ? 0 : q + 1;
+                double tt;
+                const double d2 = seg_d2(px, py, X[3 * q], X[3 * q + 1], X[3 * q1], X[3 * q1 + 1], tt);
+                if (d2 < d2b || (d2 == d2b && q < sb)) {
+                  d2b = d2;
+                  sb = q;
+                  tb = tt;
+                }
+              }
+              ok = sqrt(d2b) < thr;
+            }
+          }
+        }
+        // Entries that have expired are renewed node by node: the node's
+        // wave searches the whole ring for it (FP32 screening relative to
+        // the box centre, FP64 for every segment within the screening
+        // tolerance of the FP32 minimum, lowest index on ties) and keeps
+        // either its closest segment with the exact bound over all segments
+        // beyond the window, or, well beyond the band, its side and distance.
+        const bool renew = !ok && inbox && ca.ckey[cix] >= 0 && (ca.ckey[cix] >> 16) == m;
+        unsigned long long need = __ballot(renew);
+        if (need) {
+          const float4* stab = md.stab + b;
+          const float* sinv = md.sinv + b;
+          while (need) {
+            const int ln = __ffsll((long long)need) - 1;
+            need &= need - 1;
+            const double qx = __shfl(px, ln, 64), qy = __shfl(py, ln, 64);
+            const float fcx = (float)(qx - cx), fcy = (float)(qy - cy);
+            float bf = 3.0e38f;
+            for (int l = lane; l < n; l += 64) bf = fminf(bf, seg_d2f(fcx, fcy, stab[l], sinv[l]));
+            bf = wave_minf(bf);
+            const float tol = 2e-3f + 2e-5f * bf;
+            double rd2 = 1e300, rt = 0.0;
+            int rs = 0x7fffffff;
+            for (int l = lane; l < n; l += 64) {
+              if (seg_d2f(fcx, fcy, stab[l], sinv[l]) > bf + tol) continue;
+              const int l1 = (l + 1 == n) ? 0 : l + 1;
+              double tt;
+              const double d2 = seg_d2(qx, qy, X[3 * l], X[3 * l + 1], X[3 * l1], X[3 * l1 + 1], tt);
+              if (d2 < rd2 || (d2 == rd2 && l < rs)) {
+                rd2 = d2;
+                rs = l;
+                rt = tt;
+              }
+            }
+            for (int o2 = 32; o2 > 0; o2 >>= 1) {
+              const double d2o = __shfl_xor(rd2, o2, 64), to = __shfl_xor(rt, o2, 64);
+              const int so = __shfl_xor(rs, o2, 64);
+              if (d2o < rd2 || (d2o == rd2 && so < rs)) {
+                rd2 = d2o;
+                rs = so;
+                rt = to;
+              }
+            }
+            float o2m = 3.0e38f;
+            for (int l = lane; l < n; l += 64) {
+              int dd = abs(l - rs);
+              dd = min(dd, n - dd);
+              if (dd > COUP_WIN) o2m = fminf(o2m, seg_d2f(fcx, fcy, stab[l], sinv[l]));
+            }
+            o2m = wave_minf(o2m);
+            if (lane == ln) {
+              d2b = rd2;
+              sb = rs;
+              tb = rt;
+              side = -1;
+              const double d = sqrt(rd2);
+              if (d > ca.r_cut + COUP_BEYOND) {
+                const bool in = ring_side(X, n, o, sb, tb, px, py);
+                ca.ckey[cix] = (m << 16) | (in ? 0xFFFE : 0xFFFD);
+                ca.clb[cix] = __double2float_rd(d - 1e-3 - 1e-5 * d + bx[7]);
+              } else {
+                const double lb = sqrt(fmax((double)o2m - (2e-3 + 2e-5 * (double)o2m), 0.0));
+                ca.ckey[cix] = (m << 16) | sb;
+                ca.clb[cix] = __double2float_rd(lb - 1e-3 - 1e-5 * lb + bx[7]);
+              }
+              ok = true;
+            }
+          }
+        }
+        cached = __syncthreads_and(ok) != 0;
+        if (!cached) {
+          d2b = 1e300;
+          tb = 0.0;
+          sb = -1;
+          side = -1;
+        }
+      }
+      // lower bound to keep for this node after a full search (in the form
+      // stored: less the drift) and its key; -1: nothing kept
+      int keyw = -1;
+      double lbw = 0.0;
+      if (!cached) {
       // distance of the tile centre to the ring, in FP32 from the step's
       // segment table (the first values stay in registers for the
       // candidate list); the ray parity only for a tile beyond the band
@@ -466,7 +626,7 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       }
       for (int l = threadIdx.x + KEEPD * NT; l < n; l += NT) dl = fminf(dl, seg_d2f(pcx, pcy, stab[l], sinv[l]));
       const float dminf = sqrtf(block_minf<NT>(dl, s_redf));
-      if ((double)dminf > ca.r_cut + rn16 + 0.01) {
+      if ((double)dminf > ca.r_cut + rn16 + 0.01 + (cslot ? COUP_BEYOND : 0.0f)) {
         // no node of the tile is within the band: all on the centre's side
         int cr = 0;
         for (int l = threadIdx.x; l < n; l += NT) {
@@ -476,6 +636,12 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         const int par = ((int)block_sum<NT>((double)cr, s_red)) & 1;
         if (inbox) Itot += par ? 1.0 : 0.0;
         if (slot < COUP_KEEP) b_seg[slot][threadIdx.x] = -1;
+        if (cslot && valid) {
+          // every node is at least dmin - rn16 from the ring
+          // (outside the grown box: farther than reach, on the outside)
+          ca.ckey[cix] = (m << 16) | (inbox && par ? 0xFFFE : 0xFFFD);
+          ca.clb[cix] = __double2float_rd((inbox ? (double)dminf - rn16 - 0.011 : reach - 1e-3) + bx[7]);
+        }
         continue;
       }
       // every node's closest segment lies within dmin + 2 rn16 of the
@@ -484,11 +650,9 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       // the FP32 minimum, then re-evaluates in FP64 every candidate within a
       // margin that covers the FP32 rounding, so the FP64 closest segment
       // (lowest index on ties) is the one chosen.
-      const float cull = dminf + (float)(2.0 * rn16) + 0.01f;
+      const float pad = cslot ? COUP_PAD : 0.0f;
+      const float cull = dminf + (float)(2.0 * rn16) + 0.01f + pad;
       const float fx = (float)(px - pxt), fy = (float)(py - pyt);
-      double d2b = 1e300, tb = 0.0;
-      int sb = -1;
-      int side = -1;  // side of a node beyond the band (-1: not decided that way)
       for (int c0 = 0; c0 < n; c0 += COUP_CHUNK) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
@@ -521,7 +685,7 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
           float dw = 3.0e38f;
           for (int q = lane; q < nc; q += 64) dw = fminf(dw, d2f(q, cwx, cwy));
           for (int o2 = 32; o2 > 0; o2 >>= 1) dw = fminf(dw, __shfl_xor(dw, o2, 64));
-          const float cr = sqrtf(dw) + (float)(2.0 * rn8) + 1e-3f;
+          const float cr = sqrtf(dw) + (float)(2.0 * rn8) + 1e-3f + pad;
           int cnt = 0;
           for (int base = 0; base < nc; base += 64) {
             const int q = base + lane;
@@ -540,20 +704,33 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
                          tc);
             return ring_side(X, n, o, sc, tc, pxt + cwx, pyt + cwy) ? 1 : 0;
           };
-          const float rb = (float)(ca.r_cut + rn8);
+          const float rb = (float)(ca.r_cut + rn8) + (cslot ? COUP_BEYOND : 0.0f);
+          // segments off this wave's list lie farther than cr from the
+          // sub-tile centre (and those off the tile's list farther than
+          // cull - 4 sqrt 2): at least lout from any node of the sub-tile
+          const double lout = fmin((double)cr, (double)cull - 4.0 * 1.41421356237309515) - rn8;
           if (shortcut && dw - (2e-3f + 2e-5f * dw) > rb * rb) {
             // the whole sub-tile lies beyond the band
             side = centre_side();
+            if (inbox) {
+              keyw = (m << 16) | (side ? 0xFFFE : 0xFFFD);
+              lbw = fmin(sqrt(fmax((double)dw - (2e-3 + 2e-5 * (double)dw), 0.0)),
+                         (double)cull - 4.0 * 1.41421356237309515) - rn8;
+            }
           } else {
             float bf = 3.0e38f;
             if (inbox)
               for (int k = 0; k < cnt; k++) bf = fminf(bf, d2f(s_wl[wv][k], fx, fy));
             const float tol = 2e-3f + 2e-5f * bf;
             const float rc = (float)ca.r_cut;
-            const bool beyond = shortcut && inbox && bf - tol > rc * rc;
+            const bool beyond = shortcut && !cslot && inbox && bf - tol > rc * rc;
             if (__ballot(beyond)) {
               const int sc = centre_side();
               if (beyond) side = sc;
+            }
+            if (beyond) {
+              keyw = (m << 16) | (side ? 0xFFFE : 0xFFFD);
+              lbw = fmin(sqrt(fmax((double)bf - (double)tol, 0.0)), lout);
             }
             if (inbox && !beyond) {
               for (int k = 0; k < cnt; k++) {
@@ -568,6 +745,19 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
                   sb = s;
                   tb = tt;
                 }
+              }
+              if (cslot && sb >= 0) {
+                // nearest listed segment more than COUP_WIN from sb
+                float o2 = 3.0e38f;
+                for (int k = 0; k < cnt; k++) {
+                  const int q = s_wl[wv][k];
+                  int dd = abs(s_cand[q] - sb);
+                  dd = min(dd, n - dd);
+                  if (dd <= COUP_WIN) continue;
+                  o2 = fminf(o2, d2f(q, fx, fy));
+                }
+                keyw = (m << 16) | sb;
+                lbw = fmin(sqrt(fmax((double)o2 - (2e-3 + 2e-5 * (double)o2), 0.0)), lout);
               }
             }
           }
@@ -600,6 +790,27 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         }
         __syncthreads();
       }
+      if (cslot && valid && !inbox) {
+        // outside the box grown by reach: farther than reach from the ring
+        keyw = (m << 16) | 0xFFFD;
+        lbw = reach;
+      }
+      if (cslot && keyw >= 0 && (keyw & 0xFFFF) < 0xFFF0 && sqrt(d2b) > ca.r_cut + COUP_BEYOND) {
+        // well beyond the band: keep the side and the distance instead (a
+        // node near the ring's medial axis has no room between its closest
+        // segments)
+        keyw = (m << 16) | (ring_side(X, n, o, sb, tb, px, py) ? 0xFFFE : 0xFFFD);
+        lbw = sqrt(d2b);
+      }
+      if (cslot && valid) {
+        // FP32 distances are within 1e-5 of exact here: a margin of 1e-3
+        // plus 1e-5 of the bound; stored with the drift so far added and
+        // rounded down, so the bound at a later step is the stored value
+        // less the drift then
+        ca.ckey[cix] = keyw;
+        ca.clb[cix] = keyw >= 0 ? __double2float_rd(lbw - 1e-3 - 1e-5 * fabs(lbw) + bx[7]) : 0.0f;
+      }
+      }  // !cached
       double sd = 0.0;
       bool band = false;
       if (inbox && side >= 0) {
@@ -649,33 +860,68 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
           psi += (double)cur.template load<R>(2, dir, sn);
         }
       }
+      // per membrane: the tile's contributions are summed in LDS (integer
+      // adds of fixed-point values, so the order does not matter), indexed
+      // around the closest segment of one of its band nodes, then added to
+      // the markers with one global atomic each; a marker out of the LDS
+      // window is added directly
       for (int slot = 0; slot < nk; slot++) {
+        const int m = s_ml[slot];
+        const int b = md.moff[m], n = md.moff[m + 1] - b;
         const int sb = b_seg[slot][threadIdx.x];
-        if (sb < 0) continue;
         const double sd = b_sd[slot][threadIdx.x], tb = b_t[slot][threadIdx.x];
         const double d = fabs(sd);
-        if (d == 0.0) continue;
-        const int m = s_ml[slot];
-        const double* bx = md.mbox + 8 * m;
-        const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
-        const int b = md.moff[m], n = md.moff[m + 1] - b;
-        const double* X = md.X + 3 * b;
-        const int s1 = (sb + 1 == n) ? 0 : sb + 1;
-        const double px = near_image((double)x, cx, ca.nx);
-        const double py = ca.wall_y ? (double)y : near_image((double)y, cy, ca.ny);
-        const double fx = X[3 * sb] + tb * (X[3 * s1] - X[3 * sb]);
-        const double fy = X[3 * sb + 1] + tb * (X[3 * s1 + 1] - X[3 * sb + 1]);
-        const double nxh = (px - fx) / d, nyh = (py - fy) / d;
-        const double sg = sd > 0.0 ? 1.0 : -1.0;
-        const double ch = cosh(sd / (2.0 * ca.alpha));
-        const double wgt = ca.kappa_c / (4.0 * ca.alpha) * (psi - Itot) / (ch * ch);
-        const double gx = -sg * nxh * wgt, gy = -sg * nyh * wgt;
-        long long* A = md.Facc + 3 * (b + sb);
-        long long* B = md.Facc + 3 * (b + s1);
-        atomicAdd((unsigned long long*)&A[0], (unsigned long long)to_fix(gx * (1.0 - tb)));
-        atomicAdd((unsigned long long*)&A[1], (unsigned long long)to_fix(gy * (1.0 - tb)));
-        atomicAdd((unsigned long long*)&B[0], (unsigned long long)to_fix(gx * tb));
-        atomicAdd((unsigned long long*)&B[1], (unsigned long long)to_fix(gy * tb));
+        const bool live = sb >= 0 && d != 0.0;
+        if (threadIdx.x == 0) s_base = -1;
+        for (int i = threadIdx.x; i < COUP_FACC; i += NT) s_facc[i][0] = s_facc[i][1] = 0;
+        __syncthreads();
+        if (live) atomicCAS(&s_base, -1, sb);
+        __syncthreads();
+        const int base = s_base;
+        if (base < 0) continue;  // no band node of this membrane in the tile (uniform)
+        if (live) {
+          const double* bx = md.mbox + 8 * m;
+          const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
+          const double* X = md.X + 3 * b;
+          const int s1 = (sb + 1 == n) ? 0 : sb + 1;
+          const double px = near_image((double)x, cx, ca.nx);
+          const double py = ca.wall_y ? (double)y : near_image((double)y, cy, ca.ny);
+          const double fx = X[3 * sb] + tb * (X[3 * s1] - X[3 * sb]);
+          const double fy = X[3 * sb + 1] + tb * (X[3 * s1 + 1] - X[3 * sb + 1]);
+          const double nxh = (px - fx) / d, nyh = (py - fy) / d;
+          const double sg = sd > 0.0 ? 1.0 : -1.0;
+          const double ch = cosh(sd / (2.0 * ca.alpha));
+          const double wgt = ca.kappa_c / (4.0 * ca.alpha) * (psi - Itot) / (ch * ch);
+          const double gx = -sg * nxh * wgt, gy = -sg * nyh * wgt;
+          const int vv[2] = {sb, s1};
+          const double ww[2] = {1.0 - tb, tb};
+#pragma unroll
+          for (int e = 0; e < 2; e++) {
+            int dd = vv[e] - base;
+            if (dd > n / 2) dd -= n;
+            if (dd < -(n / 2)) dd += n;
+            const int la = dd + COUP_FACC / 2;
+            const long long vx = to_fix(gx * ww[e]), vy = to_fix(gy * ww[e]);
+            if (la >= 0 && la < COUP_FACC) {
+              atomicAdd((unsigned long long*)&s_facc[la][0], (unsigned long long)vx);
+              atomicAdd((unsigned long long*)&s_facc[la][1], (unsigned long long)vy);
+            } else {
+              long long* A = md.Facc + 3 * (b + vv[e]);
+              atomicAdd((unsigned long long*)&A[0], (unsigned long long)vx);
+              atomicAdd((unsigned long long*)&A[1], (unsigned long long)vy);
+            }
+          }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < COUP_FACC; i += NT) {
+          const long long vx = s_facc[i][0], vy = s_facc[i][1];
+          if (vx == 0 && vy == 0) continue;
+          const int v = ((base + i - COUP_FACC / 2) % n + n) % n;
+          long long* A = md.Facc + 3 * (b + v);
+          atomicAdd((unsigned long long*)&A[0], (unsigned long long)vx);
+          atomicAdd((unsigned long long*)&A[1], (unsigned long long)vy);
+        }
+        __syncthreads();
       }
     }
     __syncthreads();  // LDS band data and lists are rewritten by the next tile
@@ -684,7 +930,9 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
 
 // one tile per workgroup (grid-stride over the active-tile list)
 template <class St, typename R, int NT>
-__global__ __launch_bounds__(NT, 3) void k_coupling2d(MemDev md, TileMap tm, CoupArgs ca,
+// (the LDS of a workgroup leaves room for two per CU: registers are sized
+// for two waves per SIMD)
+__global__ __launch_bounds__(NT, 2) void k_coupling2d(MemDev md, TileMap tm, CoupArgs ca,
                                                    double* __restrict__ Ifield, St cur) {
   const int ntl = tm.tstate[0];
   for (int li = blockIdx.x; li < ntl; li += gridDim.x) coupling2d_tile<St, R, NT>(md, tm, ca, Ifield, cur, li);
@@ -881,6 +1129,7 @@ __device__ __forceinline__ void interp2d_run(const MemDev& md, const St& cur, co
     md.U[3 * g + 2] = 0.0;
     md.X[3 * g] = X + Ux;
     md.X[3 * g + 1] = Y + Uy;
+
   }
 }
 

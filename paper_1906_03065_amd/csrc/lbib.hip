@@ -61,6 +61,8 @@ struct Layout {
   size_t pop_bytes;     // bytes of one buffer
   size_t Ifield, fib, force, tflag, tlist, tstate, stage, part;
   size_t X, U, F, Facc, rest, moff, mid, ks, kb, law, mbox, status, memE, stab, sinv;
+  // 2D coupling cache: per node and cached membrane slot, key and bound
+  size_t ckey, clb;
   // 3D: moment field and triangle meshes
   size_t mom, tri, toff, edge, erest, eoff, emem, tadj, tedge, vtoff, vt, fn, vn, ttab, ctab, coff;
   int maxCl;
@@ -141,6 +143,8 @@ Layout make_layout(const lbib_params* p) {
   L.memE = c.take(64);
   L.stab = c.take(D == 2 ? (size_t)M * 16 : 0);
   L.sinv = c.take(D == 2 ? (size_t)M * 4 : 0);
+  L.ckey = c.take(D == 2 ? (size_t)COUP_CACHE * N * 4 : 0);
+  L.clb = c.take(D == 2 ? (size_t)COUP_CACHE * N * 4 : 0);
   const bool d3 = D == 3;
   L.mom = c.take(d3 ? (size_t)N * 3 * 8 : 0);
   L.tri = c.take((size_t)L.maxT * 3 * 4);
@@ -187,6 +191,7 @@ struct lbib_sim {
   int overlap = 0;        // 2D: lattice regions away from the membranes beside the
                           // membrane kernels (0 off, 1 on)
   int force_form = 0;     // force of eq. ForceFE, 0 potential form, 1 divergence form (D2Q9, the default there)
+  int coup_cache = 1;     // D2Q9: each node keeps its closest membrane segment between steps
   double fext[3] = {0, 0, 0};  // uniform external force density (eq. ForcingTermLBE)
   bool any_law = false;   // D3Q19: a mesh has a triangle strain law (the triangle pass runs)
   lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
@@ -246,6 +251,13 @@ struct lbib_sim {
   virtual int mem_energy(double* out, long long* rows) = 0;
   // a member's membranes or state changed (a batch rebuilds its tables)
   virtual void mark_dirty() {}
+  // forget every node's cached closest segment (markers moved other than by
+  // a step: checkpoint load, marker poke)
+  int drop_coupling_cache() {
+    if (D != 2 || !L.ckey) return LBIB_OK;
+    if (hipMemsetAsync(ws + L.ckey, 0xff, (size_t)COUP_CACHE * N * 4, stream) != hipSuccess) return LBIB_EHIP;
+    return LBIB_OK;
+  }
   virtual bool is_batch() const { return false; }
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -396,6 +408,9 @@ struct Engine2D final : lbib_sim {
     c.kappa_c = p.kappa_c;
     c.r_cut = r_cut;
     c.want_force = want_force;
+    c.ckey = coup_cache ? at<int>(L.ckey) : nullptr;
+    c.clb = coup_cache ? at<float>(L.clb) : nullptr;
+    c.N = N;
     return c;
   }
 
@@ -1127,7 +1142,10 @@ int init_sim(lbib_sim* s, const lbib_params* p, const Layout& L, char* ws, hipSt
       hipMemsetAsync(s->ws + L.status, 0, 64, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.force, 0, (size_t)s->N * s->D * 8, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.moff, 0, 4, st) != hipSuccess ||
-      hipMemsetAsync(s->ws + L.Ifield, 0, (size_t)s->N * 8, st) != hipSuccess)
+      hipMemsetAsync(s->ws + L.Ifield, 0, (size_t)s->N * 8, st) != hipSuccess ||
+      hipMemsetAsync(s->ws + L.mbox, 0, (size_t)std::max(p->max_membranes, 1) * 64, st) != hipSuccess)
+    return LBIB_EHIP;
+  if (s->D == 2 && hipMemsetAsync(s->ws + L.ckey, 0xff, (size_t)COUP_CACHE * s->N * 4, st) != hipSuccess)
     return LBIB_EHIP;
   // the tile flags start at 0 and the stamp at 1: no tile is active until a
   // membrane's tile pass flags it (a simulation without membranes never
@@ -1391,6 +1409,24 @@ int lbib_set_external_force(lbib_sim* s, double fx, double fy, double fz) {
   return LBIB_OK;
 }
 
+int lbib_set_coupling_cache(lbib_sim* s, int on) {
+  if (!s || s->D != 2 || on < 0 || on > 1) return LBIB_EINVAL;
+  if (s->is_batch()) {
+    for (int k = 0;; k++) {
+      lbib_sim* m = nullptr;
+      if (lbib_batch_member(s, k, &m) != LBIB_OK) break;
+      m->coup_cache = on;
+    }
+    s->coup_cache = on;
+    s->mark_dirty();
+    return LBIB_OK;
+  }
+  if (on && !s->coup_cache && s->drop_coupling_cache() != LBIB_OK) return LBIB_EHIP;  // stale entries
+  s->coup_cache = on;
+  if (s->owner) s->owner->mark_dirty();
+  return LBIB_OK;
+}
+
 int lbib_set_force_form(lbib_sim* s, int form) {
   if (!s || s->owner || s->D != 2 || form < 0 || form > 1) return LBIB_EINVAL;
   if (form == 1 && s->overlap) return LBIB_EINVAL;
@@ -1607,6 +1643,7 @@ int lbib_load(lbib_sim* s, const void* buf, size_t bytes) {
   HIPCHK(hipStreamSynchronize(s->stream));
   s->steps = hdr[1];
   s->ready = true;
+  if (s->drop_coupling_cache() != LBIB_OK || hipStreamSynchronize(s->stream) != hipSuccess) return LBIB_EHIP;
   if (s->owner) s->owner->mark_dirty();
   return LBIB_OK;
 }
@@ -1617,6 +1654,7 @@ int lbib_debug_poke(lbib_sim* s, int field, long long idx, double value) {
   if (field == 2) {
     if (idx < 0 || idx >= (long long)s->M * 3) return LBIB_EINVAL;
     HIPCHK(hipMemcpyAsync(s->ws + s->L.X + idx * 8, &value, 8, hipMemcpyHostToDevice, s->stream));
+    if (s->drop_coupling_cache() != LBIB_OK) return LBIB_EHIP;
     HIPCHK(hipStreamSynchronize(s->stream));
     return LBIB_OK;
   }

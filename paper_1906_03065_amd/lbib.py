@@ -71,6 +71,7 @@ SIGNATURES = [
     ("lbib_set_overlap", C.c_int, [_vp, C.c_int]),
     ("lbib_set_force_form", C.c_int, [_vp, C.c_int]),
     ("lbib_set_external_force", C.c_int, [_vp, C.c_double, C.c_double, C.c_double]),
+    ("lbib_set_coupling_cache", C.c_int, [_vp, C.c_int]),
     ("lbib_get_launch", C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     ("lbib_steps_done", C.c_longlong, [_vp]),
     ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
@@ -306,6 +307,12 @@ class Sim:
         coupling term), 0 its potential form."""
         _chk("lbib_set_force_form", lib().lbib_set_force_form(self.h, int(form)))
 
+    def set_coupling_cache(self, on: int):
+        """D2Q9: 1 (the default) keeps each node's closest membrane segment
+        between steps (re-evaluated, not searched, while provably still the
+        closest), 0 searches every step; the results are bitwise the same."""
+        _chk("lbib_set_coupling_cache", lib().lbib_set_coupling_cache(self.h, int(on)))
+
     def set_external_force(self, fx=0.0, fy=0.0, fz=0.0):
         """Uniform external force density f_ext of eq. ForcingTermLBE."""
         _chk("lbib_set_external_force", lib().lbib_set_external_force(self.h, float(fx), float(fy), float(fz)))
@@ -374,6 +381,10 @@ class Batch:
         """Force form of every member (see Sim.set_force_form); the next step
         captures the batch's graphs again."""
         _chk("lbib_set_force_form", lib().lbib_set_force_form(self.h, int(form)))
+
+    def set_coupling_cache(self, on: int):
+        """Coupling-search cache of every member (see Sim.set_coupling_cache)."""
+        _chk("lbib_set_coupling_cache", lib().lbib_set_coupling_cache(self.h, int(on)))
 
     def __len__(self):
         return len(self.members)
