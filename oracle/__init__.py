@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("gamma_phi", C.c_double), ("gamma_psi", C.c_double),
                 ("kappa1", C.c_double), ("kappa2", C.c_double), ("kappa3", C.c_double),
                 ("alpha", C.c_double), ("kappa_c", C.c_double), ("r_cut", C.c_double),
-                ("force_form", C.c_int), ("fext", C.c_double * 3)]
+                ("force_form", C.c_int), ("fext", C.c_double * 3), ("mw", C.c_double * 3)]
 
 
 class Energy(C.Structure):
@@ -85,6 +85,8 @@ def lib():
         L.orc_feq.argtypes = [C.c_int, C.c_double, _dp, _dp]
         L.orc_geq.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp]
         L.orc_mu.argtypes = [C.POINTER(Params)] + [C.c_double] * 7 + [_dp]
+        L.orc_mu_general.argtypes = [C.POINTER(Params)] + [C.c_double] * 7 + [_dp]
+        L.orc_concentrations.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double, _dp]
         L.orc_collide.argtypes = [C.POINTER(Params), _dp, _dp, C.c_double, C.c_double, _dp]
         L.orc_grad_lap.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_ring_forces.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
@@ -124,7 +126,8 @@ def make_params(p: dict) -> Params:
                   float(p["kappa"][0]), float(p["kappa"][1]), float(p["kappa"][2]),
                   float(p.get("alpha", 1.0)), float(p.get("kappa_c", 0.0)), float(p.get("r_cut", 0.0)),
                   int(p.get("force_form", 0)),
-                  (C.c_double * 3)(*[float(v) for v in (list(p.get("fext", ())) + [0.0, 0.0, 0.0])[:3]]))
+                  (C.c_double * 3)(*[float(v) for v in (list(p.get("fext", ())) + [0.0, 0.0, 0.0])[:3]]),
+                  (C.c_double * 3)(*[float(v) for v in (list(p.get("mw", ())) + [1.0, 1.0, 1.0])[:3]]))
 
 
 def pressure_tensor(p: dict, q, g, l, D: int = 2):
@@ -306,6 +309,20 @@ def mu(p: dict, rho, phi, psi, lap_rho, lap_phi, lap_psi, I=0.0):
     out = np.empty(3)
     prm = make_params(p)
     lib().orc_mu(C.byref(prm), rho, phi, psi, lap_rho, lap_phi, lap_psi, I, _d(out))
+    return out
+
+
+def mu_general(p: dict, rho, phi, psi, lap_rho, lap_phi, lap_psi, I=0.0):
+    out = np.empty(3)
+    prm = make_params(p)
+    lib().orc_mu_general(C.byref(prm), rho, phi, psi, lap_rho, lap_phi, lap_psi, I, _d(out))
+    return out
+
+
+def concentrations(p: dict, rho, phi, psi):
+    out = np.empty(3)
+    prm = make_params(p)
+    lib().orc_concentrations(C.byref(prm), rho, phi, psi, _d(out))
     return out
 
 

@@ -181,8 +181,96 @@ int orc_geq(int lattice, double q, double mu, double Gamma, const double* v, dou
 /* thermodynamic force is -rho grad mu_rho - phi grad mu_phi - psi grad mu_psi'.*/
 /* mu_psi' adds the coupling term kappa_c (psi - I) (Sec. 3.1).                 */
 /* ------------------------------------------------------------------ */
+/* ------------------------------------------------------------------ */
+/* Unequal component densities (the extension named in Sec. 5): eq.     */
+/* MassDensity makes the LB density the mass density rho = sum M_m C_m  */
+/* while phi = C1 - C2 and psi = C3 stay as in eq. VariableTransform.    */
+/* READING: the concentrations then follow linearly from (rho, phi, psi) */
+/* with n = C1 + C2 + C3 = (rho - a phi - b psi) / Mb, Mb = (M1 + M2)/2, */
+/* a = (M1 - M2)/2, b = M3 - Mb; the Landau energy keeps its form in the */
+/* C_m; the ideal gas is that of n, c_s^2 Mb n ln n, so the LB carries  */
+/* the pressure p0 = c_s^2 Mb n: its equilibrium adds 3 w_i dp (i > 0,   */
+/* -3 (1 - w_0) dp at rest) to f_i^eq with dp = p0 - c_s^2 rho, and in  */
+/* each bulk phase (n = 1) p0 is the same whatever its density.  All     */
+/* M_m = 1 gives the paper's model exactly.                              */
+/* ------------------------------------------------------------------ */
+static void mw_get(const orc_params* p, double M[3]) {
+  for (int m = 0; m < 3; m++) M[m] = p->mw[m] > 0.0 ? p->mw[m] : 1.0;
+}
+
+static int equal_densities(const orc_params* p) {
+  double M[3];
+  mw_get(p, M);
+  return M[0] == 1.0 && M[1] == 1.0 && M[2] == 1.0;
+}
+
+/* A[m][q]: dC_m / d(rho, phi, psi)_q */
+static void conc_matrix(const orc_params* p, double A[3][3]) {
+  double M[3];
+  mw_get(p, M);
+  const double Mb = 0.5 * (M[0] + M[1]), a = 0.5 * (M[0] - M[1]), b = M[2] - Mb;
+  A[0][0] = 0.5 / Mb;  A[0][1] = 0.5 * (1.0 - a / Mb);  A[0][2] = 0.5 * (-1.0 - b / Mb);
+  A[1][0] = 0.5 / Mb;  A[1][1] = 0.5 * (-1.0 - a / Mb); A[1][2] = 0.5 * (-1.0 - b / Mb);
+  A[2][0] = 0.0;       A[2][1] = 0.0;                    A[2][2] = 1.0;
+}
+
+void orc_concentrations(const orc_params* p, double rho, double phi, double psi, double* C) {
+  if (equal_densities(p)) {
+    /* eq. VariableTransform inverted */
+    C[0] = 0.5 * (rho + phi - psi);
+    C[1] = 0.5 * (rho - phi - psi);
+    C[2] = psi;
+    return;
+  }
+  double A[3][3];
+  conc_matrix(p, A);
+  const double q[3] = {rho, phi, psi};
+  for (int m = 0; m < 3; m++) C[m] = A[m][0] * q[0] + A[m][1] * q[1] + A[m][2] * q[2];
+}
+
+/* the LB pressure shift dp = p0 - c_s^2 rho = -c_s^2 (a phi + b psi) */
+static double pressure_shift(const orc_params* p, double phi, double psi) {
+  double M[3];
+  mw_get(p, M);
+  const double Mb = 0.5 * (M[0] + M[1]), a = 0.5 * (M[0] - M[1]), b = M[2] - Mb;
+  return -CS2 * (a * phi + b * psi);
+}
+
+/* with component densities: the shift of f_i^eq that makes the lattice's
+   pressure p0 instead of c_s^2 rho (zero for equal densities) */
+static void feq_pressure_shift(const lat_t* L, const orc_params* p, double phi, double psi, double* sh) {
+  const double dp = equal_densities(p) ? 0.0 : pressure_shift(p, phi, psi);
+  for (int i = 0; i < L->Q; i++) sh[i] = (i == 0 ? -(1.0 - L->w[0]) : L->w[i]) * dp / CS2;
+}
+
+/* mu_q = sum_m (dC_m/dq) dF/dC_m, dF/dC_m = kappa_m C (1 - C)(1 - 2C) -
+   alpha^2 kappa_m lap C_m, lap C_m = sum_q (dC_m/dq) lap q; the coupling
+   term kappa_c (psi - I) joins mu_psi */
+void orc_mu_general(const orc_params* p, double rho, double phi, double psi, double lr, double lp,
+                    double ls, double I, double* mu3) {
+  double A[3][3];
+  conc_matrix(p, A);
+  const double q[3] = {rho, phi, psi}, l[3] = {lr, lp, ls};
+  const double km[3] = {p->kappa1, p->kappa2, p->kappa3}, a2 = p->alpha * p->alpha;
+  double bm[3];
+  for (int m = 0; m < 3; m++) {
+    double C = 0.0, L = 0.0;
+    for (int k = 0; k < 3; k++) {
+      C += A[m][k] * q[k];
+      L += A[m][k] * l[k];
+    }
+    bm[m] = km[m] * C * (1.0 - C) * (1.0 - 2.0 * C) - a2 * km[m] * L;
+  }
+  for (int k = 0; k < 3; k++) mu3[k] = A[0][k] * bm[0] + A[1][k] * bm[1] + A[2][k] * bm[2];
+  mu3[2] += p->kappa_c * (psi - I);
+}
+
 void orc_mu(const orc_params* p, double rho, double phi, double psi, double lr, double lp,
             double ls, double I, double* mu3) {
+  if (!equal_densities(p)) {
+    orc_mu_general(p, rho, phi, psi, lr, lp, ls, I, mu3);
+    return;
+  }
   const double k1 = p->kappa1, k2 = p->kappa2, k3 = p->kappa3, a2 = p->alpha * p->alpha;
   const double x = rho + phi - psi; /* 2 C1 */
   const double y = rho - phi - psi; /* 2 C2 */
@@ -1053,11 +1141,22 @@ int orc_pressure_tensor(const orc_params* p, int D, const double* q, const doubl
                         double* P) {
   if (!p || D < 2 || D > 3) return -1;
   const double k1 = p->kappa1, k2 = p->kappa2, k3 = p->kappa3, a2 = p->alpha * p->alpha;
-  const double K[3][3] = {{(k1 + k2) / 4.0, (k1 - k2) / 4.0, -(k1 + k2) / 4.0},
-                          {(k1 - k2) / 4.0, (k1 + k2) / 4.0, -(k1 - k2) / 4.0},
-                          {-(k1 + k2) / 4.0, -(k1 - k2) / 4.0, (k1 + k2 + 4.0 * k3) / 4.0}};
-  const double C[3] = {0.5 * (q[0] + q[1] - q[2]), 0.5 * (q[0] - q[1] - q[2]), q[2]};
+  double K[3][3] = {{(k1 + k2) / 4.0, (k1 - k2) / 4.0, -(k1 + k2) / 4.0},
+                    {(k1 - k2) / 4.0, (k1 + k2) / 4.0, -(k1 - k2) / 4.0},
+                    {-(k1 + k2) / 4.0, -(k1 - k2) / 4.0, (k1 + k2 + 4.0 * k3) / 4.0}};
+  double C[3];
+  orc_concentrations(p, q[0], q[1], q[2], C);
   const double km[3] = {k1, k2, k3};
+  if (!equal_densities(p)) {
+    /* the gradient energy's Hessian in (rho, phi, psi): A^T diag(kappa) A */
+    double A[3][3];
+    conc_matrix(p, A);
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        K[i][j] = 0.0;
+        for (int m = 0; m < 3; m++) K[i][j] += A[m][i] * km[m] * A[m][j];
+      }
+  }
   double pb = 0.0;
   for (int m = 0; m < 3; m++) {
     const double c = C[m];
@@ -1169,9 +1268,10 @@ int orc_set_fields(orc_sim* s, const double* rho, const double* phi, const doubl
   const lat_t* L = &s->L;
 #pragma omp parallel for schedule(static)
   for (long n = 0; n < N; n++) {
-    double e[MAXQ];
+    double e[MAXQ], sh[MAXQ];
     feq_all(L, s->rho[n], s->u + 3 * n, e);
-    for (int i = 0; i < L->Q; i++) s->pop[0][(size_t)i * N + n] = e[i];
+    feq_pressure_shift(L, &s->p, s->phi[n], s->psi[n], sh);
+    for (int i = 0; i < L->Q; i++) s->pop[0][(size_t)i * N + n] = e[i] + sh[i];
     geq_all(L, s->phi[n], s->mu[1][n], s->p.gamma_phi, s->u + 3 * n, e);
     for (int i = 0; i < L->Q; i++) s->pop[1][(size_t)i * N + n] = e[i];
     geq_all(L, s->psi[n], s->mu[2][n], s->p.gamma_psi, s->u + 3 * n, e);
@@ -1202,13 +1302,16 @@ static void collide_node(const lat_t* L, const orc_params* p, double in[3][MAXQ]
     up[a] = u[a] + du[a];
     v[a] = u[a] + 0.5 * du[a];
   }
-  double fe[MAXQ], fe2[MAXQ], ge[MAXQ], he[MAXQ];
+  double fe[MAXQ], fe2[MAXQ], ge[MAXQ], he[MAXQ], sh[MAXQ];
   feq_all(L, rho, u, fe);
   feq_all(L, rho, up, fe2);
   geq_all(L, phi, mu_phi, p->gamma_phi, v, ge);
   geq_all(L, psi, mu_psi, p->gamma_psi, v, he);
+  feq_pressure_shift(L, p, phi, psi, sh);
   for (int i = 0; i < L->Q; i++) {
-    post[0][i] = in[0][i] - (in[0][i] - fe[i]) / p->tau + (fe2[i] - fe[i]);
+    /* the pressure shift moves the BGK target only: it cancels in the
+       exact-difference term */
+    post[0][i] = in[0][i] - (in[0][i] - (fe[i] + sh[i])) / p->tau + (fe2[i] - fe[i]);
     post[1][i] = in[1][i] - (in[1][i] - ge[i]) / p->tau_phi;
     post[2][i] = in[2][i] - (in[2][i] - he[i]) / p->tau_psi;
   }
@@ -1436,11 +1539,14 @@ int orc_get_fields(const orc_sim* s, double* rho, double* c1, double* c2, double
       ph += s->pop[1][(size_t)i * N + n];
       ps += s->pop[2][(size_t)i * N + n];
     }
-    /* eq. VariableTransform inverted: C1 = (rho+phi-psi)/2, C2 = (rho-phi-psi)/2, C3 = psi */
+    /* eq. VariableTransform inverted (with component densities, the map of
+       orc_concentrations) */
+    double C[3];
+    orc_concentrations(&s->p, r, ph, ps, C);
     if (rho) rho[n] = r;
-    if (c1) c1[n] = 0.5 * (r + ph - ps);
-    if (c2) c2[n] = 0.5 * (r - ph - ps);
-    if (c3) c3[n] = ps;
+    if (c1) c1[n] = C[0];
+    if (c2) c2[n] = C[1];
+    if (c3) c3[n] = C[2];
     if (ux) ux[n] = m[0] / r;
     if (uy) uy[n] = m[1] / r;
     if (uz) uz[n] = m[2] / r;
@@ -1488,9 +1594,9 @@ int orc_energy(orc_sim* s, orc_energies* out) {
   double* G = (double*)malloc(sizeof(double) * D * (size_t)N);
   for (int m = 0; m < 3; m++) C[m] = (double*)malloc(sizeof(double) * (size_t)N);
   for (long n = 0; n < N; n++) {
-    C[0][n] = 0.5 * (s->rho[n] + s->phi[n] - s->psi[n]);
-    C[1][n] = 0.5 * (s->rho[n] - s->phi[n] - s->psi[n]);
-    C[2][n] = s->psi[n];
+    double c[3];
+    orc_concentrations(&s->p, s->rho[n], s->phi[n], s->psi[n], c);
+    for (int m = 0; m < 3; m++) C[m][n] = c[m];
   }
   const double kap[3] = {s->p.kappa1, s->p.kappa2, s->p.kappa3};
   const double a2 = s->p.alpha * s->p.alpha;
@@ -1514,7 +1620,16 @@ int orc_energy(orc_sim* s, orc_energies* out) {
     double uu = 0;
     for (int a = 0; a < 3; a++) uu += s->u[3 * n + a] * s->u[3 * n + a];
     ek += 0.5 * s->rho[n] * uu;
-    pid += CS2 * s->rho[n] * log(s->rho[n]);
+    /* c_s^2 rho ln rho; with component densities that of n: c_s^2 Mb n ln n */
+    if (equal_densities(&s->p)) {
+      pid += CS2 * s->rho[n] * log(s->rho[n]);
+    } else {
+      double M[3];
+      mw_get(&s->p, M);
+      const double Mb = 0.5 * (M[0] + M[1]);
+      const double nn = C[0][n] + C[1][n] + C[2][n];
+      pid += CS2 * Mb * nn * log(nn);
+    }
   }
   out->E_kin = ek;
   out->p_ideal = pid;

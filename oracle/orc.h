@@ -43,6 +43,10 @@ typedef struct {
                              with the pressure tensor of Appendix A (D2Q9 only)  */
   double fext[3];         /* uniform external force density f_ext of eq.
                              ForcingTermLBE (zero in the paper's runs)           */
+  double mw[3];           /* component densities M_w,m of eq. MassDensity
+                             (rho = sum_m M_m C_m); <= 0 means 1.  All equal to
+                             1 is the paper's model; otherwise the extension the
+                             paper names in its conclusions, see orc.c          */
 } orc_params;
 
 /* energies and conserved sums, all FP64 */
@@ -113,9 +117,16 @@ int orc_feq(int lattice, double rho, const double* u, double* out);
 /* g^eq / h^eq for order parameter q with chemical potential mu, mobility Gamma */
 int orc_geq(int lattice, double q, double mu, double Gamma, const double* v, double* out);
 /* chemical potentials (mu_rho without its ideal-gas part, mu_phi, mu_psi')
-   from local values and Laplacians, Appendix A */
+   from local values and Laplacians, Appendix A (equal densities) or the
+   general form through the concentrations (unequal densities) */
 void orc_mu(const orc_params* p, double rho, double phi, double psi,
             double lap_rho, double lap_phi, double lap_psi, double I, double* mu3);
+/* the same always through the concentration map of mw (for the pin that
+   the general form reduces to Appendix A when every M_m is 1) */
+void orc_mu_general(const orc_params* p, double rho, double phi, double psi,
+                    double lap_rho, double lap_phi, double lap_psi, double I, double* mu3);
+/* concentrations C1..C3 from rho, phi, psi under the component densities */
+void orc_concentrations(const orc_params* p, double rho, double phi, double psi, double* C);
 /* one BGK collision (eq. LBE) of the populations in = [f(Q), g(Q), h(Q)] of
    one node under force F, with the given chemical potentials; out likewise */
 int orc_collide(const orc_params* p, const double* in, const double* F, double mu_phi,

@@ -85,16 +85,18 @@ def _min_image(dx, n):
     return dx - n * np.round(dx / n)
 
 
-def fields_from_C(C1, C2, C3, perturb=0.0, seed=0, u=None):
+def fields_from_C(C1, C2, C3, perturb=0.0, seed=0, u=None, mw=(1.0, 1.0, 1.0)):
     """rho, phi, psi from concentrations (eq. VariableTransform), after adding a
-    seeded uniform perturbation in [-perturb, perturb] to every C_m."""
+    seeded uniform perturbation in [-perturb, perturb] to every C_m.  With
+    component densities mw, rho is the mass density sum_m mw_m C_m (eq.
+    MassDensity)."""
     C1, C2, C3 = (np.array(c, dtype=np.float64) for c in (C1, C2, C3))
     if perturb:
         g = rng(seed)
         C1 = C1 + g.uniform(-perturb, perturb, C1.shape)
         C2 = C2 + g.uniform(-perturb, perturb, C2.shape)
         C3 = C3 + g.uniform(-perturb, perturb, C3.shape)
-    rho = C1 + C2 + C3
+    rho = mw[0] * C1 + mw[1] * C2 + mw[2] * C3
     out = dict(rho=rho, phi=C1 - C2, psi=C3)
     if u is not None:
         out["u"] = [np.full(rho.shape, float(c)) for c in u]
@@ -104,9 +106,10 @@ def fields_from_C(C1, C2, C3, perturb=0.0, seed=0, u=None):
 def capsule_at_interface(nx=128, ny=128, R=20.0, n_markers=128, centre=None, y0=None,
                          kappa=(0.02, 0.02, 0.02), alpha=1.0, kappa_c=0.01, kappa_s=0.01,
                          kappa_b=1e-4, wall_y=1, mobility=0.1, tau=1.0, tau_phi=1.0, tau_psi=1.0,
-                         perturb=1e-4, seed=SEED_BASE, u0=None, r_cut=0.0):
+                         perturb=1e-4, seed=SEED_BASE, u0=None, r_cut=0.0, mw=(1.0, 1.0, 1.0)):
     """One capsule of fluid 3 centred on a flat C1/C2 interface at y = y0
-    (C1 below, C2 above), in a box periodic in x (Sec. 4.1)."""
+    (C1 below, C2 above), in a box periodic in x (Sec. 4.1).  ``mw``:
+    component densities (all 1 in the paper)."""
     if centre is None:
         centre = (nx / 2.0, (ny - 1) / 2.0)
     if y0 is None:
@@ -124,7 +127,9 @@ def capsule_at_interface(nx=128, ny=128, R=20.0, n_markers=128, centre=None, y0=
         below = tanh_profile(ny / 4.0 - np.abs(dyy), alpha)
     C1 = (1.0 - C3) * below
     C2 = 1.0 - C1 - C3
-    fields = fields_from_C(C1, C2, C3, perturb, seed, u=(u0 if u0 is None else (u0, 0.0)))
+    fields = fields_from_C(C1, C2, C3, perturb, seed, u=(u0 if u0 is None else (u0, 0.0)), mw=mw)
+    if tuple(mw) != (1.0, 1.0, 1.0):
+        p["mw"] = [float(m) for m in mw]
     mem = [dict(X=circle_markers(centre[0], centre[1], R, n_markers), tris=None,
                 kappa_s=kappa_s, kappa_b=kappa_b)]
     return dict(params=p, fields=fields, membranes=mem, name=f"capsule_at_interface_{nx}x{ny}")
@@ -245,9 +250,12 @@ def forced_fluid(n=24, fext=(1e-5, -5e-6), tau=1.0, R=2.0, n_markers=12, kappa=(
                 name=f"forced_fluid_{n}x{n}_tau{tau:g}")
 
 
-def flat(nx=4, ny=64, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_y=1, seed=None):
-    """Flat C1/C2 interface at y = (ny-1)/2, C1 below; no membrane."""
+def flat(nx=4, ny=64, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_y=1, seed=None,
+         mw=(1.0, 1.0, 1.0)):
+    """Flat C1/C2 interface at y = (ny-1)/2, C1 below; no membrane.  ``mw``:
+    component densities (all 1 in the paper)."""
     p = base_params(nx, ny, wall_y=wall_y, kappa=kappa, alpha=alpha, kappa_c=0.0, mobility=mobility)
+    p["mw"] = [float(m) for m in mw]
     x, y = _grid2(nx, ny)
     y0 = (ny - 1) / 2.0
     if wall_y:
@@ -256,18 +264,20 @@ def flat(nx=4, ny=64, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, wall_y=
         C1 = tanh_profile(ny / 4.0 - np.abs(_min_image(y - y0 + ny / 4.0, ny)), alpha)
     C2 = 1.0 - C1
     C3 = np.zeros_like(C1)
-    return dict(params=p, fields=fields_from_C(C1, C2, C3), membranes=[], name="flat")
+    return dict(params=p, fields=fields_from_C(C1, C2, C3, mw=mw), membranes=[], name="flat")
 
 
-def drop(n=64, R=12.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1):
-    """C3 drop of radius R in C1, fully periodic box, no membrane."""
+def drop(n=64, R=12.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1, mw=(1.0, 1.0, 1.0)):
+    """C3 drop of radius R in C1, fully periodic box, no membrane.  ``mw``:
+    component densities (all 1 in the paper)."""
     p = base_params(n, n, wall_y=0, kappa=kappa, alpha=alpha, kappa_c=0.0, mobility=mobility)
+    p["mw"] = [float(m) for m in mw]
     x, y = _grid2(n, n)
     c = (n - 1) / 2.0
     C3 = tanh_profile(R - np.hypot(x - c, y - c), alpha)
     C1 = 1.0 - C3
     C2 = np.zeros_like(C1)
-    return dict(params=p, fields=fields_from_C(C1, C2, C3), membranes=[], name="drop")
+    return dict(params=p, fields=fields_from_C(C1, C2, C3, mw=mw), membranes=[], name="drop")
 
 
 def lens(nx=120, ny=80, R=20.0, kappa=(0.02, 0.02, 0.02), alpha=1.0, mobility=0.1):
