@@ -7,7 +7,7 @@ hand-written HIP kernels) learns the map, and a warm-started run begins
 from the predicted shape -- markers on the predicted curve, concentration
 fields built around it, rest lengths those of the undeformed circle -- while
 the cold start begins from the circle.  Equilibrium: the shape coefficients
-drift by less than `tol` over the last 1000 steps (checked every 100
+drift by less than `tol` over the last 1000 steps (checked every 250
 steps), or the step cap.
 """
 from __future__ import annotations
@@ -20,19 +20,23 @@ from . import lbib, shape
 from . import workloads as W
 
 SEED = W.SEED_BASE + 4
-R_RANGE = (8.0, 16.0)
 
 
 def param_sets(count: int, seed: int = SEED) -> list:
-    """kappa_m U[0.01, 0.05], shear modulus log-U[1e-3, 1e-1], bending
-    log-U[1e-5, 1e-3], radius U[8, 16]."""
+    """The parameter distribution of the batched capsule workload: kappa_m
+    U[0.01, 0.05], shear modulus log-U[1e-3, 1e-1], bending log-U[1e-5,
+    1e-3], and the radius drawn as there, R ~ U[12, min(48, n/4)] with the
+    lattice side n = 16 U_int[6, 32].  The run itself uses a lattice of side
+    2R + 44 (rounded up to 16, side()), whose walls stand 22 nodes from the
+    capsule: the side n only shapes the radius distribution."""
     g = W.rng(seed)
     out = []
     for _ in range(count):
         kap = g.uniform(0.01, 0.05, 3)
         ks = float(10 ** g.uniform(-3, -1))
         kb = float(10 ** g.uniform(-5, -3))
-        R = float(g.uniform(*R_RANGE))
+        n = 16 * int(g.integers(6, 33))
+        R = float(g.uniform(12.0, min(48.0, 0.25 * n)))
         out.append(dict(kappa=[float(k) for k in kap], kappa_s=ks, kappa_b=kb, R=R))
     return out
 
@@ -84,43 +88,62 @@ def warm_workload(ps: dict, coef: np.ndarray, seed: int = 0) -> dict:
 
 
 def run_batched(workloads: list, max_steps: int, tol: float = 1e-3, every: int = 250,
-                window: int = 1000, device="cuda:0", log: bool = True):
-    """Run every workload in batches of up to 256 members until its shape
-    coefficients drift by less than tol over `window` steps, or max_steps.
-    Returns (coefficients at equilibrium or at the cap, steps to
-    equilibrium or -1, seconds of wall time per batch)."""
+                window: int = 1000, device="cuda:0", log: bool = True, retire: bool = True,
+                batch_max: int = 256):
+    """Run every workload in batches of up to batch_max members until its
+    shape coefficients drift by less than tol over `window` steps, or
+    max_steps.  With `retire`, a batch whose live members have fallen to half
+    or less is rebuilt from them alone (each one's state carried over by a
+    checkpoint), so members at equilibrium stop costing steps.  Returns
+    (coefficients at equilibrium or at the cap, steps to equilibrium or -1,
+    wall seconds per batch)."""
+    import time
+
     coefs = [None] * len(workloads)
     steps = [-1] * len(workloads)
     walls = []
-    import time
-
-    for b0 in range(0, len(workloads), 256):
-        ws = workloads[b0:b0 + 256]
-        b = lbib.Batch.from_workloads(ws, device=device)
-        meta = [dict(R=w["R"], y0=(w["params"]["ny"] - 1) / 2.0, hist=[]) for w in ws]
-        live = set(range(len(ws)))
+    for b0 in range(0, len(workloads), batch_max):
+        idx = list(range(b0, min(b0 + batch_max, len(workloads))))
+        meta = {i: dict(R=workloads[i]["R"], y0=(workloads[i]["params"]["ny"] - 1) / 2.0, hist=[]) for i in idx}
         t0 = time.perf_counter()
+        b = lbib.Batch.from_workloads([workloads[i] for i in idx], device=device)
+        members = list(idx)  # workload index of each batch member
+        live = set(idx)
         step = 0
+        rebuilds = 0
         while live and step < max_steps:
             b.step(every)
             step += every
             allx = b.markers()
-            for k in list(live):
-                c = shape.coefficients(allx[k][0], meta[k]["R"], meta[k]["y0"])
-                h = meta[k]["hist"]
+            for k, i in enumerate(members):
+                if i not in live:
+                    continue
+                c = shape.coefficients(allx[k][0], meta[i]["R"], meta[i]["y0"])
+                h = meta[i]["hist"]
                 h.append((step, c))
                 while h and h[0][0] < step - window:
                     h.pop(0)
-                coefs[b0 + k] = c
+                coefs[i] = c
                 if h[0][0] == step - window and np.abs(c - h[0][1]).max() < tol:
-                    steps[b0 + k] = step
-                    live.discard(k)
+                    steps[i] = step
+                    live.discard(i)
+            if retire and live and 2 * len(live) <= len(members):
+                keep = [k for k, i in enumerate(members) if i in live]
+                blobs = [b[k].save() for k in keep]
+                nb = lbib.Batch.from_workloads([workloads[members[k]] for k in keep], device=device)
+                for j, blob in enumerate(blobs):
+                    nb[j].load(blob)
+                b.close()
+                b = nb
+                members = [members[k] for k in keep]
+                rebuilds += 1
         b.synchronize()
         walls.append(time.perf_counter() - t0)
         b.close()
         if log:
-            done = sum(st > 0 for st in steps[b0:b0 + len(ws)])
-            print(f"  batch {b0 // 256}: {len(ws)} runs, {done} at equilibrium, {walls[-1]:.1f} s", flush=True)
+            done = sum(steps[i] > 0 for i in idx)
+            print(f"  batch {b0 // batch_max}: {len(idx)} runs, {done} at equilibrium, {walls[-1]:.1f} s, "
+                  f"{rebuilds} rebuilds", flush=True)
     return coefs, steps, walls
 
 
@@ -166,9 +189,37 @@ def polygon_gap(A: np.ndarray, B: np.ndarray) -> float:
     return float(best.max())
 
 
+def _gen_files(out: str) -> list:
+    import glob
+    import os
+
+    return sorted(glob.glob(os.path.join(out, "gen_*.npz")))
+
+
+def generate(first: int, count: int, cap: int, tol: float, out: str) -> str:
+    """Cold runs of parameter sets [first, first + count) to equilibrium with
+    the batched solver; their final coefficients and steps go to
+    out/gen_<first>_<count>.npz."""
+    import os
+    import time
+
+    ps = param_sets(first + count)[first:]
+    ws = [cold_workload(p, seed=first + k) for k, p in enumerate(ps)]
+    t0 = time.perf_counter()
+    coefs, steps, walls = run_batched(ws, cap, tol)
+    wall = time.perf_counter() - t0
+    path = os.path.join(out, f"gen_{first:05d}_{count:05d}.npz")
+    np.savez(path, first=first, X=np.array([features(p) for p in ps]), Y=np.array(coefs),
+             steps=np.array(steps), wall=wall, nodes=np.array([w["params"]["nx"] * w["params"]["ny"] for w in ws]))
+    print(f"generated sets {first}..{first + count - 1} in {wall:.1f} s, "
+          f"{sum(s > 0 for s in steps)} at equilibrium -> {path}", flush=True)
+    return path
+
+
 def main():
-    """Generate equilibria with the batched solver, train the network on the
-    device, and compare warm and cold starts on held-out parameter sets."""
+    """Generate equilibria with the batched solver (in chunks), train the
+    network on the device on the runs that reached equilibrium, and compare
+    warm and cold starts on held-out parameter sets at equal batching."""
     import argparse
     import json
     import os
@@ -177,65 +228,84 @@ def main():
     from . import mlp
 
     ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["generate", "train", "evaluate"])
     ap.add_argument("--train", type=int, default=4096)
     ap.add_argument("--test", type=int, default=256)
+    ap.add_argument("--first", type=int, default=0, help="generate: first parameter set")
+    ap.add_argument("--count", type=int, default=1024, help="generate: parameter sets in this chunk")
     ap.add_argument("--cap", type=int, default=30000)
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--epochs", type=int, default=3000)
-    ap.add_argument("--single", type=int, default=32, help="held-out sets also run alone (wall time)")
+    ap.add_argument("--single", type=int, default=16, help="held-out sets also run alone (wall time)")
     ap.add_argument("--out", default="warmstart_out")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
-    ps = param_sets(args.train + args.test)
-    ws = [cold_workload(p, seed=i) for i, p in enumerate(ps)]
-    t0 = time.perf_counter()
-    coefs, steps, walls = run_batched(ws, args.cap, args.tol)
-    t_gen = time.perf_counter() - t0
-    print(f"generated {len(ws)} cold runs in {t_gen:.1f} s, reached {sum(s > 0 for s in steps)}", flush=True)
+    if args.what == "generate":
+        generate(args.first, args.count, args.cap, args.tol, args.out)
+        return
+    if args.what == "train":
+        X, Y, S, wall = [], [], [], 0.0
+        for f in _gen_files(args.out):
+            d = np.load(f)
+            first = int(d["first"])
+            n = min(len(d["steps"]), max(0, args.train - first))
+            X.append(d["X"][:n])
+            Y.append(d["Y"][:n])
+            S.append(d["steps"][:n])
+            wall += float(d["wall"])
+        X, Y, S = np.concatenate(X), np.concatenate(Y), np.concatenate(S)
+        ok = S > 0  # equilibria only: runs that hit the step cap are left out
+        model, hist = mlp.train(X[ok], Y[ok], epochs=args.epochs)
+        model.save(os.path.join(args.out, "warmstart_mlp.npz"))
+        info = {"train_sets": int(len(S)), "train_rows_at_equilibrium": int(ok.sum()), "generation_seconds": wall,
+                "train_loss": hist[-1][1], "loss_history": hist, "epochs": args.epochs}
+        json.dump(info, open(os.path.join(args.out, "warmstart_train.json"), "w"), indent=1)
+        print(json.dumps({k: v for k, v in info.items() if k != "loss_history"}), flush=True)
+        return
+    # evaluate: held-out sets, warm and cold, each batched the same way
+    model = mlp.WarmStartModel.load(os.path.join(args.out, "warmstart_mlp.npz"))
+    ps_all = param_sets(args.train + args.test)
+    test = list(range(args.train, args.train + args.test))
+    ps = [ps_all[i] for i in test]
     X = np.array([features(p) for p in ps])
-    Y = np.array(coefs)
-    ntr = args.train
-    model, hist = mlp.train(X[:ntr], Y[:ntr], epochs=args.epochs)
-    print("trained", hist[-1], flush=True)
-    model.save(os.path.join(args.out, "warmstart_mlp.npz"))
-    pred = model.predict(X[ntr:])
-    test = list(range(ntr, len(ps)))
-    wws = [warm_workload(ps[i], pred[k], seed=i) for k, i in enumerate(test)]
+    pred = model.predict(X)
+    cws = [cold_workload(p, seed=i) for p, i in zip(ps, test)]
+    wws = [warm_workload(p, pred[k], seed=i) for k, (p, i) in enumerate(zip(ps, test))]
     t0 = time.perf_counter()
-    wcoefs, wsteps, wwalls = run_batched(wws, args.cap, args.tol)
+    wcoefs, wsteps, _ = run_batched(wws, args.cap, args.tol)
     t_warm = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ccoefs, csteps, cwalls = run_batched([ws[i] for i in test], args.cap, args.tol)
+    ccoefs, csteps, _ = run_batched(cws, args.cap, args.tol)
     t_cold = time.perf_counter() - t0
     single = []
-    for i in test[:args.single]:
-        single.append(run_single(ws[i], args.cap, args.tol))
-        print(f"  single run {len(single)}: {single[-1][1]} steps, {single[-1][2]:.1f} s", flush=True)
-    R = np.array([ps[i]["R"] for i in test])
+    for k in range(min(args.single, len(cws))):
+        single.append(run_single(cws[k], args.cap, args.tol))
+        print(f"  single run {k}: {single[-1][1]} steps, {single[-1][2]:.1f} s", flush=True)
     cs, wsx = np.array(csteps), np.array(wsteps)
     both = (cs > 0) & (wsx > 0)
-    pred_err = np.abs(pred - Y[ntr:]).max(1)
+    pred_err = np.abs(pred - np.array(ccoefs)).max(1)
     shape_err = np.abs(np.array(wcoefs) - np.array(ccoefs)).max(1)
     gaps = []
-    for k, i in enumerate(test):
-        ww, cw = wws[k], ws[i]
+    for k, p in enumerate(ps):
+        cw = cws[k]
         nm = len(cw["membranes"][0]["X"])
         xc, y0 = cw["params"]["nx"] / 2.0, (cw["params"]["ny"] - 1) / 2.0
-        A = shape.markers(np.array(wcoefs[k]), ps[i]["R"], xc, y0, nm)
-        B = shape.markers(np.array(ccoefs[k]), ps[i]["R"], xc, y0, nm)
-        gaps.append(polygon_gap(A, B) / ps[i]["R"])
+        A = shape.markers(np.array(wcoefs[k]), p["R"], xc, y0, nm)
+        B = shape.markers(np.array(ccoefs[k]), p["R"], xc, y0, nm)
+        gaps.append(polygon_gap(A, B) / p["R"])
+    R = np.array([p["R"] for p in ps])
     res = {
-        "train": ntr, "test": len(test), "cap": args.cap, "tol": args.tol, "epochs": args.epochs,
-        "train_loss": hist[-1][1], "loss_history": hist,
-        "generation_seconds": t_gen, "generation_reached": int(sum(s > 0 for s in steps[:ntr])),
+        "test": len(test), "cap": args.cap, "tol": args.tol, "radius_range": [float(R.min()), float(R.max())],
         "cold_steps_median": float(np.median(cs[cs > 0])) if (cs > 0).any() else None,
         "warm_steps_median": float(np.median(wsx[wsx > 0])) if (wsx > 0).any() else None,
         "cold_reached": int((cs > 0).sum()), "warm_reached": int((wsx > 0).sum()),
         "steps_ratio_median_both": float(np.median(wsx[both] / cs[both])) if both.any() else None,
+        "warm_faster_of_both": int((wsx[both] < cs[both]).sum()), "both_reached": int(both.sum()),
         "cold_batched_seconds": t_cold, "warm_batched_seconds": t_warm,
-        "cold_single_seconds_per_run": float(np.mean([s[2] for s in single])) if single else None,
-        "cold_single_steps": [s[1] for s in single],
-        "prediction_error_max_median": float(np.median(pred_err)),
+        "wall_ratio_warm_over_cold_batched": t_warm / t_cold,
+        "cold_single_seconds_per_run": float(np.mean([s_[2] for s_ in single])) if single else None,
+        "cold_single_runs": len(single),
+        "prediction_error_max_coef_median": float(np.median(pred_err)),
         "final_shape_error_max_coef_median": float(np.median(shape_err)),
         "final_shape_error_max_coef_p90": float(np.percentile(shape_err, 90)),
         "final_max_marker_distance_over_R_median": float(np.median(gaps)),
