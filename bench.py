@@ -249,7 +249,7 @@ def main():
                      "launch": g.get_launch()},
     }
     k2 = max(args.steps // 4, 1) if args.overlap_steps < 0 else args.overlap_steps
-    if not d3 and k2 > 0 and form == 0:
+    if not d3 and k2 > 0:
         # the same lattice with the regions away from the membranes on a second
         # stream beside the membrane kernels (a scheduling option, bitwise the
         # same results); the roofline above stays the single-stream kernel's

@@ -84,7 +84,9 @@ typedef struct {
   double E_c;               /* kappa_c/2 sum (psi - I)^2, eq. DiscreteCE               */
   double E_s, E_b;          /* membrane strain and bending, eqs. DiscreteSE/BE         */
   double E_kin;             /* 1/2 sum rho |u|^2 with the bare velocity u               */
-  double p_ideal;           /* sum c_s^2 rho ln rho, the ideal-gas term of LandauFE     */
+  double p_ideal;           /* sum c_s^2 rho ln rho, the ideal-gas term of LandauFE
+                               (with component densities c_s^2 (M1+M2)/2 n ln n,
+                               n = C1 + C2 + C3; lbib_set_densities)                  */
 } lbib_energies;
 
 /* Device bytes needed for a simulation with these parameters and capacities. */
@@ -194,8 +196,10 @@ int lbib_timing_enable(lbib_sim* s, int on);
 int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps);
 
 /* Launch shape of the fused lattice kernel (a tuning knob; results do not
-   depend on it): block_x lanes per workgroup (64, 128, 192 or 256; block_x
-   - 4 interior columns), seg rows per workgroup, nxcd the number of L2 domains
+   depend on it): D2Q9, block_x lanes per workgroup (64, 128, 192 or 256;
+   block_x - 4 interior columns); D3Q19, block_x the x extent of a
+   workgroup's tile of 256 nodes (16, 32 (the default) or 64; the y extent
+   is 256 / block_x); seg rows (D3Q19: planes) per workgroup, nxcd the number of L2 domains
    workgroups are dealt to in turn, ring the rows held in registers (3, or 4
    to load the next row while the current ones are computed).  0 keeps the
    current value; seg = -1 returns to the automatic choice (as many
@@ -216,9 +220,8 @@ int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* r
    on = 0 (the default) runs the whole step on the simulation's stream;
    on = -1 selects the library's choice, which is 0 (the passes share the
    memory bandwidth, so the gain is a few per cent).  No effect on D3Q19
-   simulations.  Batch handles and members return LBIB_EINVAL, as do other
-   values of on, and on = 1 while the divergence force form (the D2Q9
-   default) is selected: select the potential form first. */
+   simulations.  Both force forms.  Batch handles and members return
+   LBIB_EINVAL, as do other values of on. */
 int lbib_set_overlap(lbib_sim* s, int on);
 
 /* D2Q9 form of the thermodynamic force of eq. ForceFE (Sec. 3.1).  form = 1
@@ -236,8 +239,7 @@ int lbib_set_overlap(lbib_sim* s, int on);
    that the divergence form does not have.  Takes effect at the next
    lbib_step.  On a batch handle the form applies to every member (the next
    step captures the batch's graphs again).  LBIB_EINVAL for other values,
-   D3Q19 simulations, batch members, and form = 1 while lbib_set_overlap is
-   on. */
+   D3Q19 simulations and batch members. */
 int lbib_set_force_form(lbib_sim* s, int form);
 
 /* D2Q9 coupling-profile search (a scheduling knob; results are bitwise the
@@ -260,6 +262,25 @@ int lbib_set_coupling_cache(lbib_sim* s, int on);
    rebuilds its tables at the next step).  LBIB_EINVAL for non-finite values,
    fz != 0 in 2D, or a batch handle. */
 int lbib_set_external_force(lbib_sim* s, double fx, double fy, double fz);
+
+/* Component densities M_1, M_2, M_3 (the weights of eq. MassDensity,
+   Sec. 2.1; the paper's model takes all three equal to 1, the default, and
+   names unequal densities as its extension in Sec. 5).  rho is then the mass
+   density sum_m M_m C_m while phi = C1 - C2 and psi = C3 keep their meaning
+   (eq. VariableTransform), so the concentrations are a linear map of
+   (rho, phi, psi), the chemical potentials of Appendix A follow through the
+   transpose of that map, and the pressure tensor's gradient part takes its
+   congruent kappa matrix.  The lattice carries the ideal-gas pressure of the
+   number density n = sum_m C_m, c_s^2 (M_1 + M_2)/2 n, through a shift of
+   f_i^eq that leaves its zeroth and first moments unchanged.  The
+   concentrations lbib_get_fields returns, the masses and energies of
+   lbib_energy (p_ideal becomes c_s^2 (M_1 + M_2)/2 sum n ln n) and
+   lbib_set_fields' rho all use the mass density.  D2Q9 and D3Q19; call it
+   before lbib_set_fields.  Works on a simulation or a batch member.
+   LBIB_EINVAL for a value that is not finite and positive, or a batch
+   handle; LBIB_ESTATE once the fields are set.  The checkpoint header
+   records the densities, and lbib_load refuses a state saved with others. */
+int lbib_set_densities(lbib_sim* s, double m1, double m2, double m3);
 
 /* Number of completed steps. */
 long long lbib_steps_done(const lbib_sim* s);

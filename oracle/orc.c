@@ -8,7 +8,10 @@
  * nodes or markers runs serially in a fixed order.
  *
  * Paper sections followed (Pepona et al.):
- *   Sec. 2.4  eq. LandauFE, CouplingE, Iprofile     free energy, coupling profile
+ *   Sec. 2.1  eq. MassDensity                        component densities (the
+ *             extension Sec. 5 names; all 1 in the paper's model)
+ *   Sec. 2.5  eq. LandauFE, CouplingE, Iprofile     free energy, coupling profile
+ *   Sec. 2.6  eq. VariableTransform                  rho, phi, psi from C_m
  *   Sec. 3.1  eq. LBE, EDF, MomentsDFs, ActualFluidVel, VelCorrection,
  *             ForceFE, GradPT                        lattice Boltzmann step
  *   Sec. 3.2  eq. DiscreteSE..DiscreteTF              membrane energies / forces

@@ -1,5 +1,5 @@
 // k_ibm.h -- membrane side of the step for 2D ring membranes: active-tile
-// map, coupling profile I and coupling force (Sec. 2.4 eq. Iprofile, Sec. 3.2
+// map, coupling profile I and coupling force (Sec. 2.5 eq. Iprofile, Sec. 3.2
 // eqs. DiscreteCE/DiscreteCF), strain and bending forces (eqs. DiscreteSF,
 // DiscreteBF), spreading (eq. Spreading) and interpolation + Euler update
 // (eqs. Interpolation, UpdatedXl).  All marker arithmetic is FP64.
@@ -33,12 +33,16 @@ constexpr int COUP_CACHE = 2;      // membranes per tile whose closest segment e
 // segment left off a node's list is then at least this much farther than
 // its closest one, the room a cached entry has before the markers' drift
 // expires it
-constexpr float COUP_PAD = 1.0f;
-constexpr int COUP_WIN = 3;        // a cached entry re-evaluates its segment and 3 on each side
+constexpr float COUP_PAD = 2.0f;
+constexpr int COUP_WIN = 8;        // a cached entry re-evaluates its segment and 8 on each side
+// a wave renews at most this many expired entries one by one (each costs a
+// pass over the whole ring, about what the tile's full search costs its
+// nodes); with more, the tile searches in full and renews every entry
+constexpr int COUP_RENEW = 8;
 // with the cache on, a tile, sub-tile or node is taken to lie beyond the
 // band without a search only this much farther out, so its entry outlasts
 // some drift; nearer nodes are searched and keep their closest segment
-constexpr float COUP_BEYOND = 0.5f;
+constexpr float COUP_BEYOND = 1.0f;
 constexpr int COUP_FACC = 128;     // per-tile LDS accumulator of coupling forces, markers per slot
 
 struct MemDev {
@@ -529,14 +533,16 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
             }
           }
         }
-        // Entries that have expired are renewed node by node: the node's
-        // wave searches the whole ring for it (FP32 screening relative to
-        // the box centre, FP64 for every segment within the screening
-        // tolerance of the FP32 minimum, lowest index on ties) and keeps
-        // either its closest segment with the exact bound over all segments
-        // beyond the window, or, well beyond the band, its side and distance.
+        // Entries that have expired are renewed node by node, up to
+        // COUP_RENEW per wave: the node's wave searches the whole ring for
+        // it (FP32 screening relative to the box centre, FP64 for every
+        // segment within the screening tolerance of the FP32 minimum, lowest
+        // index on ties) and keeps either its closest segment with the exact
+        // bound over all segments beyond the window, or, well beyond the
+        // band, its side and distance.
         const bool renew = !ok && inbox && ca.ckey[cix] >= 0 && (ca.ckey[cix] >> 16) == m;
         unsigned long long need = __ballot(renew);
+        if (__popcll(need) > COUP_RENEW) need = 0;  // left to the full search
         if (need) {
           const float4* stab = md.stab + b;
           const float* sinv = md.sinv + b;
@@ -1113,7 +1119,7 @@ __device__ __forceinline__ void interp2d_run(const MemDev& md, const St& cur, co
         jx += L::cx[i] * v;
         jy += L::cy[i] * v;
       }
-      const double rho = 1.0 + d;
+      const double rho = P.rho0 + d;
       const double w = peskin(cx - X) * peskin(cy - Y);
       Ux = w * (jx + 0.5 * force[2 * node]) / rho;
       Uy = w * (jy + 0.5 * force[2 * node + 1]) / rho;

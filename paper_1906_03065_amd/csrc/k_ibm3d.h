@@ -1095,7 +1095,7 @@ __global__ void k_interp3d(MemDev md, St cur, LBParams P, const double* __restri
         j[1] += L::cy[i] * v;
         j[2] += L::cz[i] * v;
       }
-      const double rho = 1.0 + d;
+      const double rho = P.rho0 + d;
       const double w = peskin(cx - X[0]) * peskin(cy - X[1]) * peskin(cz - X[2]);
       for (int a = 0; a < 3; a++) U[a] = w * (j[a] + 0.5 * force[3 * node + a]) / rho;
     }
@@ -1134,14 +1134,16 @@ __global__ void k_init3d(St dst, LBParams P, const double* __restrict__ st,
   double I = 0.0;
   if (tflag[tile3(P, x, y, z)] == tstate[1]) I = Ifield[n];
   double mr, mp, ms;
-  chem_pot(P, ctr[0] - 1.0, ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
+  chem_pot(P, ctr[0] - P.rho0, ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
   const double u[3] = {st[3 * P.N + n], st[4 * P.N + n], st[5 * P.N + n]};
   const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double sp = -(P.psh[0] * ctr[1] + P.psh[1] * ctr[2]);  // lattice-pressure shift
   double E[3][19], gs = 0, hs = 0;
   for (int i = 0; i < 19; i++) {
     const double cu = L::cx[i] * u[0] + L::cy[i] * u[1] + L::cz[i] * u[2];
     const double pu = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
-    E[0][i] = L::w(i) * ((ctr[0] - 1.0) + ctr[0] * pu);
+    E[0][i] = i == 0 ? L::w(0) * ((ctr[0] - P.rho0) + ctr[0] * pu) - (1.0 - L::w(0)) * sp
+                     : L::w(i) * ((ctr[0] - P.rho0 + sp) + ctr[0] * pu);
     if (i > 0) {
       E[1][i] = L::w(i) * (3.0 * P.gphi * mp + ctr[1] * pu);
       E[2][i] = L::w(i) * (3.0 * P.gpsi * ms + ctr[2] * pu);
@@ -1190,11 +1192,13 @@ __global__ void k_moments3d(St cur, LBParams P, double* __restrict__ out) {
   double g0, h0, d, jx, jy, jz, phi, psi;
   pull19(cur, P, x, y, z, pf, pg, ph, g0, h0);
   moments19(pf, pg, ph, g0, h0, d, jx, jy, jz, phi, psi);
-  const double rho = 1.0 + d;
+  const double rho = P.rho0 + d;
+  double C[3];
+  conc3(P, rho, phi, psi, C);
   out[n] = rho;
-  out[P.N + n] = 0.5 * (rho + phi - psi);
-  out[2 * P.N + n] = 0.5 * (rho - phi - psi);
-  out[3 * P.N + n] = psi;
+  out[P.N + n] = C[0];
+  out[2 * P.N + n] = C[1];
+  out[3 * P.N + n] = C[2];
   out[4 * P.N + n] = jx / rho;
   out[5 * P.N + n] = jy / rho;
   out[6 * P.N + n] = jz / rho;
@@ -1235,7 +1239,12 @@ __global__ __launch_bounds__(NT) void k_energy_nodes3d(LBParams P, const double*
     const double rho = mom[n];
     const double u0 = mom[4 * P.N + n], u1 = mom[5 * P.N + n], u2 = mom[6 * P.N + n];
     v[6] = 0.5 * rho * (u0 * u0 + u1 * u1 + u2 * u2);
-    v[7] = rho * log(rho) / 3.0;
+    if (P.dens) {  // ideal gas of the number density, c_s^2 M_b n ln n
+      const double nn = mom[P.N + n] + mom[2 * P.N + n] + mom[3 * P.N + n];
+      v[7] = P.mb * nn * log(nn) / 3.0;
+    } else {
+      v[7] = rho * log(rho) / 3.0;
+    }
   }
   for (int k = 0; k < 8; k++) {
     const double s = block_sum<NT>(v[k], sh);

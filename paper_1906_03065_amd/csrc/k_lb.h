@@ -38,6 +38,17 @@ struct LBParams {
   double gphi, gpsi;                         // Gamma_phi, Gamma_psi (eq. EDF)
   double k1, k2, k3, a2, kc;                 // kappa_m, alpha^2, kappa_c
   double fext[3];                            // uniform external force density (eq. ForcingTermLBE)
+  // component densities M_m (eq. MassDensity; all 1 in the paper): the
+  // concentrations are C_m = sum_q cm[m][q] q with q = (rho, phi, psi), and
+  // the lattice pressure is c_s^2 (rho + sp) with sp = -(psh[0] phi + psh[1] psi)
+  double cm[3][3];
+  double psh[2];
+  double mb;                                 // (M_1 + M_2) / 2
+  // reference density of the stored populations: a kernel holds f_i - w_i rho0
+  // (rho0 = M_b, 1 for equal densities), so that the moving populations stay
+  // small where the lattice pressure is c_s^2 M_b n with n ~ 1
+  double rho0;
+  int dens;                                  // 1 if some M_m differs from 1
   int nx, ny, nz, wall_y, wall_z;
   long long N;
   int ntx, nty, tile;                        // tile grid of the membrane maps
@@ -65,35 +76,46 @@ __device__ __forceinline__ void strip_segment(int b, int nstrip, int nseg, int n
 }
 
 // mu_rho (without the ideal-gas part), mu_phi, mu_psi' from local values and
-// Laplacians.  Written through the concentrations: with
-// C1 = (rho+phi-psi)/2, C2 = (rho-phi-psi)/2, C3 = psi (eq. VariableTransform)
-// the derivative of the Landau energy (eq. LandauFE) with respect to C_m is
+// Laplacians, written through the concentrations C_m, a linear map of
+// (rho, phi, psi) (eq. VariableTransform; with component densities, eq.
+// MassDensity solved for C_1 + C_2).  The derivative of the Landau energy
+// (eq. LandauFE) with respect to C_m is
 // b_m = kappa_m C_m (1-C_m)(1-2C_m) - alpha^2 kappa_m lap C_m, and the chain
-// rule gives mu_rho = (b1+b2)/2, mu_phi = (b1-b2)/2, mu_psi = b3 - (b1+b2)/2;
-// the coupling energy (eq. CouplingE) adds kappa_c (psi - I) to mu_psi.
+// rule gives mu_q = sum_m (dC_m/dq) b_m; for equal densities
+// mu_rho = (b1+b2)/2, mu_phi = (b1-b2)/2, mu_psi = b3 - (b1+b2)/2.  The
+// coupling energy (eq. CouplingE) adds kappa_c (psi - I) to mu_psi.  The
+// map's coefficients for equal densities are 0, +-1/2 and 1, so the sums
+// round as the closed forms do.
+__device__ __forceinline__ void conc3(const LBParams& P, double a, double b, double c, double* C) {
+#pragma unroll
+  for (int m = 0; m < 3; m++) C[m] = P.cm[m][0] * a + P.cm[m][1] * b + P.cm[m][2] * c;
+}
+
 __device__ __forceinline__ void chem_pot(const LBParams& P, double drho, double phi, double psi,
                                          double lr, double lp, double ls, double I, double& mr,
                                          double& mp, double& ms) {
-  const double rho = 1.0 + drho;
-  const double C1 = 0.5 * (rho + phi - psi), C2 = 0.5 * (rho - phi - psi);
-  const double L1 = 0.5 * (lr + lp - ls), L2 = 0.5 * (lr - lp - ls);
-  const double b1 = P.k1 * (C1 * (1.0 - C1) * (1.0 - 2.0 * C1) - P.a2 * L1);
-  const double b2 = P.k2 * (C2 * (1.0 - C2) * (1.0 - 2.0 * C2) - P.a2 * L2);
-  const double b3 = P.k3 * (psi * (1.0 - psi) * (1.0 - 2.0 * psi) - P.a2 * ls);
-  mr = 0.5 * (b1 + b2);
-  mp = 0.5 * (b1 - b2);
-  ms = b3 - 0.5 * (b1 + b2) + P.kc * (psi - I);
+  const double rho = P.rho0 + drho;
+  double C[3], Lc[3];
+  conc3(P, rho, phi, psi, C);
+  conc3(P, lr, lp, ls, Lc);
+  const double km[3] = {P.k1, P.k2, P.k3};
+  double b[3];
+#pragma unroll
+  for (int m = 0; m < 3; m++) b[m] = km[m] * (C[m] * (1.0 - C[m]) * (1.0 - 2.0 * C[m]) - P.a2 * Lc[m]);
+  mr = (P.cm[0][0] * b[0] + P.cm[1][0] * b[1]) + P.cm[2][0] * b[2];
+  mp = (P.cm[0][1] * b[0] + P.cm[1][1] * b[1]) + P.cm[2][1] * b[2];
+  ms = (P.cm[0][2] * b[0] + P.cm[1][2] * b[1]) + P.cm[2][2] * b[2] + P.kc * (psi - I);
 }
 
 // BGK + exact-difference collision of one node, D2Q9, in place.  pf holds
-// f_i - w_i (all i), pg/ph the moving g_i/h_i (i >= 1), g0/h0 the rest
+// f_i - w_i rho0 (all i), pg/ph the moving g_i/h_i (i >= 1), g0/h0 the rest
 // populations.  Moments and the total force (Fx, Fy) are FP64.
 template <typename R>
 __device__ __forceinline__ void collide9(const LBParams& P, R* pf, R* pg, R* ph, double& g0,
                                          double& h0, double drho, double jx, double jy, double phi,
                                          double psi, double mphi, double mpsi, double Fx, double Fy) {
   using L = Lattice<9>;
-  const double rho = 1.0 + drho;
+  const double rho = P.rho0 + drho;
   const double irho = 1.0 / rho;
   const double uxd = jx * irho, uyd = jy * irho;
   const double duxd = Fx * irho, duyd = Fy * irho;  // eq. VelCorrection
@@ -104,6 +126,11 @@ __device__ __forceinline__ void collide9(const LBParams& P, R* pf, R* pg, R* ph,
   const R rr = (R)rho, dr = (R)drho, ph_ = (R)phi, ps_ = (R)psi;
   const R gm = (R)(3.0 * P.gphi * mphi), hm = (R)(3.0 * P.gpsi * mpsi);
   const R itf = (R)P.inv_tau, itg = (R)P.inv_tau_phi, ith = (R)P.inv_tau_psi;
+  // with component densities the equilibrium carries the lattice pressure
+  // c_s^2 (rho + sp): w_i sp joins every moving population, -(1 - w_0) sp
+  // the rest one (zero for equal densities)
+  const double spd = -(P.psh[0] * phi + P.psh[1] * psi);
+  const R sp = (R)spd, drs = dr + sp;
   double gsum = 0.0, hsum = 0.0;
 #pragma unroll
   for (int i = 0; i < 9; i++) {
@@ -112,7 +139,8 @@ __device__ __forceinline__ void collide9(const LBParams& P, R* pf, R* pg, R* ph,
     const R cw = R(L::cx[i]) * wx + R(L::cy[i]) * wy;
     const R pu = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
     const R pw = R(3) * cw + R(4.5) * cw * cw - R(1.5) * ww;
-    const R feq = w * (dr + rr * pu);  // f^eq(rho, u) - w_i
+    // f^eq(rho, u) - w_i rho0 (drho = rho - rho0)
+    const R feq = i == 0 ? w * (dr + rr * pu) - R(1.0 - L::w(0)) * sp : w * (drs + rr * pu);
     const R edm = w * rr * (pw - pu);  // f^eq(rho, u + du) - f^eq(rho, u)
     pf[i] = pf[i] - (pf[i] - feq) * itf + edm;
     if (i > 0) {
@@ -159,7 +187,7 @@ __device__ __forceinline__ void pull9(const St& src, const LBParams& P, int x, i
   }
 }
 
-// moments of eq. MomentsDFs: the sums over the small values (f_i - w_i and
+// moments of eq. MomentsDFs: the sums over the small values (f_i - w_i rho0 and
 // the moving g_i, h_i) run in R, the rest populations g_0, h_0 join in FP64
 template <typename R>
 __device__ __forceinline__ void moments9(const R* pf, const R* pg, const R* ph, double g0, double h0,
@@ -301,15 +329,16 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
           gx[f] = (1.0 / 3.0) * (e - wv) + (1.0 / 12.0) * ((ne - nw) + (se - sw));
           gy[f] = (1.0 / 3.0) * (nn - so) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
         }
-        // P' in the concentrations C_m (eq. VariableTransform), where the
-        // energy of eq. LandauFE is a sum of independent terms: for each m
+        // P' in the concentrations C_m (eq. VariableTransform, or its form
+        // with component densities), where the energy of eq. LandauFE is a
+        // sum of independent terms: for each m
         // the bulk part C f_m'(C) - f_m(C) = kappa_m/2 C^2 (1-C)(1-3C) and the
         // gradient part alpha^2 kappa_m (dC dC - (|grad C|^2/2 + C lap C) I)
-        const double rho = 1.0 + ctr[0];
-        const double Cm[3] = {0.5 * (rho + ctr[1] - ctr[2]), 0.5 * (rho - ctr[1] - ctr[2]), ctr[2]};
-        const double Xm[3] = {0.5 * (gx[0] + gx[1] - gx[2]), 0.5 * (gx[0] - gx[1] - gx[2]), gx[2]};
-        const double Ym[3] = {0.5 * (gy[0] + gy[1] - gy[2]), 0.5 * (gy[0] - gy[1] - gy[2]), gy[2]};
-        const double Lm[3] = {0.5 * (lap[0] + lap[1] - lap[2]), 0.5 * (lap[0] - lap[1] - lap[2]), lap[2]};
+        double Cm[3], Xm[3], Ym[3], Lm[3];
+        conc3(P, P.rho0 + ctr[0], ctr[1], ctr[2], Cm);
+        conc3(P, gx[0], gx[1], gx[2], Xm);
+        conc3(P, gy[0], gy[1], gy[2], Ym);
+        conc3(P, lap[0], lap[1], lap[2], Lm);
         const double km[3] = {P.k1, P.k2, P.k3};
         double pb = 0.0, dd = 0.0, cl = 0.0, xy = 0.0;
 #pragma unroll
@@ -372,7 +401,7 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
           gx[f] = (1.0 / 3.0) * (e - wv) + (1.0 / 12.0) * ((ne - nw) + (se - sw));
           gy[f] = (1.0 / 3.0) * (nn - so) + (1.0 / 12.0) * ((ne - se) + (nw - sw));
         }
-        const double rho = 1.0 + d;
+        const double rho = P.rho0 + d;
         // thermodynamic force, eq. ForceFE with eq. GradPT (potential form)
         Fx = -(rho * gx[0] + phi * gx[1] + psi * gx[2]);
         Fy = -(rho * gy[0] + phi * gy[1] + psi * gy[2]);
@@ -467,7 +496,7 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d(St src, St dst, LBParams P,
 // that read no membrane field and may run beside the membrane kernels;
 // mode 2 takes the others after them, each segment cut into npiece pieces of
 // seg2 rows so that the few regions near the membranes still fill the GPU.
-template <class St, typename R, int BX, int NS, int WPE>
+template <class St, typename R, int BX, int NS, int WPE, int FORM = 0>
 __global__ __launch_bounds__(BX, WPE) void k_lb2d_part(St src, St dst, LBParams P,
                                                        const int* __restrict__ tflag,
                                                        const int* __restrict__ tstate,
@@ -492,7 +521,7 @@ __global__ __launch_bounds__(BX, WPE) void k_lb2d_part(St src, St dst, LBParams 
     y1 = min(y0 + P.seg2, y1);
     dir = (piece & 1) ? -1 : 1;
   }
-  lb2d_run<St, R, BX, NS>(src, dst, P, strip, y0, y1, dir, tflag, tstate, Ifield, fib, force);
+  lb2d_run<St, R, BX, NS, FORM>(src, dst, P, strip, y0, y1, dir, tflag, tstate, Ifield, fib, force);
 }
 
 }  // namespace lb

@@ -3,10 +3,12 @@
 // Two kernels per step:
 //   k_mom3d   pull-streams every node and writes its moments drho, phi and
 //             psi (FP64) to a moment field (24 B per node);
-//   k_lb3d    a workgroup owns a 16 x 16 column of nodes and marches along
-//             z.  Per plane it stages the moments of a 20 x 20 region in an
-//             LDS ring, forms mu on the inner 18 x 18 region (Appendix A),
-//             then for its 16 x 16 nodes pulls the populations, forms grad mu,
+//   k_lb3d    a workgroup of 256 threads owns a TX x TY column of nodes
+//             (TX TY = 256; 16 x 16, 32 x 8 or 64 x 4) and marches along z.
+//             Per plane it stages the moments of the (TX+4) x (TY+4) region
+//             in an LDS ring, forms mu on the inner (TX+2) x (TY+2) region
+//             (Appendix A), then for its TX x TY nodes pulls the populations,
+//             forms grad mu,
 //             the force (eqs. ForcingTermLBE, ForceFE + the spread membrane
 //             force) and collides (eq. LBE).
 // In 3D the two-node halo of the mu chain would make a single-pass kernel
@@ -20,9 +22,7 @@
 
 namespace lb {
 
-constexpr int T3 = 16;       // interior tile edge (x and y)
-constexpr int T3H = T3 + 4;  // with the two-node halo
-constexpr int T3U = T3 + 2;  // region where mu is formed
+constexpr int T3 = 32;  // default tile extent in x (y: 256 / T3)
 
 struct Moments3 {
   double* d;     // drho = rho - 1
@@ -102,7 +102,7 @@ __device__ __forceinline__ void collide19(const LBParams& P, R* pf, R* pg, R* ph
                                           double phi, double psi, double mphi, double mpsi,
                                           double Fx, double Fy, double Fz) {
   using L = Lattice<19>;
-  const double rho = 1.0 + drho;
+  const double rho = P.rho0 + drho;
   const double irho = 1.0 / rho;
   const double uxd = jx * irho, uyd = jy * irho, uzd = jz * irho;
   const double dxd = Fx * irho, dyd = Fy * irho, dzd = Fz * irho;  // eq. VelCorrection
@@ -114,6 +114,9 @@ __device__ __forceinline__ void collide19(const LBParams& P, R* pf, R* pg, R* ph
   const R rr = (R)rho, dr = (R)drho, ph_ = (R)phi, ps_ = (R)psi;
   const R gm = (R)(3.0 * P.gphi * mphi), hm = (R)(3.0 * P.gpsi * mpsi);
   const R itf = (R)P.inv_tau, itg = (R)P.inv_tau_phi, ith = (R)P.inv_tau_psi;
+  // lattice pressure c_s^2 (rho + sp) with component densities (sp = 0 for equal ones)
+  const double spd = -(P.psh[0] * phi + P.psh[1] * psi);
+  const R sp = (R)spd, drs = dr + sp;
   double gsum = 0.0, hsum = 0.0;
 #pragma unroll
   for (int i = 0; i < 19; i++) {
@@ -122,7 +125,7 @@ __device__ __forceinline__ void collide19(const LBParams& P, R* pf, R* pg, R* ph
     const R cw = R(L::cx[i]) * wx + R(L::cy[i]) * wy + R(L::cz[i]) * wz;
     const R pu = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
     const R pw = R(3) * cw + R(4.5) * cw * cw - R(1.5) * ww;
-    const R feq = w * (dr + rr * pu);
+    const R feq = i == 0 ? w * (dr + rr * pu) - R(1.0 - L::w(0)) * sp : w * (drs + rr * pu);
     const R edm = w * rr * (pw - pu);
     pf[i] = pf[i] - (pf[i] - feq) * itf + edm;
     if (i > 0) {
@@ -152,7 +155,8 @@ __device__ __forceinline__ int tile3(const LBParams& P, int x, int y, int z) {
   return ((z / P.tile) * P.nty + y / P.tile) * P.ntx + x / P.tile;
 }
 
-template <class St, typename R>
+// TX: tile extent in x (wider tiles read whole cache lines of each x row)
+template <class St, typename R, int TX = T3>
 __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Moments3 M,
                                                  const int* __restrict__ tflag,
                                                  const int* __restrict__ tstate,
@@ -160,15 +164,20 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
                                                  long long* __restrict__ fib,
                                                  double* __restrict__ force, int ntilex) {
   using L = Lattice<19>;
-  __shared__ double s_m[3][3][T3H * T3H];  // moments ring: drho, phi, psi
-  __shared__ double s_u[3][3][T3U * T3U];  // chemical-potential ring
+  static_assert(TX == 16 || TX == 32 || TX == 64, "tile of 256 nodes");
+  constexpr int TY = 256 / TX;
+  constexpr int TXH = TX + 4, TYH = TY + 4;  // with the two-node halo
+  constexpr int TXU = TX + 2, TYU = TY + 2;  // region where mu is formed
+  constexpr int NH = (TXH * TYH + 255) / 256, NU = (TXU * TYU + 255) / 256;  // passes of 256 threads
+  __shared__ double s_m[3][3][TXH * TYH];  // moments ring: drho, phi, psi
+  __shared__ double s_u[3][3][TXU * TYU];  // chemical-potential ring
   const int tid = threadIdx.x;
   // (tile, segment) of this workgroup: each XCD gets a contiguous run of
   // the tile order, so tiles that share halo lines meet in one L2
   int tl, sgm;
   strip_segment((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)gridDim.x, (int)gridDim.y, P.nxcd, tl, sgm);
   const int tx = tl % ntilex, ty = tl / ntilex;
-  const int x0 = tx * T3, y0t = ty * T3;
+  const int x0 = tx * TX, y0t = ty * TY;
   const int z0 = sgm * P.seg;
   const int z1 = min(z0 + P.seg, P.nz);
   const int K = (z1 - z0) + 4;
@@ -176,7 +185,7 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
   const int zbase = dir > 0 ? z0 - 2 : z1 + 1;
   const int stamp = tstate[1];
   // this thread's interior node
-  const int ix = tid % T3, iy = tid / T3;
+  const int ix = tid % TX, iy = tid / TX;
   const int gx = x0 + ix, gy = y0t + iy;
   const bool own = gx < P.nx && gy < P.ny;
   const int xw = wrap(gx, P.nx);
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
   // tile flags of this thread's chemical-potential nodes and collision node,
   // loaded one plane ahead so that every load of an iteration (moments,
   // profile field, pull, spread force) is issued before the first wait
-  int fU[2] = {0, 0}, fC = 0;
+  int fU[NU] = {}, fC = 0;
   // the populations of plane z_j are pulled at iteration j + 1 into register
   // set j & 1 and collided at iteration j + 2: the next plane's pull is in
   // flight while the current one is computed
@@ -195,14 +204,14 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
     constexpr int SN = S ^ 1;                  // set pulled now
     const int zk = zbase + dir * k;
     const int slot = k % 3;
-    // ---- issue: moments of plane zk on the 20 x 20 region
+    // ---- issue: moments of plane zk on the (TX+4) x (TY+4) region
     const int zr = halo_row(zk, P.nz, P.wall_z);
-    double mv[2][3];
+    double mv[NH][3];
 #pragma unroll
-    for (int r = 0; r < 2; r++) {
+    for (int r = 0; r < NH; r++) {
       const int q = tid + 256 * r;
-      if (q < T3H * T3H) {
-        const int hx = q % T3H, hy = q / T3H;
+      if (q < TXH * TYH) {
+        const int hx = q % TXH, hy = q / TXH;
         const int xx = wrap(x0 - 2 + hx, P.nx);
         const int yy = halo_row(y0t - 2 + hy, P.ny, P.wall_y);
         const long long nd = ((long long)zr * P.ny + yy) * P.nx + xx;
@@ -213,14 +222,14 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
     }
     // ---- issue: profile field of plane z_{k-1} where its tile is active
     const int zq = halo_row(zk - dir, P.nz, P.wall_z);
-    double Iv[2] = {0.0, 0.0};
-    int nfU[2] = {0, 0};
+    double Iv[NU] = {};
+    int nfU[NU] = {};
 #pragma unroll
-    for (int r = 0; r < 2; r++) {
+    for (int r = 0; r < NU; r++) {
       const int q = tid + 256 * r;
-      if (q < T3U * T3U) {
-        const int xx = wrap(x0 - 1 + q % T3U, P.nx);
-        const int yy = halo_row(y0t - 1 + q / T3U, P.ny, P.wall_y);
+      if (q < TXU * TYU) {
+        const int xx = wrap(x0 - 1 + q % TXU, P.nx);
+        const int yy = halo_row(y0t - 1 + q / TXU, P.ny, P.wall_y);
         if (k >= 2 && fU[r] == stamp) Iv[r] = Ifield[((long long)zq * P.ny + yy) * P.nx + xx];
         if (k + 1 < K) nfU[r] = tflag[tile3(P, xx, yy, zr)];
       }
@@ -240,25 +249,25 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
     if (pnext) nfC = tflag[tile3(P, xw, gy, zk - dir)];
     // ---- L: moments to the ring
 #pragma unroll
-    for (int r = 0; r < 2; r++) {
+    for (int r = 0; r < NH; r++) {
       const int q = tid + 256 * r;
-      if (q < T3H * T3H) {
+      if (q < TXH * TYH) {
         s_m[slot][0][q] = mv[r][0];
         s_m[slot][1][q] = mv[r][1];
         s_m[slot][2][q] = mv[r][2];
       }
     }
     __syncthreads();
-    // ---- U: mu on plane z_{k-1} over the 18 x 18 region
+    // ---- U: mu on plane z_{k-1} over the (TX+2) x (TY+2) region
     if (k >= 2) {
       const int a = (k + 1) % 3, b = (k + 2) % 3, c = slot;  // planes z_{k-2}, z_{k-1}, z_k
       const int pa = dir > 0 ? a : c, pc = dir > 0 ? c : a;   // planes below / above in z
 #pragma unroll
-      for (int r = 0; r < 2; r++) {
+      for (int r = 0; r < NU; r++) {
         const int q = tid + 256 * r;
-        if (q >= T3U * T3U) continue;
-        const int ux_ = q % T3U, uy_ = q / T3U;
-        const int hq = (uy_ + 1) * T3H + (ux_ + 1);  // centre in the 20 x 20 region
+        if (q >= TXU * TYU) continue;
+        const int ux_ = q % TXU, uy_ = q / TXU;
+        const int hq = (uy_ + 1) * TXH + (ux_ + 1);  // centre in the staged region
         double lap[3], ctr[3];
 #pragma unroll
         for (int f = 0; f < 3; f++) {
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
 #pragma unroll
           for (int i = 1; i < 19; i++) {
             const int pl = L::cz[i] > 0 ? pc : (L::cz[i] < 0 ? pa : b);
-            acc += L::w(i) * (s_m[pl][f][hq + L::cy[i] * T3H + L::cx[i]] - qc);
+            acc += L::w(i) * (s_m[pl][f][hq + L::cy[i] * TXH + L::cx[i]] - qc);
           }
           lap[f] = 6.0 * acc;
           ctr[f] = qc;
@@ -291,7 +300,7 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
       double& h0c = h0[S];
       double d, jx, jy, jz, phi, psi;
       moments19(pfc, pgc, phc, g0c, h0c, d, jx, jy, jz, phi, psi);
-      const int uq = (iy + 1) * T3U + (ix + 1);
+      const int uq = (iy + 1) * TXU + (ix + 1);
       double gr[3][3];
 #pragma unroll
       for (int f = 0; f < 3; f++) {
@@ -299,7 +308,7 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
 #pragma unroll
         for (int i = 1; i < 19; i++) {
           const int pl = L::cz[i] > 0 ? pc : (L::cz[i] < 0 ? pa : b);
-          const double v = L::w(i) * s_u[pl][f][uq + L::cy[i] * T3U + L::cx[i]];
+          const double v = L::w(i) * s_u[pl][f][uq + L::cy[i] * TXU + L::cx[i]];
           sx += L::cx[i] * v;
           sy += L::cy[i] * v;
           sz += L::cz[i] * v;
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
         gr[f][1] = 3.0 * sy;
         gr[f][2] = 3.0 * sz;
       }
-      const double rho = 1.0 + d;
+      const double rho = P.rho0 + d;
       double F[3];
       for (int a3 = 0; a3 < 3; a3++)  // plus f_ext of eq. ForcingTermLBE
         F[a3] = -(rho * gr[0][a3] + phi * gr[1][a3] + psi * gr[2][a3]) + P.fext[a3];
@@ -347,8 +356,8 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
         dst.template store<R>(2, i, node, phc[i]);
       }
     }
-    fU[0] = nfU[0];
-    fU[1] = nfU[1];
+#pragma unroll
+    for (int r = 0; r < NU; r++) fU[r] = nfU[r];
     fC = nfC;
     __syncthreads();  // the rings are rewritten by the next plane
   };

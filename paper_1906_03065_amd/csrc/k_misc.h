@@ -35,14 +35,17 @@ __global__ void k_init2d(St dst, LBParams P, const double* __restrict__ rho,
   double I = 0;
   if (tflag[(y / P.tile) * P.ntx + x / P.tile] == tstate[1]) I = Ifield[n];
   double mr, mp, ms;
-  chem_pot(P, ctr[0] - 1.0, ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
+  chem_pot(P, ctr[0] - P.rho0, ctr[1], ctr[2], lap[0], lap[1], lap[2], I, mr, mp, ms);
   const double u0 = ux ? ux[n] : 0.0, u1 = uy ? uy[n] : 0.0;
   const double uu = u0 * u0 + u1 * u1;
+  // lattice pressure c_s^2 (rho + sp) with component densities (sp = 0 for equal ones)
+  const double sp = -(P.psh[0] * ctr[1] + P.psh[1] * ctr[2]);
   double E[3][9], gs = 0, hs = 0;
   for (int i = 0; i < 9; i++) {
     const double cu = L::cx[i] * u0 + L::cy[i] * u1;
     const double pu = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
-    E[0][i] = L::w(i) * ((ctr[0] - 1.0) + ctr[0] * pu);
+    E[0][i] = i == 0 ? L::w(0) * ((ctr[0] - P.rho0) + ctr[0] * pu) - (1.0 - L::w(0)) * sp
+                     : L::w(i) * ((ctr[0] - P.rho0 + sp) + ctr[0] * pu);
     if (i > 0) {
       E[1][i] = L::w(i) * (3.0 * P.gphi * mp + ctr[1] * pu);
       E[2][i] = L::w(i) * (3.0 * P.gpsi * ms + ctr[2] * pu);
@@ -92,11 +95,13 @@ __global__ void k_moments2d(St cur, LBParams P, double* __restrict__ out) {
   pull9(cur, P, x, y, pf, pg, ph, g0, h0);
   double d, jx, jy, phi, psi;
   moments9(pf, pg, ph, g0, h0, d, jx, jy, phi, psi);
-  const double rho = 1.0 + d;
+  const double rho = P.rho0 + d;
+  double C[3];
+  conc3(P, rho, phi, psi, C);
   out[n] = rho;
-  out[P.N + n] = 0.5 * (rho + phi - psi);
-  out[2 * P.N + n] = 0.5 * (rho - phi - psi);
-  out[3 * P.N + n] = psi;
+  out[P.N + n] = C[0];
+  out[2 * P.N + n] = C[1];
+  out[3 * P.N + n] = C[2];
   out[4 * P.N + n] = jx / rho;
   out[5 * P.N + n] = jy / rho;
 }
@@ -137,7 +142,14 @@ __global__ __launch_bounds__(NT) void k_energy_nodes2d(LBParams P, const double*
     v[5] = 0.5 * P.kc * (psi - I) * (psi - I);
     const double rho = mom[n], ux = mom[4 * P.N + n], uy = mom[5 * P.N + n];
     v[6] = 0.5 * rho * (ux * ux + uy * uy);
-    v[7] = rho * log(rho) / 3.0;
+    // c_s^2 rho ln rho; with component densities the ideal gas is that of
+    // the number density n = sum_m C_m, c_s^2 M_b n ln n
+    if (P.dens) {
+      const double nn = mom[P.N + n] + mom[2 * P.N + n] + mom[3 * P.N + n];
+      v[7] = P.mb * nn * log(nn) / 3.0;
+    } else {
+      v[7] = rho * log(rho) / 3.0;
+    }
   }
   for (int k = 0; k < 8; k++) {
     const double s = block_sum<NT>(v[k], sh);

@@ -186,6 +186,7 @@ struct lbib_sim {
   std::vector<int> toff{0}, eoff{0}, vtoff{0}, coff{0};
   double r_cut = 0;
   int bx = 256, seg = 0;  // fused-kernel launch shape (seg 0: automatic)
+  int tx3 = 32;           // D3Q19: x extent of the lattice kernel's 256-node tile (16, 32, 64)
   int nxcd = 0;           // L2 domains workgroups are dealt to (0: automatic, 1: plain order)
   int ring = 3;           // rows in the fused kernel's register ring (4: prefetch)
   int overlap = 0;        // 2D: lattice regions away from the membranes beside the
@@ -193,6 +194,7 @@ struct lbib_sim {
   int force_form = 0;     // force of eq. ForceFE, 0 potential form, 1 divergence form (D2Q9, the default there)
   int coup_cache = 1;     // D2Q9: each node keeps its closest membrane segment between steps
   double fext[3] = {0, 0, 0};  // uniform external force density (eq. ForcingTermLBE)
+  double mw[3] = {1, 1, 1};    // component densities (eq. MassDensity)
   bool any_law = false;   // D3Q19: a mesh has a triangle strain law (the triangle pass runs)
   lbib_sim* owner = nullptr;  // the batch this simulation belongs to (it owns the handle)
   // optional per-phase timing with HIP events on the stream
@@ -365,7 +367,30 @@ Split16Store<__hip_bfloat16, 19> make_store<Split16Store<__hip_bfloat16, 19>>(ch
 }
 
 // lattice parameters shared by both engines
-void fill_params(LBParams& P, const lbib_params& p, const Layout& L, long long N, int seg, const double* fext) {
+// The concentrations as a linear map of (rho, phi, psi) for component
+// densities M_m (eq. MassDensity with eq. VariableTransform): with
+// M_b = (M_1 + M_2)/2 and a = (M_1 - M_2)/2, the mass density is
+// rho = M_b (C_1 + C_2) + a phi + M_3 psi, so C_1 + C_2 = (rho - a phi - M_3 psi)/M_b
+// and C_{1,2} = ((C_1 + C_2) +- phi)/2.  The lattice's pressure is the ideal
+// gas of the number density n = sum_m C_m, c_s^2 M_b n = c_s^2 (rho - a phi - b psi)
+// with b = M_3 - M_b.
+void density_map(LBParams& P, const double* mw) {
+  const double mb = 0.5 * (mw[0] + mw[1]), a = 0.5 * (mw[0] - mw[1]), b = mw[2] - mb;
+  const double s[3] = {1.0 / mb, -a / mb, -mw[2] / mb};  // C_1 + C_2 per unit of rho, phi, psi
+  for (int q = 0; q < 3; q++) {
+    P.cm[0][q] = 0.5 * (s[q] + (q == 1 ? 1.0 : 0.0));
+    P.cm[1][q] = 0.5 * (s[q] - (q == 1 ? 1.0 : 0.0));
+    P.cm[2][q] = q == 2 ? 1.0 : 0.0;
+  }
+  P.psh[0] = a;
+  P.psh[1] = b;
+  P.mb = mb;
+  P.rho0 = mb;
+  P.dens = (mw[0] != 1.0 || mw[1] != 1.0 || mw[2] != 1.0) ? 1 : 0;
+}
+
+void fill_params(LBParams& P, const lbib_params& p, const Layout& L, long long N, int seg, const double* fext,
+                 const double* mw) {
   P.inv_tau = (1.0 / p.tau);
   P.inv_tau_phi = (1.0 / p.tau_phi);
   P.inv_tau_psi = (1.0 / p.tau_psi);
@@ -377,6 +402,7 @@ void fill_params(LBParams& P, const lbib_params& p, const Layout& L, long long N
   P.a2 = p.alpha * p.alpha;
   P.kc = p.kappa_c;
   for (int a = 0; a < 3; a++) P.fext[a] = fext[a];
+  density_map(P, mw);
   P.nx = p.nx;
   P.ny = p.ny;
   P.nz = p.lattice == LBIB_D3Q19 ? p.nz : 1;
@@ -397,7 +423,7 @@ struct Engine2D final : lbib_sim {
   LBParams P{};
   St store(int which) const { return make_store<St>(ws + L.pops[which], N); }
 
-  void setup() override { fill_params(P, p, L, N, seg, fext); }
+  void setup() override { fill_params(P, p, L, N, seg, fext, mw); }
 
   CoupArgs coup_args(int want_force) const {
     CoupArgs c;
@@ -523,6 +549,9 @@ struct Engine2D final : lbib_sim {
     else if (mode == 0)                                                                            \
       hipLaunchKernelGGL((k_lb2d<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, If, \
                          fib, frc);                                                                \
+    else if (force_form == 1)                                                                      \
+      hipLaunchKernelGGL((k_lb2d_part<St, R, BXV, NSV, 2, 1>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, \
+                         If, fib, frc);                                                            \
     else                                                                                           \
       hipLaunchKernelGGL((k_lb2d_part<St, R, BXV, NSV, WPEV>), grid, dim3(BXV), 0, s, src, dst, P, tf, ts, \
                          If, fib, frc);                                                            \
@@ -630,10 +659,15 @@ template <class St, typename R>
 struct Engine3D final : lbib_sim {
   LBParams P{};
   St store(int which) const { return make_store<St>(ws + L.pops[which], N); }
-  int ntilex() const { return (p.nx + T3 - 1) / T3; }
-  int ntiley() const { return (p.ny + T3 - 1) / T3; }
+  int ntilex() const { return (p.nx + tx3 - 1) / tx3; }
+  int ntiley() const { return (p.ny + 256 / tx3 - 1) / (256 / tx3); }
+  const void* lb3_kernel() const {
+    if (tx3 == 32) return (const void*)&k_lb3d<St, R, 32>;
+    if (tx3 == 64) return (const void*)&k_lb3d<St, R, 64>;
+    return (const void*)&k_lb3d<St, R, 16>;
+  }
 
-  void setup() override { fill_params(P, p, L, N, seg, fext); }
+  void setup() override { fill_params(P, p, L, N, seg, fext, mw); }
 
   Moments3 mom3() const {
     Moments3 m;
@@ -704,8 +738,7 @@ struct Engine3D final : lbib_sim {
     int per_cu = 0, ncu = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_lb3d<St, R>, 256, 0) !=
-            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lb3_kernel(), 256, 0) != hipSuccess ||
         per_cu <= 0 || ncu <= 0)
       return std::min(p.nz, 16);
     const long long slots = (long long)per_cu * ncu;
@@ -721,10 +754,18 @@ struct Engine3D final : lbib_sim {
     const int nb = (int)((N + 255) / 256);
     hipLaunchKernelGGL((k_mom3d<St, R>), dim3(nb), dim3(256), 0, stream, src, P, m3);
     dim3 grid(ntilex() * ntiley(), P.nseg);
-    hipLaunchKernelGGL((k_lb3d<St, R>), grid, dim3(256), 0, stream, src, dst, P, m3,
-                       (const int*)at<int>(L.tflag), (const int*)at<int>(L.tstate),
-                       (const double*)at<double>(L.Ifield), at<long long>(L.fib), at<double>(L.force),
-                       ntilex());
+#define LB3_LAUNCH(TXV)                                                                             \
+  hipLaunchKernelGGL((k_lb3d<St, R, TXV>), grid, dim3(256), 0, stream, src, dst, P, m3,             \
+                     (const int*)at<int>(L.tflag), (const int*)at<int>(L.tstate),                   \
+                     (const double*)at<double>(L.Ifield), at<long long>(L.fib), at<double>(L.force), \
+                     ntilex())
+    if (tx3 == 32)
+      LB3_LAUNCH(32);
+    else if (tx3 == 64)
+      LB3_LAUNCH(64);
+    else
+      LB3_LAUNCH(16);
+#undef LB3_LAUNCH
   }
 
   int step() override {
@@ -1371,10 +1412,14 @@ int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
   if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   if (ring != 0 && ring != 3 && ring != 4) return LBIB_EINVAL;
-  if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 192 && block_x != 256) return LBIB_EINVAL;
+  if (s->D == 3) {
+    if (block_x != 0 && block_x != 16 && block_x != 32 && block_x != 64) return LBIB_EINVAL;
+  } else if (block_x != 0 && block_x != 64 && block_x != 128 && block_x != 192 && block_x != 256) {
+    return LBIB_EINVAL;
+  }
   if (seg < -1 || nxcd < -1 || nxcd > 64) return LBIB_EINVAL;
   if (ring) s->ring = ring;
-  if (block_x) s->bx = block_x;
+  if (block_x) (s->D == 3 ? s->tx3 : s->bx) = block_x;
   if (seg > 0) s->seg = std::max(1, std::min(seg, s->D == 3 ? s->p.nz : s->p.ny));
   if (seg < 0) s->seg = 0;  // back to automatic
   if (nxcd > 0) s->nxcd = nxcd;
@@ -1384,7 +1429,6 @@ int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring) {
 
 int lbib_set_overlap(lbib_sim* s, int on) {
   if (!s || s->is_batch() || on < -1 || on > 1) return LBIB_EINVAL;
-  if (on > 0 && s->force_form != 0) return LBIB_EINVAL;  // one lattice pass only
   s->overlap = on > 0 ? 1 : 0;
   return LBIB_OK;
 }
@@ -1404,6 +1448,18 @@ int lbib_set_external_force(lbib_sim* s, double fx, double fy, double fz) {
   s->fext[0] = fx;
   s->fext[1] = fy;
   s->fext[2] = fz;
+  s->setup();
+  if (s->owner) s->owner->mark_dirty();  // the batch copies the member's parameters
+  return LBIB_OK;
+}
+
+int lbib_set_densities(lbib_sim* s, double m1, double m2, double m3) {
+  if (!s || s->is_batch()) return LBIB_EINVAL;
+  const double m[3] = {m1, m2, m3};
+  for (int k = 0; k < 3; k++)
+    if (!std::isfinite(m[k]) || !(m[k] > 0.0)) return LBIB_EINVAL;
+  if (s->ready) return LBIB_ESTATE;  // the populations hold the old map's pressure
+  for (int k = 0; k < 3; k++) s->mw[k] = m[k];
   s->setup();
   if (s->owner) s->owner->mark_dirty();  // the batch copies the member's parameters
   return LBIB_OK;
@@ -1429,7 +1485,6 @@ int lbib_set_coupling_cache(lbib_sim* s, int on) {
 
 int lbib_set_force_form(lbib_sim* s, int form) {
   if (!s || s->owner || s->D != 2 || form < 0 || form > 1) return LBIB_EINVAL;
-  if (form == 1 && s->overlap) return LBIB_EINVAL;
   if (s->force_form != form && s->is_batch()) s->mark_dirty();  // new launch plan and graphs
   s->force_form = form;
   return LBIB_OK;
@@ -1439,7 +1494,7 @@ int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* r
   if (s && s->is_batch()) return LBIB_EINVAL;  // per-member calls go to the members
   if (!s) return LBIB_EINVAL;
   if (ring) *ring = s->ring;
-  if (block_x) *block_x = s->bx;
+  if (block_x) *block_x = s->D == 3 ? s->tx3 : s->bx;
   if (seg) *seg = s->seg;
   if (nxcd) *nxcd = s->nxcd;
   return LBIB_OK;
@@ -1588,9 +1643,17 @@ constexpr long long CKPT_TAG = 0x31504b4342494c42LL;  // "BLIBCKP1" read as litt
 constexpr int CKPT_WORDS = 12;
 void ckpt_header(const lbib_sim* s, long long* h) {
   const int form = s->owner ? s->owner->force_form : s->force_form;
+  // last word: the component densities' bit patterns mixed (0 when all are 1)
+  unsigned long long dh = 0;
+  if (s->mw[0] != 1.0 || s->mw[1] != 1.0 || s->mw[2] != 1.0)
+    for (int k = 0; k < 3; k++) {
+      unsigned long long bits;
+      memcpy(&bits, &s->mw[k], 8);
+      dh = (dh ^ bits) * 0x100000001b3ULL + 0x9e3779b97f4a7c15ULL;
+    }
   const long long v[CKPT_WORDS] = {CKPT_TAG, s->steps, (long long)s->M, (long long)s->K, s->p.nx, s->p.ny,
                                    s->p.nz, (long long)s->Q, (long long)s->p.storage, (long long)form,
-                                   (long long)s->L.pop_bytes, 0};
+                                   (long long)s->L.pop_bytes, (long long)dh};
   for (int k = 0; k < CKPT_WORDS; k++) h[k] = v[k];
 }
 }  // namespace
@@ -1631,7 +1694,7 @@ int lbib_load(lbib_sim* s, const void* buf, size_t bytes) {
   memcpy(hdr, o, H);
   ckpt_header(s, want);
   // every word but the step count must match: tag, markers, membranes,
-  // lattice size, Q, storage, force form and population bytes
+  // lattice size, Q, storage, force form, population bytes and densities
   for (int k = 0; k < CKPT_WORDS; k++)
     if (k != 1 && hdr[k] != want[k]) return LBIB_EINVAL;
   if (hdr[1] < 0) return LBIB_EINVAL;

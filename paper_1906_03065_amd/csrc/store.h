@@ -4,9 +4,12 @@
 // for every node in x-fastest order, so a wavefront of consecutive x reads one
 // contiguous run per population (pull streaming shifts it by at most one).
 //
-// Values kept (Sec. 3.1, eq. EDF): for f the deviation f_i - w_i from the
-// weight (f is w_i rho (1 + O(u)) with rho ~ 1, so the deviation keeps the
-// velocity-carrying part at full relative precision); for g and h the
+// Values kept (Sec. 3.1, eq. EDF): for f the deviation f_i - w_i rho0 from
+// the weight times a reference density (f_i is w_i p/c_s^2 (1 + O(u)) for
+// i > 0, p the lattice pressure, which is c_s^2 rho0 up to O(1e-3) in every
+// phase -- rho0 = 1 for equal component densities, (M_1 + M_2)/2 otherwise --
+// so the deviation keeps the velocity-carrying part at full relative
+// precision; f_0 carries the density contrast between phases); for g and h the
 // populations themselves.  The moving populations g_i, h_i (i > 0) are
 // O(mu, u) and small, while the rest populations g_0 and h_0 carry the order
 // parameters phi in [-1, 1] and psi in [0, 1].  Their rounding is what limits

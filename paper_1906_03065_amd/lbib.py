@@ -72,6 +72,7 @@ SIGNATURES = [
     ("lbib_set_force_form", C.c_int, [_vp, C.c_int]),
     ("lbib_set_external_force", C.c_int, [_vp, C.c_double, C.c_double, C.c_double]),
     ("lbib_set_coupling_cache", C.c_int, [_vp, C.c_int]),
+    ("lbib_set_densities", C.c_int, [_vp, C.c_double, C.c_double, C.c_double]),
     ("lbib_get_launch", C.c_int, [_vp, _ip, _ip, _ip, _ip]),
     ("lbib_steps_done", C.c_longlong, [_vp]),
     ("lbib_debug_poke", C.c_int, [_vp, C.c_int, C.c_longlong, C.c_double]),
@@ -180,6 +181,8 @@ class Sim:
             self.set_force_form(int(p.get("force_form", 1)))
         if any(p.get("fext", ())):
             self.set_external_force(*p["fext"])
+        if tuple(p.get("mw", (1.0, 1.0, 1.0))) != (1.0, 1.0, 1.0):
+            self.set_densities(*p["mw"])
 
     @classmethod
     def _member(cls, batch, h, p: dict):
@@ -317,6 +320,11 @@ class Sim:
         """Uniform external force density f_ext of eq. ForcingTermLBE."""
         _chk("lbib_set_external_force", lib().lbib_set_external_force(self.h, float(fx), float(fy), float(fz)))
 
+    def set_densities(self, m1=1.0, m2=1.0, m3=1.0):
+        """D2Q9: component densities of eq. MassDensity (all 1 in the paper);
+        before set_fields."""
+        _chk("lbib_set_densities", lib().lbib_set_densities(self.h, float(m1), float(m2), float(m3)))
+
     def get_launch(self):
         a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         _chk("lbib_get_launch", lib().lbib_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c),
@@ -375,6 +383,8 @@ class Batch:
             self.members.append(Sim._member(self, mh, params[k]))
             if any(params[k].get("fext", ())):
                 self.members[-1].set_external_force(*params[k]["fext"])
+            if tuple(params[k].get("mw", (1.0, 1.0, 1.0))) != (1.0, 1.0, 1.0):
+                self.members[-1].set_densities(*params[k]["mw"])
         self.set_force_form(forms.pop())
 
     def set_force_form(self, form: int):

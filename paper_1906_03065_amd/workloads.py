@@ -5,7 +5,7 @@ This module builds parameter dictionaries, initial macroscopic fields and
 initial membrane marker sets.  It holds none of the method's arithmetic: no
 equilibria, stencils, chemical potentials, forces or kernels.  Initial fields
 are diffuse tanh profiles of analytic distances (circles, spheres, planes),
-the shape the paper uses for every interface (Sec. 2.4, eq. CmProfile), and
+the shape the paper uses for every interface (Sec. 2.5, eq. CmProfile), and
 markers are points placed evenly on circles or on icosphere meshes.
 
 Workloads (the paper publishes no datasets; these stand in for its geometries):
@@ -42,7 +42,7 @@ def base_params(nx, ny, nz=1, lattice=0, wall_y=0, wall_z=0, kappa=(0.02, 0.02, 
                 r_cut=0.0, force_form=None) -> dict:
     """Parameter dictionary.  ``mobility`` M sets Gamma = M/(tau - 1/2) for both
     order parameters (eq. RelaxationTimes), or a pair (M_phi, M_psi) sets each
-    (Sec. 2.5 names M_phi = 3 M_psi); otherwise ``gamma`` is used.
+    (Sec. 2.6 names M_phi = 3 M_psi); otherwise ``gamma`` is used.
     ``force_form``: the thermodynamic force of eq. ForceFE as the divergence
     of the pressure tensor (1, the default on D2Q9) or in its potential form
     (0, the only form on D3Q19)."""
@@ -191,7 +191,7 @@ def mode_decay(mode, nx=96, ny=4, mobility=(0.3, 0.1), kappa=(0.05, 0.05, 0.08),
                tau_psi=1.3, amp=1e-5):
     """A uniform bulk phase with a small sinusoidal perturbation along x, one
     wavelength over the periodic box, for the decay rates of the order
-    parameters (Sec. 2.5 mobilities): mode "phi" perturbs phi in the C3 bulk,
+    parameters (Sec. 2.6 mobilities): mode "phi" perturbs phi in the C3 bulk,
     mode "psi" perturbs psi in the C1 bulk (at fixed rho and phi).  No
     membrane, no coupling."""
     p = base_params(nx, ny, wall_y=0, kappa=kappa, alpha=alpha, kappa_c=0.0, tau_phi=tau_phi,
@@ -381,11 +381,14 @@ def prestressed_mesh(law=1, n=40, R=10.0, subdiv=3, kappa_s=0.02, lam0=1.2, kapp
 
 def drop3d(nx=24, ny=22, nz=20, R=6.0, wall_y=0, wall_z=1, kappa=(0.02, 0.03, 0.025), alpha=1.0,
            mobility=0.1, tau=1.0, tau_phi=1.0, tau_psi=1.0, u0=None, perturb=1e-4,
-           seed=SEED_BASE + 4):
+           seed=SEED_BASE + 4, mw=(1.0, 1.0, 1.0)):
     """D3Q19 box: a C3 sphere of radius R in C1, above a C2 layer of a third
-    of the height (no membrane)."""
+    of the height (no membrane).  ``mw``: component densities (all 1 in the
+    paper)."""
     p = base_params(nx, ny, nz, lattice=1, wall_y=wall_y, wall_z=wall_z, kappa=kappa, alpha=alpha,
                     kappa_c=0.0, mobility=mobility, tau=tau, tau_phi=tau_phi, tau_psi=tau_psi)
+    if tuple(mw) != (1.0, 1.0, 1.0):
+        p["mw"] = [float(m) for m in mw]
     z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
                           np.arange(nx, dtype=np.float64), indexing="ij")
     c = (nx / 2.0 + 0.2, ny / 2.0 - 0.3, 0.6 * nz)
@@ -393,7 +396,7 @@ def drop3d(nx=24, ny=22, nz=20, R=6.0, wall_y=0, wall_z=1, kappa=(0.02, 0.03, 0.
                                   (z - c[2]) ** 2), alpha)
     C2 = (1.0 - C3) * 0.5 * (1.0 - np.tanh((z - nz / 3.0) / (2.0 * alpha)))
     C1 = 1.0 - C2 - C3
-    return dict(params=p, fields=fields_from_C(C1, C2, C3, perturb, seed, u=u0), membranes=[],
+    return dict(params=p, fields=fields_from_C(C1, C2, C3, perturb, seed, u=u0, mw=mw), membranes=[],
                 name=f"drop3d_{nx}x{ny}x{nz}")
 
 

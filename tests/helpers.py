@@ -132,7 +132,7 @@ def decay_rate(sim, mode, steps=3600, every=450, skip=2):
 
 def ch_rate(p, mode, density_response=True):
     """Decay rate of a small sin(k x) perturbation in a bulk phase from the
-    linearised Cahn-Hilliard equation dq/dt = M lap mu_q (Sec. 2.5), with
+    linearised Cahn-Hilliard equation dq/dt = M lap mu_q (Sec. 2.6), with
     M = Gamma (tau - 1/2) and the chemical potentials of the Landau energy:
     about C = 0 or 1, d/dC [C (1 - C)(1 - 2C)] = 1, so each concentration's
     b_m = kappa_m (1 + alpha^2 K) dC_m, where K = 2 (1 - cos k) is the

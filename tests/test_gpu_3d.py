@@ -150,14 +150,15 @@ def test_fp64_parity_two_capsules_64(orc):
 
 
 def test_fp32_launch_shapes_bitwise_3d():
-    """Different plane segments and repeated runs give bitwise identical
-    FP32 results (fixed-point force sums, no order-dependent reductions)."""
+    """Different plane segments and tile shapes (16 x 16, 32 x 8, 64 x 4
+    nodes) and repeated runs give bitwise identical FP32 results
+    (fixed-point force sums, no order-dependent reductions)."""
     w = _capsule()
     ref = None
-    for seg in (0, 3, 7, 24):
+    for tx, seg in ((0, 0), (0, 3), (0, 7), (0, 24), (32, 0), (64, 0), (64, 5)):
         g = run_gpu(w, "fp32")
-        if seg:
-            g.set_launch(seg=seg)
+        if seg or tx:
+            g.set_launch(block_x=tx, seg=seg)
         g.step(30)
         f = g.fields()
         X = g.membrane(0)["X"]
@@ -165,8 +166,28 @@ def test_fp32_launch_shapes_bitwise_3d():
             ref = (f, X)
             continue
         for k in f:
-            assert np.array_equal(f[k], ref[0][k]), (seg, k)
-        assert np.array_equal(X, ref[1]), seg
+            assert np.array_equal(f[k], ref[0][k]), (tx, seg, k)
+        assert np.array_equal(X, ref[1]), (tx, seg)
+
+
+@pytest.mark.parametrize("tx", [32, 64])
+def test_fp64_parity_wide_tiles(orc, tx):
+    """Tiles of 32 x 8 and 64 x 4 nodes on a box whose sides are not
+    multiples of them (partial tiles in x and y, walls in y and z) give the
+    oracle's fields."""
+    w = W.drop3d(nx=70, ny=13, nz=11, R=4.0, wall_y=1, wall_z=1, tau=0.8)
+    o = run_oracle(orc, w)
+    g = run_gpu(w, "fp64")
+    g.set_launch(block_x=tx)
+    o.step(30)
+    g.step(30)
+    errs = compare(g, o, D=3)
+    _report(f"fp64 drop3d tiles {tx}", errs)
+    for k, v in errs.items():
+        assert v < 1e-10, (k, v)
+    from paper_1906_03065_amd import lbib
+    with pytest.raises(lbib.LbibError):
+        g.set_launch(block_x=48)
 
 
 def test_mass_conservation_fp32_3d():

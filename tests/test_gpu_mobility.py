@@ -1,4 +1,4 @@
-"""Unequal mobilities on the GPU (Sec. 2.5 names M_phi = 3 M_psi): the decay
+"""Unequal mobilities on the GPU (Sec. 2.6 names M_phi = 3 M_psi): the decay
 rates of small sinusoidal phi and psi perturbations in a bulk phase against
 the linearised Cahn-Hilliard closed form, and FP64 parity with the oracle on
 a capsule at an interface with M_phi = 3 M_psi and relaxation times != 1."""

@@ -56,13 +56,22 @@ def test_equilibrium_deformation_against_sharp_interface():
 
 def test_galilean_invariance_moving_frames():
     """Sec. 4.1: the capsule of the highest symmetric and asymmetric tension
-    ratios (kappa_s = 1e-3, kappa_b = 1e-2) in frames moving at U = 1e-4 and
-    1e-3 keeps the stationary run's shape (after removing its translation)
-    and Taylor deformation at 60 000 steps, and travels with the fluid.  With
-    the coupling switched off the fluid's mean velocity is conserved exactly
-    in the divergence form; with it on, the discrete coupling forces on the
-    fluid and on the membrane do not cancel exactly (a slow drag, reported)."""
-    Us = (0.0, 1e-4, 1e-3)
+    ratios (kappa_s = 1e-3, kappa_b = 1e-2) in frames moving at U = 1e-4,
+    1e-3 and 1e-2 keeps the stationary run's shape (after removing its
+    translation) and Taylor deformation at 60 000 steps, and travels with
+    the fluid.  With the coupling switched off the fluid's mean velocity is
+    conserved exactly in the divergence form; with it on, the discrete
+    coupling forces on the fluid and on the membrane do not cancel exactly
+    (a slow drag, reported).  The capsule then lags the fluid by a few per
+    cent of U, and at U = 1e-2 that slip is a flow past the capsule of
+    capillary number eta dU / gamma_13 ~ 0.02, which deforms it by a few
+    per cent: the paper's superposition holds here at 1e-4 and 1e-3 (D to
+    0.5 %), not at 1e-2, where D is 5 % (symmetric) and 10 % (asymmetric)
+    above the stationary value and the shape is off by 0.05 R and 0.13 R.
+    The bars at 1e-2 bound that deviation; they do not claim the paper's
+    result."""
+    Us = (0.0, 1e-4, 1e-3, 1e-2)
+    nU = len(Us)
     sets = [(True, 5e-4), (False, 5e-4)]
     ws = [W.taylor2d(k3, 1e-3, 1e-2, symmetric=sym, u0=(U or None)) for sym, k3 in sets for U in Us]
     ws += [W.taylor2d(5e-4, 1e-3, 1e-2, symmetric=True, u0=1e-2, kappa_c=0.0),
@@ -76,21 +85,25 @@ def test_galilean_invariance_moving_frames():
     assert b.check() == 0
     X = b.markers()
     for si, (sym, _) in enumerate(sets):
-        ref = X[3 * si][0]
+        ref = X[nU * si][0]
         D0 = T.taylor_deformation(ref)
         for ui, U in enumerate(Us[1:], start=1):
-            Xk = X[3 * si + ui][0]
+            Xk = X[nU * si + ui][0]
             dshape = np.abs((Xk - Xk.mean(0)) - (ref - ref.mean(0))).max()
             v = (Xk.mean(0)[0] - ref.mean(0)[0]) / 60000
             D = T.taylor_deformation(Xk)
             print(f"sym={sym} U={U:g}: shape {dshape:.3e} D {D:.4f} (stationary {D0:.4f}) speed/U {v / U:.4f}",
                   flush=True)
-            assert abs(D / D0 - 1) < 5e-3
-            assert dshape < (0.01 if sym else 0.03) * 20.0
+            if U < 5e-3:
+                assert abs(D / D0 - 1) < 5e-3
+                assert dshape < (0.01 if sym else 0.03) * 20.0
+            else:
+                assert abs(D / D0 - 1) < 0.12
+                assert dshape < 0.15 * 20.0
             assert abs(v / U - 1) < 0.06
-    for k, U in ((6, 1e-2), (7, 1e-3)):
+    for k, U in ((2 * nU, 1e-2), (2 * nU + 1, 1e-3)):
         f = b[k].fields()
         P = float((f["rho"] * f["ux"]).sum() / f["rho"].sum())
-        print(f"kappa_c {'0' if k == 6 else '1e-2'}: mean fluid velocity / U = {P / U:.5f}", flush=True)
-        if k == 6:
+        print(f"kappa_c {'0' if k == 2 * nU else '1e-2'}: mean fluid velocity / U = {P / U:.5f}", flush=True)
+        if k == 2 * nU:
             assert abs(P / U - 1) < 2e-3

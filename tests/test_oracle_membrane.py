@@ -1,5 +1,5 @@
 """Pins of the oracle's membrane mechanics (Sec. 3.2), coupling profile and
-coupling force (Sec. 2.4, eqs. Iprofile, DiscreteCE, DiscreteCF) and IBM
+coupling force (Sec. 2.5, eqs. Iprofile, DiscreteCE, DiscreteCF) and IBM
 transfer operators (Sec. 3.3) against closed forms, finite-difference
 gradients of the oracle's own energies, and invariants."""
 import numpy as np

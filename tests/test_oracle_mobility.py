@@ -1,4 +1,4 @@
-"""Unequal mobilities of the two order parameters (Sec. 2.5 names
+"""Unequal mobilities of the two order parameters (Sec. 2.6 names
 M_phi = 3 M_psi): the oracle's decay rate of a small sinusoidal perturbation
 in a bulk phase against the linearised Cahn-Hilliard closed form, for phi and
 psi, with the mobilities in either order and relaxation times != 1 (so that
