@@ -21,6 +21,11 @@ namespace lb {
 constexpr int TILE3 = 8;
 constexpr int COUP3_THREADS = 512;  // one thread per node of an 8^3 tile
 constexpr int COUP3_KEEP = 2;
+// the coupling forces of a tile's band nodes are summed per marker in an LDS
+// hash table of this many markers (open addressing) before one global
+// atomic per marker and component; a marker that finds the table full adds
+// straight to global memory
+constexpr int COUP3_HASH = 512;
 
 struct MeshDev {
   int* tri;       // 3 per triangle, marker ids
@@ -451,6 +456,8 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
   __shared__ float s_redf[NT / 64];
   __shared__ int b_tri[COUP3_KEEP][NT];
   __shared__ double b_sd[COUP3_KEEP][NT];
+  __shared__ int s_hv[COUP3_HASH];                 // marker id of each hash slot, -1 free
+  __shared__ long long s_ha[COUP3_HASH][3];        // its fixed-point force sums
   __shared__ int s_li;
   const int ntl = tm.tstate[0];
   const double reach = ca.r_cut + 1.0;
@@ -811,6 +818,12 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
           psi += (double)cur.template load<R>(2, dir, sn);
         }
       }
+      // an empty hash table (the previous tile flushed it before its last barrier)
+      for (int i = lt; i < COUP3_HASH; i += NT) {
+        s_hv[i] = -1;
+        s_ha[i][0] = s_ha[i][1] = s_ha[i][2] = 0;
+      }
+      __syncthreads();
       int slot = 0;
       for (int m = 0; wband && m < md.K && slot < COUP3_KEEP; m++) {
         const TileGeo g = tile_geo(md.mbox + 8 * m, ct, xi, t0, dims, per, hd, reach, valid);
@@ -831,11 +844,37 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
         const double ch = cosh(sd / (2.0 * ca.alpha));
         const double wgt = ca.kappa_c / (4.0 * ca.alpha) * (psi - Itot) / (ch * ch);
         for (int k = 0; k < 3; k++) {
-          long long* A = md.Facc + 3 * tv[k];
-          for (int a = 0; a < 3; a++) {
-            const double gk = -sg * (g.pp[a] - Qp[a]) / d * wgt * w[k];
-            atomicAdd((unsigned long long*)&A[a], (unsigned long long)to_fix(gk));
+          const int v = tv[k];
+          long long fx[3];
+          for (int a = 0; a < 3; a++) fx[a] = to_fix(-sg * (g.pp[a] - Qp[a]) / d * wgt * w[k]);
+          // slot of marker v: linear probing from its hash
+          int h = (int)(((unsigned)v * 2654435761u) >> 23) & (COUP3_HASH - 1);
+          int found = -1;
+          for (int probe = 0; probe < COUP3_HASH; probe++) {
+            const int prev = atomicCAS(&s_hv[h], -1, v);
+            if (prev == -1 || prev == v) {
+              found = h;
+              break;
+            }
+            h = (h + 1) & (COUP3_HASH - 1);
           }
+          if (found >= 0) {
+            for (int a = 0; a < 3; a++) atomicAdd((unsigned long long*)&s_ha[found][a], (unsigned long long)fx[a]);
+          } else {
+            long long* A = md.Facc + 3 * v;
+            for (int a = 0; a < 3; a++) atomicAdd((unsigned long long*)&A[a], (unsigned long long)fx[a]);
+          }
+        }
+      }
+      __syncthreads();
+      // one global atomic per marker and component (integer sums: the same
+      // totals in any order)
+      for (int i = lt; i < COUP3_HASH; i += NT) {
+        const int v = s_hv[i];
+        if (v >= 0) {
+          long long* A = md.Facc + 3 * v;
+          for (int a = 0; a < 3; a++)
+            if (s_ha[i][a] != 0) atomicAdd((unsigned long long*)&A[a], (unsigned long long)s_ha[i][a]);
         }
       }
     }
