@@ -204,8 +204,8 @@ int lbib_timing_read(lbib_sim* s, double* ms, int n, int* steps);
    to load the next row while the current ones are computed).  0 keeps the
    current value; seg = -1 returns to the automatic choice (as many
    workgroups as fit on the GPU at once, so none waits for a second round),
-   nxcd = -1 to the automatic dealing (one domain for D2Q9, eight for the
-   D3Q19 tiles, whose halo lines are then shared inside one L2).  A value
+   nxcd = -1 to the automatic dealing (eight domains, the XCDs of the
+   MI355X, so that workgroups sharing halo rows or lines meet in one L2).  A value
    reported as 0 means automatic.  Invalid values change nothing. */
 int lbib_set_launch(lbib_sim* s, int block_x, int seg, int nxcd, int ring);
 int lbib_get_launch(const lbib_sim* s, int* block_x, int* seg, int* nxcd, int* ring);
@@ -242,15 +242,18 @@ int lbib_set_overlap(lbib_sim* s, int on);
    D3Q19 simulations and batch members. */
 int lbib_set_force_form(lbib_sim* s, int form);
 
-/* D2Q9 coupling-profile search (a scheduling knob; results are bitwise the
-   same either way).  on = 1 (the default): every node keeps, for up to two
-   membranes near it, the closest membrane segment found by the last full
-   search and a lower bound on the distance of all other segments; while the
-   markers have not moved enough to break that bound (the library tracks the
-   largest marker step of each membrane), the next step re-evaluates only
-   that segment and its two neighbours, exactly, instead of searching.
-   on = 0 searches every step.  On a batch handle it applies to every
-   member.  LBIB_EINVAL for other values or D3Q19 simulations. */
+/* Coupling-profile search (a scheduling knob; results are bitwise the same
+   either way).  on = 1 (the default): every node keeps, for up to two
+   membranes near it, the closest membrane element found by the last full
+   search (D2Q9: a ring segment; D3Q19: a triangle) and a lower bound on the
+   distance of the elements farther off (D2Q9: more than eight segments
+   along the ring; D3Q19: sharing no vertex with it), or, beyond the band,
+   its side and a lower bound on its distance.  While the markers have not
+   moved enough to break that bound (the library tracks the largest marker
+   step of each membrane), the next step re-evaluates only the nearby
+   elements, exactly, instead of searching.  on = 0 searches every step.  On
+   a batch handle it applies to every member.  LBIB_EINVAL for other
+   values. */
 int lbib_set_coupling_cache(lbib_sim* s, int on);
 
 /* Uniform external force density f_ext of eq. ForcingTermLBE (Sec. 3.1),

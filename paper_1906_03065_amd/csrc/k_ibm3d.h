@@ -26,6 +26,18 @@ constexpr int COUP3_KEEP = 2;
 // atomic per marker and component; a marker that finds the table full adds
 // straight to global memory
 constexpr int COUP3_HASH = 512;
+// Temporal coherence (as in 2D): each node keeps, for up to COUP3_CACHE
+// membranes of its tile, either its closest triangle t with a lower bound
+// on the distance of every triangle that shares no vertex with t, or (beyond
+// the band) its side and a lower bound on its distance.  With the cache on
+// the candidate lists reach COUP3_PAD farther and a tile or sub-tile is
+// taken to lie beyond the band without a node search only COUP3_BEYOND
+// farther out, so that entries outlast some drift of the markers.
+constexpr int COUP3_CACHE = 2;
+constexpr float COUP3_PAD = 2.0f;
+constexpr float COUP3_BEYOND = 1.0f;
+constexpr int C3_KEYB = 20;         // key = membrane << 20 | triangle (or a beyond code)
+constexpr int C3_IN = 0xFFFFE, C3_OUT = 0xFFFFD;
 
 struct MeshDev {
   int* tri;       // 3 per triangle, marker ids
@@ -167,6 +179,11 @@ struct Coup3Args {
   int nx, ny, nz, wall_y, wall_z;
   double alpha, kappa_c, r_cut;
   int want_force;
+  // per node and cached membrane slot (COUP3_CACHE x N): key and bound (plus
+  // the membrane's drift when written); null disables the cache
+  int* ckey;
+  float* clb;
+  long long N;
 };
 
 __device__ __forceinline__ double near_img(double v, double c, int n, int per) {
@@ -485,6 +502,7 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
     const int t0[3] = {tx * TILE3, ty * TILE3, tz * TILE3};
     const int xi[3] = {t0[0] + off[0], t0[1] + off[1], t0[2] + off[2]};
     const bool valid = xi[0] < ca.nx && xi[1] < ca.ny && xi[2] < ca.nz;
+    const long long nodeid = valid ? ((long long)xi[2] * ca.ny + xi[1]) * ca.nx + xi[0] : 0;
     const double ct[3] = {t0[0] + 0.5 * (TILE3 - 1), t0[1] + 0.5 * (TILE3 - 1), t0[2] + 0.5 * (TILE3 - 1)};
     double Itot = 0.0;
     int kept = 0;
@@ -497,7 +515,55 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
       double d2b = 1e300;
       int tb = -1;
       bool decided = false;  // I of this node already added (no band data)
-      if (g.split) {
+      // cache: a node's entry holds while the nearest triangle of the one-ring
+      // of its kept triangle (FP64, lowest index on ties) is nearer than the
+      // bound less the drift since, or, beyond the band, while the bound less
+      // the drift exceeds r_cut.  A tile skips the search when every node holds.
+      const bool cslot = ca.ckey != nullptr && slot < COUP3_CACHE && !g.split && m < 2048;  // uniform
+      const long long cix = (long long)slot * ca.N + nodeid;
+      const double drift = md.mbox[8 * m + 7];
+      bool cached = false;
+      if (cslot) {
+        bool ok = true;
+        int side = -1;
+        if (valid && g.inbox) {
+          const int key = ca.ckey[cix];
+          ok = key >= 0 && (key >> C3_KEYB) == m;
+          if (ok) {
+            const double thr = (double)ca.clb[cix] - drift;
+            const int q = key & ((1 << C3_KEYB) - 1);
+            if (q >= C3_OUT) {
+              ok = thr > ca.r_cut;
+              side = q == C3_IN ? 1 : 0;
+            } else {
+              const int* tv = mh.tri + 3 * (t0m + q);
+              for (int k = 0; k < 3; k++) {
+                const int v = tv[k];
+                for (int e = mh.vtoff[v]; e < mh.vtoff[v + 1]; e++) {
+                  const int tq = mh.vt[e];
+                  double w[3];
+                  argmin_merge(d2b, tb, tri_d2_id(md, mh, tq, g.pp, w), tq - t0m);
+                }
+              }
+              ok = sqrt(d2b) < thr;
+            }
+          }
+        }
+        cached = __syncthreads_and(ok) != 0;
+        if (!cached) {
+          d2b = 1e300;
+          tb = -1;
+        } else if (side >= 0) {
+          Itot += side ? 1.0 : 0.0;
+          decided = true;
+        }
+      }
+      // entry written after a search (-1: none)
+      int keyw = -1;
+      double lbw = 0.0;
+      if (cached) {
+        // nothing to search
+      } else if (g.split) {
         // nodes of different images: each searches the whole mesh in FP64
         if (g.inbox)
           for (int q = 0; q < nt; q++) {
@@ -525,7 +591,7 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
           if (q < nt) dl = fminf(dl, tri_d2f_vtx(pcr[0], pcr[1], pcr[2], tab[4 * q], tab[4 * q + 1], tab[4 * q + 2]));
         }
         const float dminf = sqrtf(block_minf<NT>(dl, s_redf));
-        if ((double)dminf > ca.r_cut + rn8 + 0.02) {
+        if ((double)dminf > ca.r_cut + rn8 + 0.02 + (cslot ? COUP3_BEYOND : 0.0f)) {
           // the whole tile is beyond r_cut: every node is on the side of the
           // tile centre, taken at the centre's closest triangle
           const float tl = dminf * dminf + 0.05f + 1e-4f * dminf * dminf;
@@ -546,14 +612,20 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
           if (ic >= 0) {  // always: the FP32 minimum itself is within tl
             double w[3];
             tri_d2_id(md, mh, t0m + ic, g.pc, w);
-            if (g.inbox && mesh_side(md, mh, t0m + ic, w, g.pc, o)) Itot += 1.0;
+            const bool in = mesh_side(md, mh, t0m + ic, w, g.pc, o);
+            if (g.inbox && in) Itot += 1.0;
+            if (cslot && valid && g.inbox) {
+              // every node is at least dmin - rn8 from the mesh, on the centre's side
+              keyw = (m << C3_KEYB) | (in ? C3_IN : C3_OUT);
+              lbw = (double)dminf - rn8 - 0.02 - 1e-4 * (double)dminf;
+            }
           }
           decided = true;
         } else {
           // tile candidates: every node's closest triangle lies within
           // dmin + 2 rn8 of the tile centre.  Their ids go to LDS; their
           // geometry is staged C3_LIST at a time.
-          const float cull = dminf + (float)(2.0 * rn8) + 0.02f;
+          const float cull = dminf + (float)(2.0 * rn8) + 0.02f + (cslot ? COUP3_PAD : 0.0f);
           if (lt == 0) s_cnt = 0;
           __syncthreads();
           for (int k = wv; k < ncl; k += NT / 64) {
@@ -633,11 +705,11 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
             dw = wave_minf(dw);
             const float dwr = sqrtf(dw);
             // the whole sub-tile beyond r_cut: the side of its centre
-            const bool wfar = (double)dwr > ca.r_cut + rn4 + 0.01;  // uniform over the wave
+            const bool wfar = (double)dwr > ca.r_cut + rn4 + 0.01 + (cslot ? COUP3_BEYOND : 0.0f);  // uniform over the wave
             const double pw[3] = {g.pc[0] + cwf[0], g.pc[1] + cwf[1], g.pc[2] + cwf[2]};
             const float tlw = dw + 0.05f + 1e-4f * dw;
             const float tlwr = sqrtf(tlw) + mg;
-            const float cwr = dwr + (float)(2.0 * rn4) + mg;
+            const float cwr = dwr + (float)(2.0 * rn4) + mg + (cslot ? COUP3_PAD : 0.0f);
             const float pn[3] = {(float)(g.pp[0] - g.pc[0]), (float)(g.pp[1] - g.pc[1]), (float)(g.pp[2] - g.pc[2])};
             // the sub-tile's share of chunk c (bounding spheres within reach),
             // compacted with ballots
@@ -706,7 +778,12 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
               if (ic >= 0) {  // always: the FP32 minimum itself is within tlw
                 double w[3];
                 tri_d2_id(md, mh, t0m + ic, pw, w);
-                if (g.inbox && mesh_side(md, mh, t0m + ic, w, pw, o)) Itot += 1.0;
+                const bool in = mesh_side(md, mh, t0m + ic, w, pw, o);
+                if (g.inbox && in) Itot += 1.0;
+                if (cslot && valid && g.inbox) {
+                  keyw = (m << C3_KEYB) | (in ? C3_IN : C3_OUT);
+                  lbw = (double)dwr - rn4 - 0.01 - 1e-4 * (double)dwr;
+                }
               }
               decided = true;
             }
@@ -773,8 +850,45 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
                   }
               }
             }
+            if (cslot && !wfar && nch == 1 && valid && g.inbox && tb >= 0) {
+              const double d = sqrt(d2b);
+              if (d > ca.r_cut + COUP3_BEYOND) {
+                // well beyond the band: keep the side and the distance
+                double w[3];
+                tri_d2_id(md, mh, t0m + tb, g.pp, w);
+                keyw = (m << C3_KEYB) | (mesh_side(md, mh, t0m + tb, w, g.pp, o) ? C3_IN : C3_OUT);
+                lbw = d;
+              } else {
+                // triangles off the sub-tile's list lie farther than cwr from
+                // its centre and those off the tile's list farther than cull
+                // from the tile centre; listed ones that share no vertex with
+                // tb are bounded by their FP32 distance less its rounding
+                const int* tv = mh.tri + 3 * (t0m + tb);
+                const int v0 = tv[0], v1 = tv[1], v2 = tv[2];
+                float o2 = 3.0e38f;
+                for (int k = 0; k < cnt; k++) {
+                  const int j = s_wl[wv][k];
+                  const int* uv = mh.tri + 3 * (t0m + s_id[j]);
+                  bool adj = false;
+#pragma unroll
+                  for (int a = 0; a < 3; a++) adj |= uv[a] == v0 || uv[a] == v1 || uv[a] == v2;
+                  if (!adj) o2 = fminf(o2, geo_d2f(s_g, j, pn[0], pn[1], pn[2]));
+                }
+                const double lout = fmin((double)cwr - rn4 - 0.01, (double)cull - rn8 - 0.02);
+                keyw = (m << C3_KEYB) | tb;
+                lbw = fmin(sqrt(fmax((double)o2 - (1e-3 + 1e-5 * (double)o2), 0.0)), lout);
+              }
+            }
           }
         }
+      }
+      if (cslot && !cached && valid) {
+        // FP32 distances are within 1e-5 relative of exact here: a margin of
+        // 1e-3 plus 1e-5 of the bound; stored with the drift so far added and
+        // rounded down, so the bound at a later step is the stored value less
+        // the drift then
+        ca.ckey[cix] = keyw;
+        ca.clb[cix] = keyw >= 0 ? __double2float_rd(lbw - 1e-3 - 1e-5 * fabs(lbw) + drift) : 0.0f;
       }
       double sd = 0.0;
       bool band = false;

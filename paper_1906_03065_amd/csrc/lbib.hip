@@ -143,8 +143,8 @@ Layout make_layout(const lbib_params* p) {
   L.memE = c.take(64);
   L.stab = c.take(D == 2 ? (size_t)M * 16 : 0);
   L.sinv = c.take(D == 2 ? (size_t)M * 4 : 0);
-  L.ckey = c.take(D == 2 ? (size_t)COUP_CACHE * N * 4 : 0);
-  L.clb = c.take(D == 2 ? (size_t)COUP_CACHE * N * 4 : 0);
+  L.ckey = c.take((size_t)(D == 2 ? COUP_CACHE : COUP3_CACHE) * N * 4);
+  L.clb = c.take((size_t)(D == 2 ? COUP_CACHE : COUP3_CACHE) * N * 4);
   const bool d3 = D == 3;
   L.mom = c.take(d3 ? (size_t)N * 3 * 8 : 0);
   L.tri = c.take((size_t)L.maxT * 3 * 4);
@@ -192,7 +192,7 @@ struct lbib_sim {
   int overlap = 0;        // 2D: lattice regions away from the membranes beside the
                           // membrane kernels (0 off, 1 on)
   int force_form = 0;     // force of eq. ForceFE, 0 potential form, 1 divergence form (D2Q9, the default there)
-  int coup_cache = 1;     // D2Q9: each node keeps its closest membrane segment between steps
+  int coup_cache = 1;     // each node keeps its closest membrane segment / triangle between steps
   double fext[3] = {0, 0, 0};  // uniform external force density (eq. ForcingTermLBE)
   double mw[3] = {1, 1, 1};    // component densities (eq. MassDensity)
   bool any_law = false;   // D3Q19: a mesh has a triangle strain law (the triangle pass runs)
@@ -256,8 +256,10 @@ struct lbib_sim {
   // forget every node's cached closest segment (markers moved other than by
   // a step: checkpoint load, marker poke)
   int drop_coupling_cache() {
-    if (D != 2 || !L.ckey) return LBIB_OK;
-    if (hipMemsetAsync(ws + L.ckey, 0xff, (size_t)COUP_CACHE * N * 4, stream) != hipSuccess) return LBIB_EHIP;
+    if (!L.ckey) return LBIB_OK;
+    if (hipMemsetAsync(ws + L.ckey, 0xff, (size_t)(D == 2 ? COUP_CACHE : COUP3_CACHE) * N * 4, stream) !=
+        hipSuccess)
+      return LBIB_EHIP;
     return LBIB_OK;
   }
   virtual bool is_batch() const { return false; }
@@ -530,7 +532,10 @@ struct Engine2D final : lbib_sim {
     const int W = bx - 4;
     P.nstrip = (p.nx + W - 1) / W;
     P.nseg = (p.ny + P.seg - 1) / P.seg;
-    P.nxcd = nxcd > 0 ? nxcd : 1;
+    // automatic: eight L2 domains (the XCDs), so a segment's vertical
+    // neighbours, which read the same halo rows at the same time, sit in
+    // the same L2 (fetched bytes -15 % on the 2048^2 workload)
+    P.nxcd = nxcd > 0 ? nxcd : 8;
     P.mode = mode;
     P.npiece = mode == 2 ? (P.seg + 5) / 6 : 1;  // pieces of about five rows
     P.seg2 = (P.seg + P.npiece - 1) / P.npiece;
@@ -688,6 +693,9 @@ struct Engine3D final : lbib_sim {
     c.kappa_c = p.kappa_c;
     c.r_cut = r_cut;
     c.want_force = want_force;
+    c.ckey = coup_cache ? at<int>(L.ckey) : nullptr;
+    c.clb = coup_cache ? at<float>(L.clb) : nullptr;
+    c.N = N;
     return c;
   }
 
@@ -1186,7 +1194,8 @@ int init_sim(lbib_sim* s, const lbib_params* p, const Layout& L, char* ws, hipSt
       hipMemsetAsync(s->ws + L.Ifield, 0, (size_t)s->N * 8, st) != hipSuccess ||
       hipMemsetAsync(s->ws + L.mbox, 0, (size_t)std::max(p->max_membranes, 1) * 64, st) != hipSuccess)
     return LBIB_EHIP;
-  if (s->D == 2 && hipMemsetAsync(s->ws + L.ckey, 0xff, (size_t)COUP_CACHE * s->N * 4, st) != hipSuccess)
+  if (hipMemsetAsync(s->ws + L.ckey, 0xff, (size_t)(s->D == 2 ? COUP_CACHE : COUP3_CACHE) * s->N * 4, st) !=
+      hipSuccess)
     return LBIB_EHIP;
   // the tile flags start at 0 and the stamp at 1: no tile is active until a
   // membrane's tile pass flags it (a simulation without membranes never
@@ -1466,7 +1475,7 @@ int lbib_set_densities(lbib_sim* s, double m1, double m2, double m3) {
 }
 
 int lbib_set_coupling_cache(lbib_sim* s, int on) {
-  if (!s || s->D != 2 || on < 0 || on > 1) return LBIB_EINVAL;
+  if (!s || on < 0 || on > 1) return LBIB_EINVAL;
   if (s->is_batch()) {
     for (int k = 0;; k++) {
       lbib_sim* m = nullptr;

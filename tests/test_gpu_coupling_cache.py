@@ -1,7 +1,8 @@
 """The coupling-profile search with and without the per-node cache of the
-closest membrane segment (lbib_set_coupling_cache): a cached segment is
-used only while a bound proves a full search would pick it, so both give
-bitwise the same fields, markers, marker velocities and forces."""
+closest membrane element (lbib_set_coupling_cache; ring segments in 2D,
+triangles in 3D): a cached element is used only while a bound proves a full
+search would pick it, so both give bitwise the same fields, markers, marker
+velocities and forces."""
 import numpy as np
 import pytest
 
@@ -92,9 +93,36 @@ def test_cache_bitwise_batch_and_rules():
     for k, w in enumerate(ws):
         bad = _same(a[k], b[k], len(w["membranes"]))
         assert bad is None, (k, bad)
-    s3 = lbib.Sim(W.base_params(16, 16, 16, lattice=1))
-    with pytest.raises(lbib.LbibError):
-        s3.set_coupling_cache(1)
     g = run_gpu(W.c1(), "fp32")
     with pytest.raises(lbib.LbibError):
         g.set_coupling_cache(2)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_cache_bitwise_moving_capsules_3d(storage):
+    """Two icosphere capsules (1280 triangles each) bridged on an interface,
+    walls in z, driven across the box by a uniform force so that cached
+    triangles keep expiring: cache on and off bitwise equal."""
+    w = W.capsule3d(n=40, R=8.0, subdiv=3, tau=0.85, shift=(0.3, 0.2, 0.1))
+    w["params"]["fext"] = [4e-6, 2e-6, 1e-6]
+    a = run_gpu(w, storage)
+    b = run_gpu(w, storage)
+    b.set_coupling_cache(0)
+    for n in (1, 30, 150):
+        a.step(n - a.steps_done)
+        b.step(n - b.steps_done)
+        bad = _same(a, b, 2)
+        print(storage, "3d step", n, "cache on vs off:", bad or "bitwise equal", flush=True)
+        assert bad is None, (n, bad)
+
+
+def test_cache_bitwise_c3():
+    """The 256^3 two-capsule benchmark workload, 8 steps."""
+    w = W.c3()
+    a = run_gpu(w, "fp32")
+    b = run_gpu(w, "fp32")
+    b.set_coupling_cache(0)
+    a.step(8)
+    b.step(8)
+    bad = _same(a, b, len(w["membranes"]))
+    assert bad is None, bad

@@ -78,18 +78,19 @@ def _bitwise(a, b, n_mem):
 
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_divergence_launch_shapes_bitwise(storage):
-    """Lanes per workgroup, rows per workgroup and ring depth change nothing
-    in the results of the divergence form."""
+    """Lanes per workgroup, rows per workgroup, ring depth and the dealing
+    of workgroups to L2 domains change nothing in the results of the
+    divergence form."""
     w = _form(_two_capsules(1), 1)
     ref = run_gpu(w, storage)
     ref.step(30)
-    for bx, seg, ring in [(64, 7, 3), (128, -1, 4), (192, 13, 3), (256, 5, 4)]:
+    for bx, seg, ring, nxcd in [(64, 7, 3, 0), (128, -1, 4, 0), (192, 13, 3, 3), (256, 5, 4, 0), (256, 0, 3, 1)]:
         g = run_gpu(w, storage)
-        g.set_launch(block_x=bx, seg=seg, ring=ring)
+        g.set_launch(block_x=bx, seg=seg, nxcd=nxcd, ring=ring)
         g.step(30)
         bad = _bitwise(ref, g, 2)
-        print(storage, bx, seg, ring, "differs in" if bad else "bitwise equal", bad or "", flush=True)
-        assert bad is None, (bx, seg, ring, bad)
+        print(storage, bx, seg, ring, nxcd, "differs in" if bad else "bitwise equal", bad or "", flush=True)
+        assert bad is None, (bx, seg, ring, nxcd, bad)
 
 
 def _momentum(g):
