@@ -125,8 +125,10 @@ __global__ __launch_bounds__(BX, WPE) void kb_lb2d(const BMember<St>* T, const i
   // fits the single kernel's register budget (three waves per SIMD)
   const int total = bpre[ncm];
   {
-    const int item = blockIdx.x;
-    if (item >= total) return;
+    if ((int)blockIdx.x >= total) return;
+    // items dealt to the eight XCDs in contiguous runs, so the neighbouring
+    // segments of a member share their halo rows in one L2
+    const int item = (int)gridDim.x == total ? dealt_index((int)blockIdx.x, total, 8) : (int)blockIdx.x;
     const int q = prefix_find(bpre, ncm, item);
     const int i = cm[q];
     const LBParams P = T[i].P;

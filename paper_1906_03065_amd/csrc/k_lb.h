@@ -64,13 +64,15 @@ struct LBParams {
 // workgroups to the XCDs in turn, and each XCD has its own L2.  Give every
 // XCD a contiguous run of the logical order (strips fastest), so the strips
 // that share halo columns run side by side on one XCD and meet in its L2.
-__device__ __forceinline__ void strip_segment(int b, int nstrip, int nseg, int nxcd, int& s, int& g) {
-  const int total = nstrip * nseg;
+__device__ __forceinline__ int dealt_index(int b, int total, int nxcd) {
   const int c = b % nxcd, j = b / nxcd;
   // blocks dealt to XCDs before c: sum over c' < c of ceil((total - c') / nxcd)
   const int q = total / nxcd, rem = total % nxcd;
-  const int off = c * q + min(c, rem);
-  const int L = off + j;
+  return c * q + min(c, rem) + j;
+}
+
+__device__ __forceinline__ void strip_segment(int b, int nstrip, int nseg, int nxcd, int& s, int& g) {
+  const int L = dealt_index(b, nstrip * nseg, nxcd);
   s = L % nstrip;
   g = L / nstrip;
 }
