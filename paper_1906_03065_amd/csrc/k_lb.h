@@ -254,6 +254,18 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
   // membrane fields of rows k-1 and k-2 are then fetched at the start of
   // iteration k, beside the pull, instead of after a dependent flag load
   int tfl[NS];
+  // NS = 4: the membrane fields a row needs (profile field on the row of the
+  // chemical potential, spread force on the row of the collision) are
+  // fetched one iteration early, before that iteration's stores.  Waits
+  // count outstanding loads and stores in issue order, so fetched after the
+  // next row's prefetch they would make the wait for them a wait for the
+  // prefetch (and for the stores) as well.
+  // Two register slots, alternating with the row parity (the loop is
+  // unrolled by four), so no value is copied between registers while its
+  // load may still be in flight.
+  double Ipre_c[2] = {0.0, 0.0};
+  long long fb0_c[2] = {0, 0}, fb1_c[2] = {0, 0};
+  bool cact_c[2] = {false, false};
 
   auto load_row = [&](auto slot_c, int k) {
     constexpr int S = decltype(slot_c)::value;
@@ -269,20 +281,30 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
     constexpr int SP = (S + NS - 1) % NS;        // slot of row k-1 (chemical potential now)
     const int r = rbase + dir * k;               // row whose moments are formed now
     if constexpr (NS == 4) {
-      if (k + 1 < K) load_row(std::integral_constant<int, SN>{}, k + 1);
+      // unconditional (the last iteration reloads its own row), so every
+      // path has the same loads in flight
+      load_row(std::integral_constant<int, SN>{}, min(k + 1, K - 1));
     } else {
       load_row(std::integral_constant<int, S>{}, k);
     }
     const int qy = fd_row(r - dir, P.ny, P.wall_y);  // row of the chemical potential
     const int cy = r - 2 * dir;                      // row of the collision
     double Ipre = 0.0;
-    if (k >= 2 && j >= 1 && j < BX - 1 && tfl[SP] == stamp) Ipre = Ifield[(long long)qy * P.nx + x];
     long long fb0 = 0, fb1 = 0;
-    const bool cact = k >= 4 && interior && tfl[SC] == stamp;
-    if (cact) {
-      const long long* fp = fib + 2 * ((long long)cy * P.nx + x);
-      fb0 = fp[0];
-      fb1 = fp[1];
+    bool cact;
+    if constexpr (NS == 4) {
+      Ipre = Ipre_c[S & 1];
+      fb0 = fb0_c[S & 1];
+      fb1 = fb1_c[S & 1];
+      cact = cact_c[S & 1];
+    } else {
+      if (k >= 2 && j >= 1 && j < BX - 1 && tfl[SP] == stamp) Ipre = Ifield[(long long)qy * P.nx + x];
+      cact = k >= 4 && interior && tfl[SC] == stamp;
+      if (cact) {
+        const long long* fp = fib + 2 * ((long long)cy * P.nx + x);
+        fb0 = fp[0];
+        fb1 = fp[1];
+      }
     }
     // ---- M: moments of row r -> ring slot k%3
     {
@@ -363,6 +385,23 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
       s_u[sl][2][j] = ms;
     }
     __syncthreads();
+    if constexpr (NS == 4) {
+      // the next iteration's membrane fields: its chemical-potential row is
+      // row r (flag in slot S), its collision row r - dir (flag in slot SP)
+      constexpr int T = SN & 1;
+      const int k1 = k + 1;
+      Ipre_c[T] = 0.0;
+      if (k1 >= 2 && k1 < K && j >= 1 && j < BX - 1 && tfl[S] == stamp)
+        Ipre_c[T] = Ifield[(long long)fd_row(r, P.ny, P.wall_y) * P.nx + x];
+      cact_c[T] = k1 >= 4 && k1 < K && interior && tfl[SP] == stamp;
+      fb0_c[T] = 0;
+      fb1_c[T] = 0;
+      if (cact_c[T]) {
+        const long long* fp = fib + 2 * ((long long)(r - dir) * P.nx + x);
+        fb0_c[T] = fp[0];
+        fb1_c[T] = fp[1];
+      }
+    }
     // ---- C: collide row r - 2 dir with the registers of slot SC
     if (k >= 4 && interior) {
       const int a = (k + 1) % 3, b = (k + 2) % 3, c = k % 3;  // mu rows cy-dir, cy, cy+dir
