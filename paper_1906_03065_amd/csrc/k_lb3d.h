@@ -204,23 +204,23 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
     constexpr int SN = S ^ 1;                  // set pulled now
     const int zk = zbase + dir * k;
     const int slot = k % 3;
-    // ---- issue: moments of plane zk on the (TX+4) x (TY+4) region
+    // Loads are issued with the ones under a condition first and the
+    // unconditional ones in the order they are consumed: waits count
+    // outstanding loads and stores in issue order, so a conditional load
+    // issued after another would leave the wait for the earlier one unsure
+    // of its count, and it would then wait for everything (the next plane's
+    // pull included).
+    // ---- issue: the spread force of plane z_{k-2} (collided now)
+    const int cz = zk - 2 * dir;
+    const bool doC = k >= 4 && own;
+    const bool cact = doC && fC == stamp;
+    const long long node = ((long long)cz * P.ny + gy) * P.nx + xw;
+    long long fb[3] = {0, 0, 0};
+    if (cact)
+      for (int a3 = 0; a3 < 3; a3++) fb[a3] = fib[3 * node + a3];
+    // ---- issue: profile field of plane z_{k-1} where its tile is active,
+    // tile flags of the next plane's chemical-potential nodes
     const int zr = halo_row(zk, P.nz, P.wall_z);
-    double mv[NH][3];
-#pragma unroll
-    for (int r = 0; r < NH; r++) {
-      const int q = tid + 256 * r;
-      if (q < TXH * TYH) {
-        const int hx = q % TXH, hy = q / TXH;
-        const int xx = wrap(x0 - 2 + hx, P.nx);
-        const int yy = halo_row(y0t - 2 + hy, P.ny, P.wall_y);
-        const long long nd = ((long long)zr * P.ny + yy) * P.nx + xx;
-        mv[r][0] = M.d[nd];
-        mv[r][1] = M.phi[nd];
-        mv[r][2] = M.psi[nd];
-      }
-    }
-    // ---- issue: profile field of plane z_{k-1} where its tile is active
     const int zq = halo_row(zk - dir, P.nz, P.wall_z);
     double Iv[NU] = {};
     int nfU[NU] = {};
@@ -230,23 +230,33 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
       if (q < TXU * TYU) {
         const int xx = wrap(x0 - 1 + q % TXU, P.nx);
         const int yy = halo_row(y0t - 1 + q / TXU, P.ny, P.wall_y);
-        if (k >= 2 && fU[r] == stamp) Iv[r] = Ifield[((long long)zq * P.ny + yy) * P.nx + xx];
         if (k + 1 < K) nfU[r] = tflag[tile3(P, xx, yy, zr)];
+        if (k >= 2 && fU[r] == stamp) Iv[r] = Ifield[((long long)zq * P.ny + yy) * P.nx + xx];
       }
     }
-    // ---- issue: pull of plane z_{k-1} (collided next iteration), the
-    // spread force of plane z_{k-2} (collided now)
-    const bool pnext = k >= 3 && k + 1 < K && own;
-    if (pnext) pull19(src, P, xw, gy, zk - dir, pf[SN], pg[SN], ph[SN], g0[SN], h0[SN]);
-    const int cz = zk - 2 * dir;
-    const bool doC = k >= 4 && own;
-    const bool cact = doC && fC == stamp;
-    const long long node = ((long long)cz * P.ny + gy) * P.nx + xw;
-    long long fb[3] = {0, 0, 0};
-    if (cact)
-      for (int a3 = 0; a3 < 3; a3++) fb[a3] = fib[3 * node + a3];
-    int nfC = 0;
-    if (pnext) nfC = tflag[tile3(P, xw, gy, zk - dir)];
+    // ---- issue: tile flag of the next collision node (consumed at the
+    // start of the next iteration, so issued before the bulk of this one's loads)
+    const int pz = min(max(zk - dir, 0), P.nz - 1), gyc = min(gy, P.ny - 1);
+    const int nfC = tflag[tile3(P, xw, gyc, pz)];
+    // ---- issue: moments of plane zk on the (TX+4) x (TY+4) region (lanes
+    // past the region load its last node again, unused)
+    double mv[NH][3];
+#pragma unroll
+    for (int r = 0; r < NH; r++) {
+      const int q = min(tid + 256 * r, TXH * TYH - 1);
+      const int hx = q % TXH, hy = q / TXH;
+      const int xx = wrap(x0 - 2 + hx, P.nx);
+      const int yy = halo_row(y0t - 2 + hy, P.ny, P.wall_y);
+      const long long nd = ((long long)zr * P.ny + yy) * P.nx + xx;
+      mv[r][0] = M.d[nd];
+      mv[r][1] = M.phi[nd];
+      mv[r][2] = M.psi[nd];
+    }
+    // ---- issue: pull of plane z_{k-1} (collided next iteration), on every
+    // iteration and lane (a plane or row outside the lattice is clamped into
+    // it; only the pulls of iterations 3 .. K-2 at the workgroup's own nodes
+    // are collided)
+    pull19(src, P, xw, gyc, pz, pf[SN], pg[SN], ph[SN], g0[SN], h0[SN]);
     // ---- L: moments to the ring
 #pragma unroll
     for (int r = 0; r < NH; r++) {
@@ -323,6 +333,9 @@ __global__ __launch_bounds__(256, 2) void k_lb3d(St src, St dst, LBParams P, Mom
         F[a3] = -(rho * gr[0][a3] + phi * gr[1][a3] + psi * gr[2][a3]) + P.fext[a3];
       if (cact) {
         for (int a3 = 0; a3 < 3; a3++) {
+          // keeps the conversion (and so the wait for the load) here rather
+          // than next to the load, where waiting would include every later load
+          asm volatile("" : "+v"(fb[a3]));
           F[a3] += from_fix(fb[a3]);
           fib[3 * node + a3] = 0;
           force[3 * node + a3] = F[a3];
