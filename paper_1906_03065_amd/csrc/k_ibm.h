@@ -100,6 +100,34 @@ __device__ double block_min(double v, double* sh) {
   return t;
 }
 
+// seven minima and one sum over the block with a single exchange, in the
+// order of block_min and block_sum (bitwise the same results)
+template <int NT>
+__device__ void block_min7_sum1(double (&v)[8], double* sh) {
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 7; k++) v[k] = fmin(v[k], __shfl_down(v[k], o, 64));
+    v[7] += __shfl_down(v[7], o, 64);
+  }
+  constexpr int W = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 8; k++) sh[k * W + wv] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 7; k++) {
+    double t = sh[k * W];
+    for (int i = 1; i < W; i++) t = fmin(t, sh[k * W + i]);
+    v[k] = t;
+  }
+  double t = 0;
+  for (int i = 0; i < W; i++) t += sh[7 * W + i];
+  v[7] = t;
+  __syncthreads();
+}
+
 __device__ __forceinline__ float wave_minf(float v) {
   for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
   return v;
@@ -134,39 +162,39 @@ __global__ void k_begin(int* tstate) {
 template <int NT>
 __device__ __forceinline__ void tiles_run(const MemDev& md, const TileMap& tm, int nx, int ny, int nz,
                                           int wall_y, int wall_z, int D, double reach, int m) {
-  __shared__ double sh[NT / 64];
+  __shared__ double sh[8 * (NT / 64)];
   const int tid = threadIdx.x;
   const int b = md.moff[m], e = md.moff[m + 1], n = e - b;
   const int stamp = tm.tstate[1];
+  // one pass over the markers: box (minima of X and of -X), largest step of
+  // the last marker update |U| (each step adds it to the membrane's drift
+  // bound; a call between steps adds it again, which only loosens the bound)
+  // and, in 2D, the signed area (shoelace sum) that gives the orientation;
+  // then one block-wide exchange for all eight values
+  double v[8] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300, 0.0, 0.0};
+  for (int l = tid; l < n; l += NT) {
+    const double* Xl = md.X + 3 * (b + l);
+    for (int a = 0; a < D; a++) {
+      v[a] = fmin(v[a], Xl[a]);
+      v[3 + a] = fmax(v[3 + a], Xl[a]);
+    }
+    const double* Ul = md.U + 3 * (b + l);
+    v[6] = fmax(v[6], Ul[0] * Ul[0] + Ul[1] * Ul[1] + Ul[2] * Ul[2]);
+    if (D == 2) {
+      const int l1 = (l + 1 == n) ? 0 : l + 1;
+      const double* X1 = md.X + 3 * (b + l1);
+      v[7] += Xl[0] * X1[1] - X1[0] * Xl[1];
+    }
+  }
+  for (int k = 3; k < 7; k++) v[k] = -v[k];
+  block_min7_sum1<NT>(v, sh);
   double lo[3], hi[3];
   for (int a = 0; a < 3; a++) {
-    double mn = 1e300, mx = -1e300;
-    if (a < D)
-      for (int l = b + tid; l < e; l += NT) {
-        const double v = md.X[3 * l + a];
-        mn = fmin(mn, v);
-        mx = fmax(mx, v);
-      }
-    lo[a] = block_min<NT>(mn, sh);
-    hi[a] = -block_min<NT>(-mx, sh);
+    lo[a] = v[a];
+    hi[a] = -v[3 + a];
   }
-  // largest step of the last marker update, |U| (each step adds it to the
-  // membrane's drift bound; a call between steps adds it again, which only
-  // loosens the bound)
-  double u2 = 0.0;
-  for (int l = b + tid; l < e; l += NT)
-    u2 = fmax(u2, md.U[3 * l] * md.U[3 * l] + md.U[3 * l + 1] * md.U[3 * l + 1] + md.U[3 * l + 2] * md.U[3 * l + 2]);
-  const double umax = sqrt(-block_min<NT>(-u2, sh));
-  // orientation of a 2D ring from its signed area (shoelace sum)
-  double area = 0.0;
-  if (D == 2) {
-    double acc = 0.0;
-    for (int l = tid; l < n; l += NT) {
-      const int l1 = (l + 1 == n) ? 0 : l + 1;
-      acc += md.X[3 * (b + l)] * md.X[3 * (b + l1) + 1] - md.X[3 * (b + l1)] * md.X[3 * (b + l) + 1];
-    }
-    area = block_sum<NT>(acc, sh);
-  }
+  const double umax = sqrt(-v[6]);
+  const double area = D == 2 ? v[7] : 0.0;
   if (tid == 0) {
     for (int a = 0; a < 3; a++) {
       md.mbox[8 * m + a] = lo[a];
@@ -398,6 +426,40 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     // largest distance of a node from its tile / sub-tile centre
     const double rn16 = 7.5 * 1.41421356237309515, rn8 = 3.5 * 1.41421356237309515;
     const bool valid = (x < ca.nx) && (y < ca.ny);
+    const long long node = (long long)y * ca.nx + x;
+    // loads that depend on the node only are issued before the membrane
+    // list, so their latency overlaps it: the cache entries of the first
+    // COUP_CACHE slots and, for the force, the populations h_i that sum to psi
+    int kpre[COUP_CACHE];
+    float lpre[COUP_CACHE];
+#pragma unroll
+    for (int c = 0; c < COUP_CACHE; c++) {
+      kpre[c] = -1;
+      lpre[c] = 0.0f;
+      if (ca.ckey != nullptr && valid) {
+        kpre[c] = ca.ckey[(long long)c * ca.N + node];
+        lpre[c] = ca.clb[(long long)c * ca.N + node];
+      }
+    }
+    double hrest = 0.0;
+    R hmov[8];
+    if (ca.want_force && valid) {
+      using L = Lattice<9>;
+      hrest = cur.rest(2, node);
+#pragma unroll
+      for (int i = 1; i < 9; i++) {
+        const int sy = y - L::cy[i];
+        long long sn;
+        int dir = i;
+        if (ca.wall_y && (sy < 0 || sy >= ca.ny)) {
+          sn = node;
+          dir = L::opp[i];
+        } else {
+          sn = (long long)wrap(sy, ca.ny) * ca.nx + wrap(x - L::cx[i], ca.nx);
+        }
+        hmov[i - 1] = cur.template load<R>(2, dir, sn);
+      }
+    }
     const double xt = tx * TILE2 + 0.5 * (TILE2 - 1), yt = ty * TILE2 + 0.5 * (TILE2 - 1);
     // image of the tile centre nearest a membrane's box centre (cx, cy): the
     // image of the tile's first node, since the nodes of a tile that does
@@ -506,28 +568,43 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       bool cached = false;
       if (cslot) {
         bool ok = true;
+        int key = kpre[0];
+        float klb = lpre[0];
+#pragma unroll
+        for (int c = 1; c < COUP_CACHE; c++)
+          if (slot == c) {
+            key = kpre[c];
+            klb = lpre[c];
+          }
         if (inbox) {
-          const int key = ca.ckey[cix];
           ok = key >= 0 && (key >> 16) == m;
           if (ok) {
-            const double thr = (double)ca.clb[cix] - bx[7];
+            const double thr = (double)klb - bx[7];
             const int sk = key & 0xFFFF;
             if (sk >= 0xFFF0) {
               ok = thr > ca.r_cut;
               side = sk == 0xFFFE ? 1 : 0;
             } else {
               // the kept segment and COUP_WIN on each side (lowest index on
-              // equal distances, whatever the order)
+              // equal distances, whatever the order), walked along the ring
+              // so each vertex is loaded once
+              int q = (sk - COUP_WIN) % n;
+              if (q < 0) q += n;
+              double ax = X[3 * q], ay = X[3 * q + 1];
 #pragma unroll
-              for (int k = -COUP_WIN; k <= COUP_WIN; k++) {
-                const int q = ((sk + k) % n + n) % n, q1 = (q + 1 == n) ? 0 : q + 1;
+              for (int k = 0; k <= 2 * COUP_WIN; k++) {
+                const int q1 = (q + 1 == n) ? 0 : q + 1;
+                const double bx_ = X[3 * q1], by_ = X[3 * q1 + 1];
                 double tt;
-                const double d2 = seg_d2(px, py, X[3 * q], X[3 * q + 1], X[3 * q1], X[3 * q1 + 1], tt);
+                const double d2 = seg_d2(px, py, ax, ay, bx_, by_, tt);
                 if (d2 < d2b || (d2 == d2b && q < sb)) {
                   d2b = d2;
                   sb = q;
                   tb = tt;
                 }
+                ax = bx_;
+                ay = by_;
+                q = q1;
               }
               ok = sqrt(d2b) < thr;
             }
@@ -540,7 +617,7 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         // index on ties) and keeps either its closest segment with the exact
         // bound over all segments beyond the window, or, well beyond the
         // band, its side and distance.
-        const bool renew = !ok && inbox && ca.ckey[cix] >= 0 && (ca.ckey[cix] >> 16) == m;
+        const bool renew = !ok && inbox && key >= 0 && (key >> 16) == m;
         unsigned long long need = __ballot(renew);
         if (__popcll(need) > COUP_RENEW) need = 0;  // left to the full search
         if (need) {
@@ -837,7 +914,6 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         b_sd[slot][threadIdx.x] = sd;
       }
     }
-    const long long node = (long long)y * ca.nx + x;
     if (valid) Ifield[node] = Itot;
     if (ca.want_force) {
       // coupling force on the markers, -dE_c/dX (eq. DiscreteCF): from every
@@ -851,20 +927,9 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       // psi only where a node of the wave is in a band
       double psi = 0.0;
       if (valid && __ballot(anyband)) {
-        using L = Lattice<9>;
-        psi = cur.rest(2, node);
-        for (int i = 1; i < 9; i++) {
-          const int sy = y - L::cy[i];
-          long long sn;
-          int dir = i;
-          if (ca.wall_y && (sy < 0 || sy >= ca.ny)) {
-            sn = node;
-            dir = L::opp[i];
-          } else {
-            sn = (long long)wrap(sy, ca.ny) * ca.nx + wrap(x - L::cx[i], ca.nx);
-          }
-          psi += (double)cur.template load<R>(2, dir, sn);
-        }
+        psi = hrest;
+#pragma unroll
+        for (int i = 0; i < 8; i++) psi += (double)hmov[i];
       }
       // per membrane: the tile's contributions are summed in LDS (integer
       // adds of fixed-point values, so the order does not matter), indexed
