@@ -248,7 +248,17 @@ __device__ __forceinline__ void tiles_run(const MemDev& md, const TileMap& tm, i
     const int tx = wrap(t0[0] + ix, nt[0]), ty = wrap(t0[1] + iy, nt[1]);
     const int tz = (D == 3) ? wrap(t0[2] + iz, nt[2]) : 0;
     const int t = (tz * tm.nty + ty) * tm.ntx + tx;
-    if (atomicMax(&tm.tflag[t], stamp) < stamp) tm.tlist[atomicAdd(&tm.tstate[0], 1)] = t;
+    // a tile first marked in this step takes a list slot: one counter
+    // update per wave for all of its newly marked tiles
+    const bool fresh = atomicMax(&tm.tflag[t], stamp) < stamp;
+    const unsigned long long mk = __ballot(fresh);
+    if (mk) {
+      const int lane = tid & 63, lead = __ffsll((long long)mk) - 1;
+      int base = 0;
+      if (lane == lead) base = atomicAdd(&tm.tstate[0], __popcll(mk));
+      base = __shfl(base, lead, 64);
+      if (fresh) tm.tlist[base + __popcll(mk & ((1ull << lane) - 1ull))] = t;
+    }
   }
 }
 
@@ -1060,61 +1070,62 @@ __device__ __forceinline__ double seg_energy(int law, double ks, double lam) {
   return 0.5 * ks * q * q;
 }
 
-__device__ __forceinline__ void memforce2d_run(const MemDev& md, int g, double& Fxo, double& Fyo) {
+// one term of marker g's force (eq. DiscreteTF), by lane k of its group:
+// k = 0, 1 the strain of segments l -> l+1 and l-1 -> l (eq. DiscreteSF,
+// each pulling with its tension along itself), k = 2, 3, 4 the bending terms
+// of vertices l-1, l, l+1, which depend on X_l (eq. DiscreteBF), k = 5 the
+// coupling force accumulated by the profile kernel (read and cleared).
+// Returns the membrane's bending modulus.
+__device__ __forceinline__ double memforce2d_part(const MemDev& md, int g, int k, double& tx, double& ty) {
   const int m = md.mid[g];
   const int b = md.moff[m], n = md.moff[m + 1] - b;
   const int l = g - b;
-  auto P = [&](int k, int a) { return md.X[3 * (b + ((l + k) % n + n) % n) + a]; };
-  auto rest = [&](int k) { return md.rest[b + ((l + k) % n + n) % n]; };
-  const double ks = md.ks[m], kbm = md.kb[m];
-  const int law = md.law[m];
-  double Fx = 0, Fy = 0;
-  // strain, eq. DiscreteSF: segments l-1 -> l and l -> l+1, each pulling
-  // with its tension along itself
-  {
-    const double ex = P(1, 0) - P(0, 0), ey = P(1, 1) - P(0, 1);
+  const double kbm = md.kb[m];
+  tx = ty = 0.0;
+  // marker l + j for |j| <= 2 (a ring holds at least three markers)
+  auto at = [&](int j) {
+    int i = l + j;
+    if (i < 0) i += n;
+    if (i >= n) i -= n;
+    return b + i;
+  };
+  if (k <= 1) {
+    const int v = at(-k), w = at(1 - k);
+    const double ex = md.X[3 * w] - md.X[3 * v], ey = md.X[3 * w + 1] - md.X[3 * v + 1];
     const double len = sqrt(ex * ex + ey * ey);
-    const double s = seg_tension(law, ks, len / rest(0)) / len;
-    Fx += s * ex;
-    Fy += s * ey;
-    const double fx = P(0, 0) - P(-1, 0), fy = P(0, 1) - P(-1, 1);
-    const double lf = sqrt(fx * fx + fy * fy);
-    const double sf = seg_tension(law, ks, lf / rest(-1)) / lf;
-    Fx -= sf * fx;
-    Fy -= sf * fy;
+    const double s = seg_tension(md.law[m], md.ks[m], len / md.rest[v]) / len;
+    // X_l is the start of segment l -> l+1 and the end of l-1 -> l
+    tx = k == 0 ? s * ex : -(s * ex);
+    ty = k == 0 ? s * ey : -(s * ey);
+  } else if (k <= 4) {
+    if (kbm != 0.0) {
+      // vertex v = l + k - 3: a = X_{v+1} - X_v, b = X_v - X_{v-1}
+      const int u = at(k - 4), v = at(k - 3), w = at(k - 2);
+      double gax, gay, gbx, gby, e;
+      bend_grad(md.X[3 * w] - md.X[3 * v], md.X[3 * w + 1] - md.X[3 * v + 1], md.X[3 * v] - md.X[3 * u],
+                md.X[3 * v + 1] - md.X[3 * u + 1], kbm, gax, gay, gbx, gby, e);
+      // X_l enters vertex l-1 through a (+1), vertex l through a (-1) and b
+      // (+1), vertex l+1 through b (-1)
+      if (k == 2) {
+        tx = -gax;
+        ty = -gay;
+      } else if (k == 3) {
+        tx = gax - gbx;
+        ty = gay - gby;
+      } else {
+        tx = gbx;
+        ty = gby;
+      }
+    }
+  } else if (k == 5) {
+    long long* acc = md.Facc + 3 * g;
+    tx = from_fix(acc[0]);
+    ty = from_fix(acc[1]);
+    acc[0] = 0;
+    acc[1] = 0;
+    acc[2] = 0;
   }
-  // bending, eq. DiscreteBF: vertex terms l-1, l, l+1 depend on X_l
-  if (kbm != 0.0) {
-    double gax, gay, gbx, gby, e;
-    // vertex l-1: X_l = X_{(l-1)+1} enters through a
-    bend_grad(P(0, 0) - P(-1, 0), P(0, 1) - P(-1, 1), P(-1, 0) - P(-2, 0), P(-1, 1) - P(-2, 1), kbm,
-              gax, gay, gbx, gby, e);
-    Fx -= gax;
-    Fy -= gay;
-    // vertex l: a = X_{l+1} - X_l (dX_l: -1), b = X_l - X_{l-1} (dX_l: +1)
-    bend_grad(P(1, 0) - P(0, 0), P(1, 1) - P(0, 1), P(0, 0) - P(-1, 0), P(0, 1) - P(-1, 1), kbm, gax,
-              gay, gbx, gby, e);
-    Fx -= -gax + gbx;
-    Fy -= -gay + gby;
-    // vertex l+1: X_l = X_{(l+1)-1} enters through b with sign -1
-    bend_grad(P(2, 0) - P(1, 0), P(2, 1) - P(1, 1), P(1, 0) - P(0, 0), P(1, 1) - P(0, 1), kbm, gax,
-              gay, gbx, gby, e);
-    Fx += gbx;
-    Fy += gby;
-  }
-  // coupling force accumulated by the profile kernel
-  long long* acc = md.Facc + 3 * g;
-  Fx += from_fix(acc[0]);
-  Fy += from_fix(acc[1]);
-  acc[0] = 0;
-  acc[1] = 0;
-  acc[2] = 0;
-  if (!(fabs(Fx) < FIX_LIMIT) || !(fabs(Fy) < FIX_LIMIT)) md.status[0] = 1;
-  md.F[3 * g] = Fx;
-  md.F[3 * g + 1] = Fy;
-  md.F[3 * g + 2] = 0.0;
-  Fxo = Fx;
-  Fyo = Fy;
+  return kbm;
 }
 
 // spreading, eq. Spreading with delta x = 1 (READING: no extra Delta s):
@@ -1131,15 +1142,35 @@ __device__ __forceinline__ void spread2d_run(const MemDev& md, long long* __rest
   atomicAdd((unsigned long long*)&fib[2 * node + 1], (unsigned long long)to_fix(Fy * w));
 }
 
-// marker forces (strain + bending + coupling, eq. DiscreteTF) by the first
-// lane of each sixteen-lane group, handed to the group by shuffles, then
-// spread by all sixteen; every lane of a group must call it
+// marker forces (strain + bending + coupling, eq. DiscreteTF): six lanes of
+// each sixteen-lane group form one term each, the group sums them by
+// shuffles, then all sixteen spread; every lane of a group must call it
 __device__ __forceinline__ void forcespread2d_run(const MemDev& md, long long* __restrict__ fib, int nx, int ny,
                                                   int wall_y, int g, int k, bool live) {
-  double Fx = 0.0, Fy = 0.0;
-  if (live && k == 0) memforce2d_run(md, g, Fx, Fy);
-  Fx = __shfl(Fx, 0, 16);
-  Fy = __shfl(Fy, 0, 16);
+  double tx = 0.0, ty = 0.0, kbm = 0.0;
+  if (live && k < 6) kbm = memforce2d_part(md, g, k, tx, ty);
+  kbm = __shfl(kbm, 0, 16);
+  // the terms added in a fixed order: strain, bending (when the membrane has
+  // a bending modulus), coupling
+  double Fx = __shfl(tx, 0, 16), Fy = __shfl(ty, 0, 16);
+  Fx += __shfl(tx, 1, 16);
+  Fy += __shfl(ty, 1, 16);
+#pragma unroll
+  for (int j = 2; j < 5; j++) {
+    const double bx = __shfl(tx, j, 16), by = __shfl(ty, j, 16);
+    if (kbm != 0.0) {
+      Fx += bx;
+      Fy += by;
+    }
+  }
+  Fx += __shfl(tx, 5, 16);
+  Fy += __shfl(ty, 5, 16);
+  if (live && k == 0) {
+    if (!(fabs(Fx) < FIX_LIMIT) || !(fabs(Fy) < FIX_LIMIT)) md.status[0] = 1;
+    md.F[3 * g] = Fx;
+    md.F[3 * g + 1] = Fy;
+    md.F[3 * g + 2] = 0.0;
+  }
   if (live) spread2d_run(md, fib, nx, ny, wall_y, g, k, Fx, Fy);
 }
 
