@@ -348,6 +348,35 @@ __device__ __forceinline__ bool ring_side(const double* X, int n, double o, int 
   return o * (nx_ * (px - vx) + ny_ * (py - vy)) > 0.0;
 }
 
+// profile value 0.5 (1 + tanh x) of eq. Iprofile (x = d / (2 alpha), d the
+// signed distance) and sech^2 x, the factor of the coupling force (eq.
+// DiscreteCF), from one exponential
+__device__ __forceinline__ double profile_sech2(double x, double& s2) {
+  const double em = expm1(-2.0 * fabs(x));  // e^{-2|x|} - 1, in (-1, 0]
+  const double th = -em / (2.0 + em);        // tanh |x|
+  s2 = 4.0 * (1.0 + em) / ((2.0 + em) * (2.0 + em));
+  return 0.5 * (1.0 + (x < 0.0 ? -th : th));
+}
+
+// A band node at signed distance sd (|sd| = d) from the closest point of
+// segment s (parameter t): the direction in which the coupling energy pushes
+// the segment's vertices, -sign(sd) nhat sech^2(sd / (2 alpha)) with nhat the
+// unit vector from the closest point to the node (eq. DiscreteCF without the
+// factor kappa_c / (4 alpha) (psi - I) and the vertex weights).  Zero for a
+// node on the ring, where nhat is undefined.
+__device__ __forceinline__ void band_push(const double* X, int n, int s, double t, double px, double py,
+                                          double sd, double s2, double& gx, double& gy) {
+  const double d = fabs(sd);
+  gx = gy = 0.0;
+  if (d == 0.0) return;
+  const int s1 = (s + 1 == n) ? 0 : s + 1;
+  const double fx = X[3 * s] + t * (X[3 * s1] - X[3 * s]);
+  const double fy = X[3 * s + 1] + t * (X[3 * s1 + 1] - X[3 * s + 1]);
+  const double sg = sd > 0.0 ? 1.0 : -1.0;
+  gx = -sg * ((px - fx) / d) * s2;
+  gy = -sg * ((py - fy) / d) * s2;
+}
+
 // whole tile outside membrane m's grown box?  (uniform over the block)
 __device__ __forceinline__ bool tile_misses(const double* bx, double pxt, double pyt, double hd,
                                             double reach) {
@@ -421,7 +450,8 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
   __shared__ int s_base;
   __shared__ int b_seg[COUP_KEEP][NT];
   __shared__ double b_t[COUP_KEEP][NT];
-  __shared__ double b_sd[COUP_KEEP][NT];
+  __shared__ double b_gx[COUP_KEEP][NT];  // band_push direction of each band node
+  __shared__ double b_gy[COUP_KEEP][NT];
   const double reach = ca.r_cut + 1.0;
   const double hd = 0.5 * TILE2 * 1.41421356237309515;
   {
@@ -543,19 +573,26 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
               tb = tt;
             }
           }
-        double sd = 0.0;
         bool band = false;
+        double gx = 0.0, gy = 0.0;
         if (inbox && sb >= 0) {
           const double d = sqrt(d2b);
           const bool in = ring_side(X, n, o, sb, tb, px, py);
-          sd = in ? d : -d;
+          const double sd = in ? d : -d;
           band = d <= ca.r_cut;
-          Itot += band ? 0.5 * (1.0 + tanh(sd / (2.0 * ca.alpha))) : (in ? 1.0 : 0.0);
+          if (band) {
+            double s2;
+            Itot += profile_sech2(sd / (2.0 * ca.alpha), s2);
+            if (ca.want_force) band_push(X, n, sb, tb, px, py, sd, s2, gx, gy);
+          } else {
+            Itot += in ? 1.0 : 0.0;
+          }
         }
         if (slot < COUP_KEEP) {
           b_seg[slot][threadIdx.x] = band ? sb : -1;
           b_t[slot][threadIdx.x] = tb;
-          b_sd[slot][threadIdx.x] = sd;
+          b_gx[slot][threadIdx.x] = gx;
+          b_gy[slot][threadIdx.x] = gy;
         }
         continue;
       }
@@ -904,24 +941,28 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         ca.clb[cix] = keyw >= 0 ? __double2float_rd(lbw - 1e-3 - 1e-5 * fabs(lbw) + bx[7]) : 0.0f;
       }
       }  // !cached
-      double sd = 0.0;
       bool band = false;
+      double gx = 0.0, gy = 0.0;
       if (inbox && side >= 0) {
         Itot += side ? 1.0 : 0.0;
       } else if (inbox && sb >= 0) {
         const double d = sqrt(d2b);
         const bool in = ring_side(X, n, o, sb, tb, px, py);
-        sd = in ? d : -d;
+        const double sd = in ? d : -d;
         band = d <= ca.r_cut;
-        if (!band)
+        if (band) {
+          double s2;
+          Itot += profile_sech2(sd / (2.0 * ca.alpha), s2);
+          if (ca.want_force) band_push(X, n, sb, tb, px, py, sd, s2, gx, gy);
+        } else {
           Itot += in ? 1.0 : 0.0;
-        else
-          Itot += 0.5 * (1.0 + tanh(sd / (2.0 * ca.alpha)));
+        }
       }
       if (slot < COUP_KEEP) {
         b_seg[slot][threadIdx.x] = band ? sb : -1;
         b_t[slot][threadIdx.x] = tb;
-        b_sd[slot][threadIdx.x] = sd;
+        b_gx[slot][threadIdx.x] = gx;
+        b_gy[slot][threadIdx.x] = gy;
       }
     }
     if (valid) Ifield[node] = Itot;
@@ -950,9 +991,9 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         const int m = s_ml[slot];
         const int b = md.moff[m], n = md.moff[m + 1] - b;
         const int sb = b_seg[slot][threadIdx.x];
-        const double sd = b_sd[slot][threadIdx.x], tb = b_t[slot][threadIdx.x];
-        const double d = fabs(sd);
-        const bool live = sb >= 0 && d != 0.0;
+        const double tb = b_t[slot][threadIdx.x];
+        const double ux = b_gx[slot][threadIdx.x], uy = b_gy[slot][threadIdx.x];
+        const bool live = sb >= 0 && (ux != 0.0 || uy != 0.0);
         if (threadIdx.x == 0) s_base = -1;
         for (int i = threadIdx.x; i < COUP_FACC; i += NT) s_facc[i][0] = s_facc[i][1] = 0;
         __syncthreads();
@@ -961,19 +1002,9 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         const int base = s_base;
         if (base < 0) continue;  // no band node of this membrane in the tile (uniform)
         if (live) {
-          const double* bx = md.mbox + 8 * m;
-          const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
-          const double* X = md.X + 3 * b;
           const int s1 = (sb + 1 == n) ? 0 : sb + 1;
-          const double px = near_image((double)x, cx, ca.nx);
-          const double py = ca.wall_y ? (double)y : near_image((double)y, cy, ca.ny);
-          const double fx = X[3 * sb] + tb * (X[3 * s1] - X[3 * sb]);
-          const double fy = X[3 * sb + 1] + tb * (X[3 * s1 + 1] - X[3 * sb + 1]);
-          const double nxh = (px - fx) / d, nyh = (py - fy) / d;
-          const double sg = sd > 0.0 ? 1.0 : -1.0;
-          const double ch = cosh(sd / (2.0 * ca.alpha));
-          const double wgt = ca.kappa_c / (4.0 * ca.alpha) * (psi - Itot) / (ch * ch);
-          const double gx = -sg * nxh * wgt, gy = -sg * nyh * wgt;
+          const double wgt = ca.kappa_c / (4.0 * ca.alpha) * (psi - Itot);
+          const double gx = ux * wgt, gy = uy * wgt;
           const int vv[2] = {sb, s1};
           const double ww[2] = {1.0 - tb, tb};
 #pragma unroll
