@@ -850,7 +850,37 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
                   }
               }
             }
-            if (cslot && !wfar && nch == 1 && valid && g.inbox && tb >= 0) {
+            // several chunks: once every node's closest triangle is known,
+            // the chunks are staged again to bound the listed triangles that
+            // share no vertex with it (one chunk: still staged, below)
+            float o2m = 3.0e38f;
+            if (cslot && nch > 1) {  // uniform over the block
+              int v0 = -1, v1 = -1, v2 = -1;
+              if (valid && g.inbox && tb >= 0) {
+                const int* tv = mh.tri + 3 * (t0m + tb);
+                v0 = tv[0];
+                v1 = tv[1];
+                v2 = tv[2];
+              }
+              for (int c = 0; c < nch; c++) {
+                __syncthreads();
+                stage(c);
+                __syncthreads();
+                if (!wfar) {
+                  const int c0 = c * C3_LIST, cn = wave_list(c);
+                  if (v0 >= 0)
+                    for (int k = 0; k < cn; k++) {
+                      const int j = s_wl[wv][k];
+                      const int* uv = mh.tri + 3 * (t0m + s_id[c0 + j]);
+                      bool adj = false;
+#pragma unroll
+                      for (int a = 0; a < 3; a++) adj |= uv[a] == v0 || uv[a] == v1 || uv[a] == v2;
+                      if (!adj) o2m = fminf(o2m, geo_d2f(s_g, j, pn[0], pn[1], pn[2]));
+                    }
+                }
+              }
+            }
+            if (cslot && !wfar && valid && g.inbox && tb >= 0) {
               const double d = sqrt(d2b);
               if (d > ca.r_cut + COUP3_BEYOND) {
                 // well beyond the band: keep the side and the distance
@@ -863,16 +893,18 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
                 // its centre and those off the tile's list farther than cull
                 // from the tile centre; listed ones that share no vertex with
                 // tb are bounded by their FP32 distance less its rounding
-                const int* tv = mh.tri + 3 * (t0m + tb);
-                const int v0 = tv[0], v1 = tv[1], v2 = tv[2];
-                float o2 = 3.0e38f;
-                for (int k = 0; k < cnt; k++) {
-                  const int j = s_wl[wv][k];
-                  const int* uv = mh.tri + 3 * (t0m + s_id[j]);
-                  bool adj = false;
+                float o2 = o2m;
+                if (nch == 1) {
+                  const int* tv = mh.tri + 3 * (t0m + tb);
+                  const int v0 = tv[0], v1 = tv[1], v2 = tv[2];
+                  for (int k = 0; k < cnt; k++) {
+                    const int j = s_wl[wv][k];
+                    const int* uv = mh.tri + 3 * (t0m + s_id[j]);
+                    bool adj = false;
 #pragma unroll
-                  for (int a = 0; a < 3; a++) adj |= uv[a] == v0 || uv[a] == v1 || uv[a] == v2;
-                  if (!adj) o2 = fminf(o2, geo_d2f(s_g, j, pn[0], pn[1], pn[2]));
+                    for (int a = 0; a < 3; a++) adj |= uv[a] == v0 || uv[a] == v1 || uv[a] == v2;
+                    if (!adj) o2 = fminf(o2, geo_d2f(s_g, j, pn[0], pn[1], pn[2]));
+                  }
                 }
                 const double lout = fmin((double)cwr - rn4 - 0.01, (double)cull - rn8 - 0.02);
                 keyw = (m << C3_KEYB) | tb;
