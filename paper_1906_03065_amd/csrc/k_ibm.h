@@ -445,6 +445,8 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
   __shared__ double s_red[NT / 64];
   __shared__ float s_redf[NT / 64];
   __shared__ int s_ml[COUP_ML];  // membranes whose grown box meets the tile, ascending
+  __shared__ double s_mbx[COUP_ML][8];  // their boxes (the eight words of mbox)
+  __shared__ int s_mof[COUP_ML][2];     // and marker ranges [moff[m], moff[m + 1])
   __shared__ int s_mn, s_wc[NT / 64];
   __shared__ long long s_facc[COUP_FACC][2];  // coupling forces of one slot's markers, fixed point
   __shared__ int s_base;
@@ -467,35 +469,49 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     const double rn16 = 7.5 * 1.41421356237309515, rn8 = 3.5 * 1.41421356237309515;
     const bool valid = (x < ca.nx) && (y < ca.ny);
     const long long node = (long long)y * ca.nx + x;
-    // loads that depend on the node only are issued before the membrane
-    // list, so their latency overlaps it: the cache entries of the first
-    // COUP_CACHE slots and, for the force, the populations h_i that sum to psi
+    // The boxes of the first NT membranes, for the list below, are loaded
+    // first; then the loads that depend on the node only, whose latency the
+    // list overlaps: the cache entries of the first COUP_CACHE slots and, for
+    // the force, the populations h_i that sum to psi.  Every lane issues all
+    // of them (indices clamped, selected afterwards), so the list waits for
+    // the boxes alone: waits count outstanding loads in issue order.
+    const int mq = min((int)threadIdx.x, md.K - 1);
+    double mbq[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) mbq[k] = md.mbox[8 * mq + k];
+    const int mo0 = md.moff[mq], mo1 = md.moff[mq + 1];
+    asm volatile("" ::: "memory");
+    const int xc = min(x, ca.nx - 1), yc = min(y, ca.ny - 1);
+    const long long cnode = (long long)yc * ca.nx + xc;
+    // (read only for nodes inside a membrane's grown box, which are valid,
+    // and only with the cache on)
     int kpre[COUP_CACHE];
     float lpre[COUP_CACHE];
+    {
+      const bool on = ca.ckey != nullptr;
+      const int* kp = on ? ca.ckey : md.status;
+      const float* lp = on ? ca.clb : (const float*)md.status;
 #pragma unroll
-    for (int c = 0; c < COUP_CACHE; c++) {
-      kpre[c] = -1;
-      lpre[c] = 0.0f;
-      if (ca.ckey != nullptr && valid) {
-        kpre[c] = ca.ckey[(long long)c * ca.N + node];
-        lpre[c] = ca.clb[(long long)c * ca.N + node];
+      for (int c = 0; c < COUP_CACHE; c++) {
+        const long long e = on ? (long long)c * ca.N + cnode : 0;
+        kpre[c] = kp[e];
+        lpre[c] = lp[e];
       }
     }
-    double hrest = 0.0;
     R hmov[8];
-    if (ca.want_force && valid) {
+    const double hrest = cur.rest(2, cnode);
+    {
       using L = Lattice<9>;
-      hrest = cur.rest(2, node);
 #pragma unroll
       for (int i = 1; i < 9; i++) {
-        const int sy = y - L::cy[i];
+        const int sy = yc - L::cy[i];
         long long sn;
         int dir = i;
         if (ca.wall_y && (sy < 0 || sy >= ca.ny)) {
-          sn = node;
+          sn = cnode;
           dir = L::opp[i];
         } else {
-          sn = (long long)wrap(sy, ca.ny) * ca.nx + wrap(x - L::cx[i], ca.nx);
+          sn = (long long)wrap(sy, ca.ny) * ca.nx + wrap(xc - L::cx[i], ca.nx);
         }
         hmov[i - 1] = cur.template load<R>(2, dir, sn);
       }
@@ -509,13 +525,13 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       pxt = xt + (near_image((double)(tx * TILE2), cx, ca.nx) - tx * TILE2);
       pyt = ca.wall_y ? yt : yt + (near_image((double)(ty * TILE2), cy, ca.ny) - ty * TILE2);
     };
-    auto meets = [&](int m) {
-      const double* bx = md.mbox + 8 * m;
-      const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
+    auto meets_box = [&](double b0, double b1, double b3, double b4) {
+      const double cx = 0.5 * (b0 + b3), cy = 0.5 * (b1 + b4);
       double pxt, pyt;
       tile_image(cx, cy, pxt, pyt);
       const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
-      return split || !tile_misses(bx, pxt, pyt, hd, reach);
+      const double bb[6] = {b0, b1, 0.0, b3, b4, 0.0};
+      return split || !tile_misses(bb, pxt, pyt, hd, reach);
     };
     // the membranes this tile meets, tested in parallel and listed in
     // ascending order (ordered compaction by ballots)
@@ -523,7 +539,23 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     __syncthreads();
     for (int c0 = 0; c0 < md.K; c0 += NT) {
       const int m = c0 + threadIdx.x;
-      const bool mt = m < md.K && meets(m);
+      double bv[8];
+      int ov[2];
+      if (c0 == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) bv[k] = mbq[k];
+        ov[0] = mo0;
+        ov[1] = mo1;
+      } else if (m < md.K) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) bv[k] = md.mbox[8 * m + k];
+        ov[0] = md.moff[m];
+        ov[1] = md.moff[m + 1];
+        // (more than NT membranes) these loads complete here, so that no
+        // wait after the list has to cover the node's loads issued above
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      }
+      const bool mt = m < md.K && meets_box(bv[0], bv[1], bv[3], bv[4]);
       const unsigned long long mk = __ballot(mt);
       if (lane == 0) s_wc[wv] = __popcll(mk);
       __syncthreads();
@@ -532,7 +564,14 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         off += w < wv ? s_wc[w] : 0;
         tot += s_wc[w];
       }
-      if (mt && off + __popcll(mk & below) < COUP_ML) s_ml[off + __popcll(mk & below)] = m;
+      const int pos = off + __popcll(mk & below);
+      if (mt && pos < COUP_ML) {
+        s_ml[pos] = m;
+#pragma unroll
+        for (int k = 0; k < 8; k++) s_mbx[pos][k] = bv[k];
+        s_mof[pos][0] = ov[0];
+        s_mof[pos][1] = ov[1];
+      }
       __syncthreads();
       if (threadIdx.x == 0) s_mn += tot;
       __syncthreads();
@@ -546,12 +585,12 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     const bool shortcut = ca.r_cut > rn8 + 1.0;
     for (int slot = 0; slot < min(nm, COUP_ML); slot++) {
       const int m = s_ml[slot];
-      const double* bx = md.mbox + 8 * m;
+      const double* bx = s_mbx[slot];
       const double cx = 0.5 * (bx[0] + bx[3]), cy = 0.5 * (bx[1] + bx[4]);
       double pxt, pyt;
       tile_image(cx, cy, pxt, pyt);
       const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
-      const int b = md.moff[m], n = md.moff[m + 1] - b;
+      const int b = s_mof[slot][0], n = s_mof[slot][1] - b;
       const double* X = md.X + 3 * b;
       const double o = bx[6];
       const double px = near_image((double)x, cx, ca.nx);
@@ -988,8 +1027,7 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       // the markers with one global atomic each; a marker out of the LDS
       // window is added directly
       for (int slot = 0; slot < nk; slot++) {
-        const int m = s_ml[slot];
-        const int b = md.moff[m], n = md.moff[m + 1] - b;
+        const int b = s_mof[slot][0], n = s_mof[slot][1] - b;
         const int sb = b_seg[slot][threadIdx.x];
         const double tb = b_t[slot][threadIdx.x];
         const double ux = b_gx[slot][threadIdx.x], uy = b_gy[slot][threadIdx.x];
