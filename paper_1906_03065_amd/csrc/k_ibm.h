@@ -672,25 +672,38 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
               side = sk == 0xFFFE ? 1 : 0;
             } else {
               // the kept segment and COUP_WIN on each side (lowest index on
-              // equal distances, whatever the order), walked along the ring
-              // so each vertex is loaded once
+              // equal distances, whatever the order), walked along the ring;
+              // each vertex is loaded two segments before it is needed, so
+              // the loads of three vertices are in flight at once
+              constexpr int NW = 2 * COUP_WIN + 2;  // vertices of the window
+              auto nxt = [&](int v) { return (v + 1 == n) ? 0 : v + 1; };
               int q = (sk - COUP_WIN) % n;
               if (q < 0) q += n;
+              int q1 = nxt(q), q2 = nxt(q1);
               double ax = X[3 * q], ay = X[3 * q + 1];
+              double b1x = X[3 * q1], b1y = X[3 * q1 + 1];
+              double b2x = X[3 * q2], b2y = X[3 * q2 + 1];
 #pragma unroll
-              for (int k = 0; k <= 2 * COUP_WIN; k++) {
-                const int q1 = (q + 1 == n) ? 0 : q + 1;
-                const double bx_ = X[3 * q1], by_ = X[3 * q1 + 1];
+              for (int k = 0; k + 1 < NW; k++) {
+                // vertex k + 3 (the last ones load their predecessor again)
+                const int q3 = k + 3 < NW ? nxt(q2) : q2;
+                const double b3x = X[3 * q3], b3y = X[3 * q3 + 1];
                 double tt;
-                const double d2 = seg_d2(px, py, ax, ay, bx_, by_, tt);
+                const double d2 = seg_d2(px, py, ax, ay, b1x, b1y, tt);
                 if (d2 < d2b || (d2 == d2b && q < sb)) {
                   d2b = d2;
                   sb = q;
                   tb = tt;
                 }
-                ax = bx_;
-                ay = by_;
                 q = q1;
+                q1 = q2;
+                q2 = q3;
+                ax = b1x;
+                ay = b1y;
+                b1x = b2x;
+                b1y = b2y;
+                b2x = b3x;
+                b2y = b3y;
               }
               ok = sqrt(d2b) < thr;
             }
