@@ -377,13 +377,6 @@ __device__ __forceinline__ void band_push(const double* X, int n, int s, double 
   gy = -sg * ((py - fy) / d) * s2;
 }
 
-// whole tile outside membrane m's grown box?  (uniform over the block)
-__device__ __forceinline__ bool tile_misses(const double* bx, double pxt, double pyt, double hd,
-                                            double reach) {
-  return pxt + hd < bx[0] - reach || pxt - hd > bx[3] + reach || pyt + hd < bx[1] - reach ||
-         pyt - hd > bx[4] + reach;
-}
-
 // do the nodes of the tile starting at s (width TILE2, lattice n) fall into
 // different periodic images relative to centre c?  (the tile straddles the
 // antipode of c; its nodes are then searched one by one)
@@ -525,13 +518,26 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
       pxt = xt + (near_image((double)(tx * TILE2), cx, ca.nx) - tx * TILE2);
       pyt = ca.wall_y ? yt : yt + (near_image((double)(ty * TILE2), cy, ca.ny) - ty * TILE2);
     };
+    // Per axis, the grown box [lo - reach, hi + reach] against the tile: the
+    // square of half-width hd around the tile centre's image, or, when the
+    // tile's nodes fall into two images (it straddles the antipode of the box
+    // centre c), each image's run of nodes: from the first node's image up to
+    // c + n/2, and from c - n/2 up to the last node's image (the grown box is
+    // narrower than the period, so it reaches neither c + n/2 nor c - n/2).
+    auto axis_meets = [&](int s0, int n, double c, double lo, double hi, double pt, bool split) {
+      if (split) {
+        const int e = min(s0 + TILE2 - 1, n - 1);
+        return near_image((double)s0, c, n) <= hi + reach || near_image((double)e, c, n) >= lo - reach;
+      }
+      return !(pt + hd < lo - reach || pt - hd > hi + reach);
+    };
     auto meets_box = [&](double b0, double b1, double b3, double b4) {
       const double cx = 0.5 * (b0 + b3), cy = 0.5 * (b1 + b4);
       double pxt, pyt;
       tile_image(cx, cy, pxt, pyt);
-      const bool split = tile_splits(tx * TILE2, ca.nx, cx) || (!ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy));
-      const double bb[6] = {b0, b1, 0.0, b3, b4, 0.0};
-      return split || !tile_misses(bb, pxt, pyt, hd, reach);
+      const bool sx = tile_splits(tx * TILE2, ca.nx, cx);
+      const bool sy = !ca.wall_y && tile_splits(ty * TILE2, ca.ny, cy);
+      return axis_meets(tx * TILE2, ca.nx, cx, b0, b3, pxt, sx) && axis_meets(ty * TILE2, ca.ny, cy, b1, b4, pyt, sy);
     };
     // the membranes this tile meets, tested in parallel and listed in
     // ascending order (ordered compaction by ballots)
