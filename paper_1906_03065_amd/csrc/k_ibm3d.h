@@ -207,6 +207,7 @@ __device__ __forceinline__ TileGeo tile_geo(const double* bx, const double* ct, 
   g.miss = false;
   g.split = false;
   g.inbox = valid;
+  bool far = false;  // a split axis whose two runs of nodes both miss the grown box
   for (int a = 0; a < 3; a++) {
     const double cm = 0.5 * (bx[a] + bx[3 + a]);
     // the image of the tile's first node: the nodes of a tile that does not
@@ -214,20 +215,25 @@ __device__ __forceinline__ TileGeo tile_geo(const double* bx, const double* ct, 
     // beyond the antipode
     g.pc[a] = ct[a] + (near_img((double)t0[a], cm, dims[a], per[a]) - t0[a]);
     g.pp[a] = near_img((double)xi[a], cm, dims[a], per[a]);
+    const bool out = g.pc[a] + hd < bx[a] - reach || g.pc[a] - hd > bx[3 + a] + reach;
     if (g.pp[a] < bx[a] - reach || g.pp[a] > bx[3 + a] + reach) g.inbox = false;
-    const int s0 = t0[a], s1 = min(t0[a] + TILE3 - 1, dims[a] - 1);
-    const double i0 = near_img((double)s0, cm, dims[a], per[a]), i1 = near_img((double)s1, cm, dims[a], per[a]);
-    if (per[a] && i0 - s0 != i1 - s1) {
-      // the tile's nodes fall into two images (it straddles the antipode of
-      // the box centre): the first image's nodes run from i0 up to the
-      // antipode, the second image's from the antipode up to i1, and the
-      // grown box, narrower than the period, reaches neither antipode side
-      g.split = true;
-      if (!(i0 <= bx[3 + a] + reach || i1 >= bx[a] - reach)) g.miss = true;
-    } else if (g.pc[a] + hd < bx[a] - reach || g.pc[a] - hd > bx[3 + a] + reach) {
-      g.miss = true;
+    bool sa = false;
+    if (per[a]) {
+      const int s0 = t0[a], s1 = min(t0[a] + TILE3 - 1, dims[a] - 1);
+      const double i0 = near_img((double)s0, cm, dims[a], 1), i1 = near_img((double)s1, cm, dims[a], 1);
+      if (i0 - s0 != i1 - s1) {
+        // the tile's nodes fall into two images (it straddles the antipode
+        // of the box centre): the first image's nodes run from i0 up to the
+        // antipode, the second image's from the antipode up to i1, and the
+        // grown box, narrower than the period, reaches neither antipode side
+        sa = true;
+        far |= !(i0 <= bx[3 + a] + reach || i1 >= bx[a] - reach);
+      }
     }
+    g.split |= sa;
+    if (!sa) g.miss |= out;
   }
+  g.miss |= far;
   return g;
 }
 
