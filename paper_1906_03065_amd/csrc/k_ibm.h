@@ -324,28 +324,34 @@ struct CoupArgs {
 // inside test at the closest feature of a ring (markers X, n of them,
 // orientation o = +1 counter-clockwise): the side of segment s at parameter
 // t, or at an end vertex the side of the sum of the two edge normals
-__device__ __forceinline__ bool ring_side(const double* X, int n, double o, int s, double t,
-                                          double px, double py) {
+__device__ __forceinline__ bool ring_side_ab(const double* X, int n, double o, int s, double t, double ax,
+                                             double ay, double bx, double by, double px, double py) {
   const int s1 = (s + 1 == n) ? 0 : s + 1;
-  const double ax = X[3 * s], ay = X[3 * s + 1], bx = X[3 * s1], by = X[3 * s1 + 1];
   if (t > 0.0 && t < 1.0) return o * ((bx - ax) * (py - ay) - (by - ay) * (px - ax)) > 0.0;
-  int v, u, w;  // vertex, previous, next
+  // the closest point is a vertex v: its edges from the previous vertex u
+  // and to the next w (one of them is the segment itself)
+  double vx, vy, ux, uy, wx, wy;
   if (t <= 0.0) {
-    v = s;
-    u = (s == 0) ? n - 1 : s - 1;
-    w = s1;
+    const int u = (s == 0) ? n - 1 : s - 1;
+    vx = ax, vy = ay, wx = bx, wy = by;
+    ux = X[3 * u], uy = X[3 * u + 1];
   } else {
-    v = s1;
-    u = s;
-    w = (s1 + 1 == n) ? 0 : s1 + 1;
+    const int w = (s1 + 1 == n) ? 0 : s1 + 1;
+    vx = bx, vy = by, ux = ax, uy = ay;
+    wx = X[3 * w], wy = X[3 * w + 1];
   }
-  const double vx = X[3 * v], vy = X[3 * v + 1];
-  const double e1x = vx - X[3 * u], e1y = vy - X[3 * u + 1];
-  const double e2x = X[3 * w] - vx, e2y = X[3 * w + 1] - vy;
+  const double e1x = vx - ux, e1y = vy - uy;
+  const double e2x = wx - vx, e2y = wy - vy;
   const double l1 = sqrt(e1x * e1x + e1y * e1y), l2 = sqrt(e2x * e2x + e2y * e2y);
   // left normals (-ey, ex) of both edges, summed
   const double nx_ = -e1y / l1 - e2y / l2, ny_ = e1x / l1 + e2x / l2;
   return o * (nx_ * (px - vx) + ny_ * (py - vy)) > 0.0;
+}
+
+__device__ __forceinline__ bool ring_side(const double* X, int n, double o, int s, double t, double px,
+                                          double py) {
+  const int s1 = (s + 1 == n) ? 0 : s + 1;
+  return ring_side_ab(X, n, o, s, t, X[3 * s], X[3 * s + 1], X[3 * s1], X[3 * s1 + 1], px, py);
 }
 
 // profile value 0.5 (1 + tanh x) of eq. Iprofile (x = d / (2 alpha), d the
@@ -359,19 +365,18 @@ __device__ __forceinline__ double profile_sech2(double x, double& s2) {
 }
 
 // A band node at signed distance sd (|sd| = d) from the closest point of
-// segment s (parameter t): the direction in which the coupling energy pushes
+// the segment from a to b (parameter t): the direction in which the coupling energy pushes
 // the segment's vertices, -sign(sd) nhat sech^2(sd / (2 alpha)) with nhat the
 // unit vector from the closest point to the node (eq. DiscreteCF without the
 // factor kappa_c / (4 alpha) (psi - I) and the vertex weights).  Zero for a
 // node on the ring, where nhat is undefined.
-__device__ __forceinline__ void band_push(const double* X, int n, int s, double t, double px, double py,
-                                          double sd, double s2, double& gx, double& gy) {
+__device__ __forceinline__ void band_push(double ax, double ay, double bx, double by, double t, double px,
+                                          double py, double sd, double s2, double& gx, double& gy) {
   const double d = fabs(sd);
   gx = gy = 0.0;
   if (d == 0.0) return;
-  const int s1 = (s + 1 == n) ? 0 : s + 1;
-  const double fx = X[3 * s] + t * (X[3 * s1] - X[3 * s]);
-  const double fy = X[3 * s + 1] + t * (X[3 * s1 + 1] - X[3 * s + 1]);
+  const double fx = ax + t * (bx - ax);
+  const double fy = ay + t * (by - ay);
   const double sg = sd > 0.0 ? 1.0 : -1.0;
   gx = -sg * ((px - fx) / d) * s2;
   gy = -sg * ((py - fy) / d) * s2;
@@ -622,13 +627,15 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         double gx = 0.0, gy = 0.0;
         if (inbox && sb >= 0) {
           const double d = sqrt(d2b);
-          const bool in = ring_side(X, n, o, sb, tb, px, py);
+          const int sb1 = (sb + 1 == n) ? 0 : sb + 1;
+          const double eax = X[3 * sb], eay = X[3 * sb + 1], ebx = X[3 * sb1], eby = X[3 * sb1 + 1];
+          const bool in = ring_side_ab(X, n, o, sb, tb, eax, eay, ebx, eby, px, py);
           const double sd = in ? d : -d;
           band = d <= ca.r_cut;
           if (band) {
             double s2;
             Itot += profile_sech2(sd / (2.0 * ca.alpha), s2);
-            if (ca.want_force) band_push(X, n, sb, tb, px, py, sd, s2, gx, gy);
+            if (ca.want_force) band_push(eax, eay, ebx, eby, tb, px, py, sd, s2, gx, gy);
           } else {
             Itot += in ? 1.0 : 0.0;
           }
@@ -1005,13 +1012,15 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
         Itot += side ? 1.0 : 0.0;
       } else if (inbox && sb >= 0) {
         const double d = sqrt(d2b);
-        const bool in = ring_side(X, n, o, sb, tb, px, py);
+        const int sb1 = (sb + 1 == n) ? 0 : sb + 1;
+        const double eax = X[3 * sb], eay = X[3 * sb + 1], ebx = X[3 * sb1], eby = X[3 * sb1 + 1];
+        const bool in = ring_side_ab(X, n, o, sb, tb, eax, eay, ebx, eby, px, py);
         const double sd = in ? d : -d;
         band = d <= ca.r_cut;
         if (band) {
           double s2;
           Itot += profile_sech2(sd / (2.0 * ca.alpha), s2);
-          if (ca.want_force) band_push(X, n, sb, tb, px, py, sd, s2, gx, gy);
+          if (ca.want_force) band_push(eax, eay, ebx, eby, tb, px, py, sd, s2, gx, gy);
         } else {
           Itot += in ? 1.0 : 0.0;
         }
