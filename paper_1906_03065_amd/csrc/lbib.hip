@@ -448,7 +448,7 @@ struct Engine2D final : lbib_sim {
     TileMap tm = tilemap();
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
     hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, 1, p.wall_y,
-                       0, 2, r_cut + 3.0);
+                       0, 2, map_reach2(r_cut));
   }
   // profile field and coupling forces on the active tiles
   void profile_pass(int want_force) {

@@ -19,8 +19,8 @@ def _mixed(count=7, seed=11):
     for k in range(count):
         n = int(g.choice([80, 96, 112, 144, 200, 272, 320]))
         ny = n + int(g.integers(-8, 9))
-        # the coupling band (r_cut + 3 = 20 around the capsule) must fit in
-        # the period: 2 R + 40 < n
+        # the tile map (r_cut + 1 = 18 around the capsule) must fit in the
+        # period: 2 R + 36 < n (kept at 2 R + 40)
         R = float(g.uniform(8.0, min(0.25 * min(n, ny), (n - 41) / 2.0)))
         nm = int(min(384, max(64, np.ceil(2 * np.pi * R / 0.8))))
         kap = g.uniform(0.01, 0.05, 3)

@@ -223,7 +223,7 @@ def test_c2_fullsize_fp32_vs_oracle(orc):
 
 @pytest.mark.parametrize("wall_y", [1, 0])
 def test_fp64_parity_band_near_period(orc, wall_y):
-    """Capsule band (r_cut + 3 around the ring) nearly as wide as the
+    """Capsule band (r_cut + 1 around the ring) nearly as wide as the
     periodic lattice: tiles that straddle the antipode of the capsule hold
     nodes of two periodic images and are searched node by node."""
     w = W.capsule_at_interface(nx=80, ny=82, R=18.5, n_markers=144, centre=(37.3, 40.2),
