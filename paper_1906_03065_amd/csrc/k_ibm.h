@@ -478,8 +478,9 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     // first; then the loads that depend on the node only, whose latency the
     // list overlaps: the cache entries of the first COUP_CACHE slots and, for
     // the force, the populations h_i that sum to psi.  Every lane issues all
-    // of them (indices clamped, selected afterwards), so the list waits for
-    // the boxes alone: waits count outstanding loads in issue order.
+    // of them (indices clamped: a lane past the lattice edge, or without the
+    // cache, reads a valid location whose value it never uses), so the list
+    // waits for the boxes alone: waits count outstanding loads in issue order.
     const int mq = min((int)threadIdx.x, md.K - 1);
     double mbq[8];
 #pragma unroll
@@ -488,8 +489,6 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     asm volatile("" ::: "memory");
     const int xc = min(x, ca.nx - 1), yc = min(y, ca.ny - 1);
     const long long cnode = (long long)yc * ca.nx + xc;
-    // (read only for nodes inside a membrane's grown box, which are valid,
-    // and only with the cache on)
     int kpre[COUP_CACHE];
     float lpre[COUP_CACHE];
     {
