@@ -166,11 +166,10 @@ int lbib_energy(lbib_sim* s, lbib_energies* out);
 /* Finiteness check of the populations (FP64 sums): LBIB_ENONFINITE when a
    population is NaN or infinite; LBIB_EUNSTABLE when, during the last steps,
    a marker force left the fixed-point range, a membrane's grown box (box +
-   max(r_cut + 1, 3) each side in 2D, r_cut + 3 in 3D) was as wide as a
-   period, or a tile of the coupling
-   pass lay within reach (r_cut + 1) of more membranes than it keeps band data
-   for (four in 2D, two in 3D; then the excess membranes' coupling forces on
-   that tile are lost).  Synchronises. */
+   max(r_cut + 1, 3) each side) was as wide as a period, or a tile of the
+   coupling pass lay within reach (r_cut + 1) of more membranes than it keeps
+   band data for (four in 2D, two in 3D; then the excess membranes' coupling
+   forces on that tile are lost).  Synchronises. */
 int lbib_check(lbib_sim* s);
 
 /* Device view of an internal array for zero-copy inspection:

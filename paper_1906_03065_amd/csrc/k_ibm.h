@@ -5,8 +5,7 @@
 // (eqs. Interpolation, UpdatedXl).  All marker arithmetic is FP64.
 //
 // Active tiles: every lattice tile (TILE x TILE nodes) that meets a
-// membrane's bounding box grown by map_reach2(r_cut) (r_cut + 3 for the 3D
-// cubes).  Only these tiles carry a
+// membrane's bounding box grown by map_reach(r_cut).  Only these tiles carry a
 // profile I different from 0, a spread force, or a stored total force; the
 // fused lattice kernel reads the maps there and nowhere else.  A tile is
 // active in a step when its flag equals that step's stamp, so no pass is
@@ -355,11 +354,12 @@ __device__ __forceinline__ bool ring_side(const double* X, int n, double o, int 
   return ring_side_ab(X, n, o, s, t, X[3 * s], X[3 * s + 1], X[3 * s1], X[3 * s1 + 1], px, py);
 }
 
-// How far beyond a membrane's box the 2D tile map reaches: the coupling
-// pass takes a membrane for a tile within r_cut + 1 of its box (beyond, the
-// profile is 0 and no force arises), and spreading writes up to two nodes
-// beyond the markers, which the lattice kernel reads on mapped tiles only.
-__host__ __device__ __forceinline__ double map_reach2(double r_cut) { return fmax(r_cut + 1.0, 3.0); }
+// How far beyond a membrane's box the tile map reaches (2D and 3D): the
+// coupling pass takes a membrane for a tile within r_cut + 1 of its box
+// (beyond, the profile is 0 and no force arises), and spreading writes up to
+// two nodes beyond the markers, which the lattice kernels read on mapped
+// tiles only.
+__host__ __device__ __forceinline__ double map_reach(double r_cut) { return fmax(r_cut + 1.0, 3.0); }
 
 // profile value 0.5 (1 + tanh x) of eq. Iprofile (x = d / (2 alpha), d the
 // signed distance) and sech^2 x, the factor of the coupling force (eq.

@@ -448,7 +448,7 @@ struct Engine2D final : lbib_sim {
     TileMap tm = tilemap();
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
     hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, 1, p.wall_y,
-                       0, 2, map_reach2(r_cut));
+                       0, 2, map_reach(r_cut));
   }
   // profile field and coupling forces on the active tiles
   void profile_pass(int want_force) {
@@ -708,7 +708,7 @@ struct Engine3D final : lbib_sim {
     TileMap tm = tilemap();
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
     hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, p.nz, p.wall_y,
-                       p.wall_z, 3, r_cut + 3.0);
+                       p.wall_z, 3, map_reach(r_cut));
     hipLaunchKernelGGL(k_facenormals, dim3((ntri + 255) / 256), dim3(256), 0, stream, md, mh);
     hipLaunchKernelGGL(k_meshvolume<256>, dim3(K), dim3(256), 0, stream, md, mh);
     hipLaunchKernelGGL(k_vertexnormals, dim3((M + 255) / 256), dim3(256), 0, stream, md, mh);
