@@ -323,7 +323,8 @@ struct CoupArgs {
 
 // inside test at the closest feature of a ring (markers X, n of them,
 // orientation o = +1 counter-clockwise): the side of segment s at parameter
-// t, or at an end vertex the side of the sum of the two edge normals
+// t, or at an end vertex the side of the sum of the two edge normals;
+// (ax, ay) and (bx, by) are the end points of s, already loaded
 __device__ __forceinline__ bool ring_side_ab(const double* X, int n, double o, int s, double t, double ax,
                                              double ay, double bx, double by, double px, double py) {
   const int s1 = (s + 1 == n) ? 0 : s + 1;
