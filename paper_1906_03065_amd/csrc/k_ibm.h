@@ -373,11 +373,11 @@ __device__ __forceinline__ double profile_sech2(double x, double& s2) {
 }
 
 // A band node at signed distance sd (|sd| = d) from the closest point of
-// the segment from a to b (parameter t): the direction in which the coupling energy pushes
-// the segment's vertices, -sign(sd) nhat sech^2(sd / (2 alpha)) with nhat the
-// unit vector from the closest point to the node (eq. DiscreteCF without the
-// factor kappa_c / (4 alpha) (psi - I) and the vertex weights).  Zero for a
-// node on the ring, where nhat is undefined.
+// the segment from a to b (parameter t): the direction in which the coupling
+// energy pushes the segment's vertices, -sign(sd) nhat sech^2(sd / (2 alpha))
+// with nhat the unit vector from the closest point to the node (eq.
+// DiscreteCF without the factor kappa_c / (4 alpha) (psi - I) and the vertex
+// weights).  Zero for a node on the ring, where nhat is undefined.
 __device__ __forceinline__ void band_push(double ax, double ay, double bx, double by, double t, double px,
                                           double py, double sd, double s2, double& gx, double& gy) {
   const double d = fabs(sd);
