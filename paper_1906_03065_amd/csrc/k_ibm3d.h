@@ -514,6 +514,22 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
     const int xi[3] = {t0[0] + off[0], t0[1] + off[1], t0[2] + off[2]};
     const bool valid = xi[0] < ca.nx && xi[1] < ca.ny && xi[2] < ca.nz;
     const long long nodeid = valid ? ((long long)xi[2] * ca.ny + xi[1]) * ca.nx + xi[0] : 0;
+    // the node's cache entries of both slots, loaded before the membrane loop
+    // so that their latency overlaps the tile geometry (read only for a valid
+    // node inside a grown box, and only with the cache on)
+    int kpre[COUP3_CACHE];
+    float lpre[COUP3_CACHE];
+    {
+      const bool on = ca.ckey != nullptr;
+      const int* kp = on ? ca.ckey : md.status;
+      const float* lp = on ? ca.clb : (const float*)md.status;
+#pragma unroll
+      for (int c = 0; c < COUP3_CACHE; c++) {
+        const long long e = on ? (long long)c * ca.N + nodeid : 0;
+        kpre[c] = kp[e];
+        lpre[c] = lp[e];
+      }
+    }
     const double ct[3] = {t0[0] + 0.5 * (TILE3 - 1), t0[1] + 0.5 * (TILE3 - 1), t0[2] + 0.5 * (TILE3 - 1)};
     double Itot = 0.0;
     int kept = 0;
@@ -538,10 +554,17 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
         bool ok = true;
         int side = -1;
         if (valid && g.inbox) {
-          const int key = ca.ckey[cix];
+          int key = kpre[0];
+          float klb = lpre[0];
+#pragma unroll
+          for (int c = 1; c < COUP3_CACHE; c++)
+            if (slot == c) {
+              key = kpre[c];
+              klb = lpre[c];
+            }
           ok = key >= 0 && (key >> C3_KEYB) == m;
           if (ok) {
-            const double thr = (double)ca.clb[cix] - drift;
+            const double thr = (double)klb - drift;
             const int q = key & ((1 << C3_KEYB) - 1);
             if (q >= C3_OUT) {
               ok = thr > ca.r_cut;
