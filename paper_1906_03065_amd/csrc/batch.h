@@ -64,7 +64,7 @@ __global__ __launch_bounds__(NT) void kb_tiles(const BMember<St>* T, const int2*
   const TileMap tm = T[e.x].tm;
   const LBParams P = T[e.x].P;
   const double rc = T[e.x].ca.r_cut;
-  tiles_run<NT>(md, tm, P.nx, P.ny, 1, P.wall_y, 0, 2, map_reach(rc), e.y);
+  tiles_run<NT>(md, tm, P.nx, P.ny, 1, P.wall_y, 0, 2, map_reach(rc), e.y, tm.tstate[1], tm.tstate);
 }
 
 // persistent: the active tiles of all members

@@ -67,7 +67,8 @@ struct MemDev {
 struct TileMap {
   int* tflag;         // per tile: stamp of the last step it was active in
   int* tlist;         // active tiles of this step
-  int* tstate;        // [0] active-tile count, [1] stamp of this step, [2] 3D tile counter
+  int* tstate;        // [0] active-tile count, [1] stamp of this step, [2] 3D tile counter,
+                      // [4], [5] active-tile counts of a 2D simulation, by stamp parity
   int ntx, nty, ntz, tile;
 };
 
@@ -147,9 +148,9 @@ __device__ float block_minf(float v, float* sh) {
 }
 
 // ---------------------------------------------------------------------------
-// start of a step: new stamp, empty active-tile list (one thread)
-// new step of the tile map: [0] active-tile count, [1] stamp, [2] counter
-// the 3D profile kernel's workgroups take tiles from
+// new step of the tile map (3D simulations and batch members; one thread):
+// [0] active-tile count, [1] stamp, [2] counter the 3D profile kernel's
+// workgroups take tiles from
 __global__ void k_begin(int* tstate) {
   if (threadIdx.x == 0) {
     tstate[0] = 0;
@@ -161,11 +162,11 @@ __global__ void k_begin(int* tstate) {
 // bounding box, orientation and active tiles of membrane blockIdx.x
 template <int NT>
 __device__ __forceinline__ void tiles_run(const MemDev& md, const TileMap& tm, int nx, int ny, int nz,
-                                          int wall_y, int wall_z, int D, double reach, int m) {
+                                          int wall_y, int wall_z, int D, double reach, int m, int stamp,
+                                          int* __restrict__ cnt) {
   __shared__ double sh[8 * (NT / 64)];
   const int tid = threadIdx.x;
   const int b = md.moff[m], e = md.moff[m + 1], n = e - b;
-  const int stamp = tm.tstate[1];
   // one pass over the markers: box (minima of X and of -X), largest step of
   // the last marker update |U| (each step adds it to the membrane's drift
   // bound; a call between steps adds it again, which only loosens the bound)
@@ -255,17 +256,31 @@ __device__ __forceinline__ void tiles_run(const MemDev& md, const TileMap& tm, i
     if (mk) {
       const int lane = tid & 63, lead = __ffsll((long long)mk) - 1;
       int base = 0;
-      if (lane == lead) base = atomicAdd(&tm.tstate[0], __popcll(mk));
+      if (lane == lead) base = atomicAdd(cnt, __popcll(mk));
       base = __shfl(base, lead, 64);
       if (fresh) tm.tlist[base + __popcll(mk & ((1ull << lane) - 1ull))] = t;
     }
   }
 }
 
+// stamp > 0: this pass's stamp, chosen by the host (a 2D simulation); the
+// tiles are counted in tstate[4 + (stamp & 1)], and the first thread
+// publishes the stamp and empties the other counter for the next pass.
+// stamp 0: the stamp and the empty counter tstate[0] that k_begin prepared.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_tiles(MemDev md, TileMap tm, int nx, int ny, int nz,
-                                              int wall_y, int wall_z, int D, double reach) {
-  tiles_run<NT>(md, tm, nx, ny, nz, wall_y, wall_z, D, reach, (int)blockIdx.x);
+                                              int wall_y, int wall_z, int D, double reach, int stamp) {
+  int* cnt = tm.tstate;
+  if (stamp > 0) {
+    cnt = tm.tstate + 4 + (stamp & 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      tm.tstate[1] = stamp;
+      tm.tstate[4 + ((stamp + 1) & 1)] = 0;
+    }
+  } else {
+    stamp = tm.tstate[1];
+  }
+  tiles_run<NT>(md, tm, nx, ny, nz, wall_y, wall_z, D, reach, (int)blockIdx.x, stamp, cnt);
 }
 
 // FP32 squared distance from p to the segment (s.x, s.y) + t (s.z, s.w)
@@ -1118,8 +1133,9 @@ template <class St, typename R, int NT>
 // (the LDS of a workgroup leaves room for two per CU: registers are sized
 // for two waves per SIMD)
 __global__ __launch_bounds__(NT, 2) void k_coupling2d(MemDev md, TileMap tm, CoupArgs ca,
-                                                   double* __restrict__ Ifield, St cur) {
-  const int ntl = tm.tstate[0];
+                                                   double* __restrict__ Ifield, St cur,
+                                                   const int* __restrict__ cnt) {
+  const int ntl = *cnt;  // active tiles (the counter the tile pass used)
   for (int li = blockIdx.x; li < ntl; li += gridDim.x) coupling2d_tile<St, R, NT>(md, tm, ca, Ifield, cur, li);
 }
 

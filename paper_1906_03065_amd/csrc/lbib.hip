@@ -442,19 +442,30 @@ struct Engine2D final : lbib_sim {
     return c;
   }
 
+  // stamp of the last tile pass: the host chooses it for a simulation of its
+  // own (one launch fewer per step); a batch member's stamps advance on the
+  // device with its batch, so it keeps the begin kernel
+  int tile_stamp = 1;
+  // the counter holding the last tile pass's active-tile count
+  const int* tile_count() const { return at<int>(L.tstate) + (owner ? 0 : 4 + (tile_stamp & 1)); }
   // boxes, segment table and active-tile map at X(t)
   void tiles_pass() {
     MemDev md = memdev();
     TileMap tm = tilemap();
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
+    int stamp = 0;
+    if (owner)
+      hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
+    else
+      stamp = ++tile_stamp;
     hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, 1, p.wall_y,
-                       0, 2, map_reach(r_cut));
+                       0, 2, map_reach(r_cut), stamp);
   }
   // profile field and coupling forces on the active tiles
   void profile_pass(int want_force) {
     const int grid = (int)std::min<long long>(std::max<long long>(L.ntiles, 1), 2048);
     hipLaunchKernelGGL((k_coupling2d<St, R, COUP_THREADS>), dim3(grid), dim3(COUP_THREADS), 0, stream,
-                       memdev(), tilemap(), coup_args(want_force), at<double>(L.Ifield), store(cur));
+                       memdev(), tilemap(), coup_args(want_force), at<double>(L.Ifield), store(cur),
+                       tile_count());
   }
   int coupling(int want_force) override {
     if (K == 0) return LBIB_OK;
@@ -708,7 +719,7 @@ struct Engine3D final : lbib_sim {
     TileMap tm = tilemap();
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, stream, tm.tstate);
     hipLaunchKernelGGL(k_tiles<256>, dim3(K), dim3(256), 0, stream, md, tm, p.nx, p.ny, p.nz, p.wall_y,
-                       p.wall_z, 3, map_reach(r_cut));
+                       p.wall_z, 3, map_reach(r_cut), 0);
     hipLaunchKernelGGL(k_facenormals, dim3((ntri + 255) / 256), dim3(256), 0, stream, md, mh);
     hipLaunchKernelGGL(k_meshvolume<256>, dim3(K), dim3(256), 0, stream, md, mh);
     hipLaunchKernelGGL(k_vertexnormals, dim3((M + 255) / 256), dim3(256), 0, stream, md, mh);
