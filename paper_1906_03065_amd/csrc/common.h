@@ -56,10 +56,28 @@ LB_HOST_DEVICE int wrap(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
+// wrap(v, n) for a uniform index: one that is at most one period off is
+// corrected without a division
+LB_HOST_DEVICE int wrap_near(int v, int n) {
+  if (v < 0)
+    v += n;
+  else if (v >= n)
+    v -= n;
+  return v >= 0 && v < n ? v : wrap(v, n);
+}
+
 // row index for finite differences: periodic wrap, or the mirror ghost of a
 // wall at -1/2 / n-1/2 (zero normal gradient, eq. NaturalBCs)
 LB_HOST_DEVICE int fd_row(int v, int n, int wall) {
   if (!wall) return wrap(v, n);
+  if (v < 0) return -1 - v;
+  if (v >= n) return 2 * n - 1 - v;
+  return v;
+}
+
+// fd_row for a row index that is the same across a wavefront
+LB_HOST_DEVICE int fd_row_near(int v, int n, int wall) {
+  if (!wall) return wrap_near(v, n);
   if (v < 0) return -1 - v;
   if (v >= n) return 2 * n - 1 - v;
   return v;

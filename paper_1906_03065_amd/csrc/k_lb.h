@@ -161,28 +161,31 @@ __device__ __forceinline__ void collide9(const LBParams& P, R* pf, R* pg, R* ph,
   h0 = h0 - (h0 - (psi - hsum)) * P.inv_tau_psi;
 }
 
-// pull the populations of node (x, y) at the current time: population i
-// arrives from x - c_i; across a wall it is the reversed population that
-// left (x, y) (half-way bounce-back).
+// pull the populations of node (x, y), 0 <= x < nx, 0 <= y < ny, at the
+// current time: population i arrives from x - c_i; across a wall it is the
+// reversed population that left (x, y) (half-way bounce-back).
 template <class St, typename R>
 __device__ __forceinline__ void pull9(const St& src, const LBParams& P, int x, int y, R* pf, R* pg,
                                       R* ph, double& g0, double& h0) {
   using L = Lattice<9>;
   const long long here = (long long)y * P.nx + x;
+  // the neighbour rows and columns, wrapped once per node
+  const long long rlo = (long long)(y == 0 ? P.ny - 1 : y - 1) * P.nx;
+  const long long rhi = (long long)(y == P.ny - 1 ? 0 : y + 1) * P.nx;
+  const int xlo = x == 0 ? P.nx - 1 : x - 1;
+  const int xhi = x == P.nx - 1 ? 0 : x + 1;
+  const bool wlo = P.wall_y && y == 0;         // row y - 1 lies beyond a wall
+  const bool whi = P.wall_y && y == P.ny - 1;  // row y + 1 lies beyond a wall
   pf[0] = src.template load<R>(0, 0, here);
   g0 = src.rest(1, here);
   h0 = src.rest(2, here);
 #pragma unroll
   for (int i = 1; i < 9; i++) {
-    const int sy = y - L::cy[i];
-    long long node;
-    int dir = i;
-    if (P.wall_y && (sy < 0 || sy >= P.ny)) {
-      node = here;
-      dir = L::opp[i];
-    } else {
-      node = (long long)wrap(sy, P.ny) * P.nx + wrap(x - L::cx[i], P.nx);
-    }
+    const bool back = L::cy[i] > 0 ? wlo : (L::cy[i] < 0 ? whi : false);
+    const long long row = L::cy[i] > 0 ? rlo : (L::cy[i] < 0 ? rhi : here - x);
+    const int col = L::cx[i] > 0 ? xlo : (L::cx[i] < 0 ? xhi : x);
+    const long long node = back ? here : row + col;
+    const int dir = back ? L::opp[i] : i;
     pf[i] = src.template load<R>(0, dir, node);
     pg[i] = src.template load<R>(1, dir, node);
     ph[i] = src.template load<R>(2, dir, node);
@@ -269,7 +272,7 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
 
   auto load_row = [&](auto slot_c, int k) {
     constexpr int S = decltype(slot_c)::value;
-    const int ry = fd_row(rbase + dir * k, P.ny, P.wall_y);
+    const int ry = fd_row_near(rbase + dir * k, P.ny, P.wall_y);
     pull9(src, P, x, ry, pf[S], pg[S], ph[S], g0[S], h0[S]);
     tfl[S] = tflag[(ry / P.tile) * P.ntx + x / P.tile];
   };
@@ -287,7 +290,7 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
     } else {
       load_row(std::integral_constant<int, S>{}, k);
     }
-    const int qy = fd_row(r - dir, P.ny, P.wall_y);  // row of the chemical potential
+    const int qy = fd_row_near(r - dir, P.ny, P.wall_y);  // row of the chemical potential
     const int cy = r - 2 * dir;                      // row of the collision
     double Ipre = 0.0;
     long long fb0 = 0, fb1 = 0;
@@ -392,7 +395,7 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
       const int k1 = k + 1;
       Ipre_c[T] = 0.0;
       if (k1 >= 2 && k1 < K && j >= 1 && j < BX - 1 && tfl[S] == stamp)
-        Ipre_c[T] = Ifield[(long long)fd_row(r, P.ny, P.wall_y) * P.nx + x];
+        Ipre_c[T] = Ifield[(long long)fd_row_near(r, P.ny, P.wall_y) * P.nx + x];
       cact_c[T] = k1 >= 4 && k1 < K && interior && tfl[SP] == stamp;
       fb0_c[T] = 0;
       fb1_c[T] = 0;

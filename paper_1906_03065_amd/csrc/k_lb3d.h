@@ -30,26 +30,35 @@ struct Moments3 {
   double* psi;
 };
 
-// pull the populations of node (x, y, z); bounce-back across walls in y, z
+// pull the populations of node (x, y, z), each index within the lattice;
+// bounce-back across walls in y, z
 template <class St, typename R>
 __device__ __forceinline__ void pull19(const St& src, const LBParams& P, int x, int y, int z, R* pf,
                                        R* pg, R* ph, double& g0, double& h0) {
   using L = Lattice<19>;
-  const long long here = ((long long)z * P.ny + y) * P.nx + x;
+  const long long plane = (long long)P.ny * P.nx;
+  const long long zc = z * plane;
+  const long long here = zc + (long long)y * P.nx + x;
+  // the neighbour planes, rows and columns, wrapped once per node
+  const long long zlo = (z == 0 ? P.nz - 1 : z - 1) * plane, zhi = (z == P.nz - 1 ? 0 : z + 1) * plane;
+  const long long ylo = (long long)(y == 0 ? P.ny - 1 : y - 1) * P.nx;
+  const long long yhi = (long long)(y == P.ny - 1 ? 0 : y + 1) * P.nx, yc = (long long)y * P.nx;
+  const int xlo = x == 0 ? P.nx - 1 : x - 1;
+  const int xhi = x == P.nx - 1 ? 0 : x + 1;
+  const bool wylo = P.wall_y && y == 0, wyhi = P.wall_y && y == P.ny - 1;  // beyond a wall in y
+  const bool wzlo = P.wall_z && z == 0, wzhi = P.wall_z && z == P.nz - 1;  // beyond a wall in z
   pf[0] = src.template load<R>(0, 0, here);
   g0 = src.rest(1, here);
   h0 = src.rest(2, here);
 #pragma unroll
   for (int i = 1; i < 19; i++) {
-    const int sy = y - L::cy[i], sz = z - L::cz[i];
-    long long node;
-    int dir = i;
-    if ((P.wall_y && (sy < 0 || sy >= P.ny)) || (P.wall_z && (sz < 0 || sz >= P.nz))) {
-      node = here;
-      dir = L::opp[i];
-    } else {
-      node = ((long long)wrap(sz, P.nz) * P.ny + wrap(sy, P.ny)) * P.nx + wrap(x - L::cx[i], P.nx);
-    }
+    const bool back = (L::cy[i] > 0 ? wylo : (L::cy[i] < 0 ? wyhi : false)) ||
+                      (L::cz[i] > 0 ? wzlo : (L::cz[i] < 0 ? wzhi : false));
+    const long long zo = L::cz[i] > 0 ? zlo : (L::cz[i] < 0 ? zhi : zc);
+    const long long yo = L::cy[i] > 0 ? ylo : (L::cy[i] < 0 ? yhi : yc);
+    const int xo = L::cx[i] > 0 ? xlo : (L::cx[i] < 0 ? xhi : x);
+    const long long node = back ? here : zo + yo + xo;
+    const int dir = back ? L::opp[i] : i;
     pf[i] = src.template load<R>(0, dir, node);
     pg[i] = src.template load<R>(1, dir, node);
     ph[i] = src.template load<R>(2, dir, node);
