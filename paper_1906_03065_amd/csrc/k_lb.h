@@ -51,7 +51,7 @@ struct LBParams {
   int dens;                                  // 1 if some M_m differs from 1
   int nx, ny, nz, wall_y, wall_z;
   long long N;
-  int ntx, nty, tile;                        // tile grid of the membrane maps
+  int ntx, nty, tile;                        // tile grid of the membrane maps (edge a power of two)
   int seg;                                   // rows (2D) or planes (3D) per workgroup
   int nstrip, nseg;                          // workgroup grid: strips x segments
   int nxcd;                                  // XCDs the dispatcher deals workgroups to
@@ -251,6 +251,7 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
   const int rbase = dir > 0 ? y0 - 2 : y1 + 1;
 
   const int stamp = tstate[1];  // tiles flagged with this step's stamp are active
+  const int tsh = __builtin_ctz((unsigned)P.tile);  // log2 of the tile edge
   R pf[NS][9], pg[NS][9], ph[NS][9];
   double g0[NS], h0[NS];
   // tile flag of the row in each register slot, loaded with the row; the
@@ -274,7 +275,7 @@ __device__ __forceinline__ void lb2d_run(const St& src, const St& dst, const LBP
     constexpr int S = decltype(slot_c)::value;
     const int ry = fd_row_near(rbase + dir * k, P.ny, P.wall_y);
     pull9(src, P, x, ry, pf[S], pg[S], ph[S], g0[S], h0[S]);
-    tfl[S] = tflag[(ry / P.tile) * P.ntx + x / P.tile];
+    tfl[S] = tflag[(ry >> tsh) * P.ntx + (x >> tsh)];
   };
 
   auto body = [&](auto slot_c, int k) {

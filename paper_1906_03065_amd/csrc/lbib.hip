@@ -107,6 +107,7 @@ Layout make_layout(const lbib_params* p) {
   const int Q = p->lattice == LBIB_D2Q9 ? 9 : 19;
   const int D = p->lattice == LBIB_D2Q9 ? 2 : 3;
   const long long N = (long long)p->nx * p->ny * p->nz;
+  static_assert((TILE2 & (TILE2 - 1)) == 0, "the lattice kernels index tiles by shifts");
   L.tile = D == 2 ? TILE2 : 8;
   L.ntx = (p->nx + L.tile - 1) / L.tile;
   L.nty = (p->ny + L.tile - 1) / L.tile;
