@@ -522,18 +522,17 @@ __device__ __forceinline__ void coupling2d_tile(const MemDev& md, const TileMap&
     const double hrest = cur.rest(2, cnode);
     {
       using L = Lattice<9>;
+      // neighbour rows and columns of (xc, yc), wrapped once
+      const long long rlo = (long long)(yc == 0 ? ca.ny - 1 : yc - 1) * ca.nx;
+      const long long rhi = (long long)(yc == ca.ny - 1 ? 0 : yc + 1) * ca.nx;
+      const int xlo = xc == 0 ? ca.nx - 1 : xc - 1, xhi = xc == ca.nx - 1 ? 0 : xc + 1;
+      const bool wlo = ca.wall_y && yc == 0, whi = ca.wall_y && yc == ca.ny - 1;
 #pragma unroll
       for (int i = 1; i < 9; i++) {
-        const int sy = yc - L::cy[i];
-        long long sn;
-        int dir = i;
-        if (ca.wall_y && (sy < 0 || sy >= ca.ny)) {
-          sn = cnode;
-          dir = L::opp[i];
-        } else {
-          sn = (long long)wrap(sy, ca.ny) * ca.nx + wrap(xc - L::cx[i], ca.nx);
-        }
-        hmov[i - 1] = cur.template load<R>(2, dir, sn);
+        const bool back = L::cy[i] > 0 ? wlo : (L::cy[i] < 0 ? whi : false);
+        const long long row = L::cy[i] > 0 ? rlo : (L::cy[i] < 0 ? rhi : cnode - xc);
+        const int col = L::cx[i] > 0 ? xlo : (L::cx[i] < 0 ? xhi : xc);
+        hmov[i - 1] = cur.template load<R>(2, back ? L::opp[i] : i, back ? cnode : row + col);
       }
     }
     const double xt = tx * TILE2 + 0.5 * (TILE2 - 1), yt = ty * TILE2 + 0.5 * (TILE2 - 1);
@@ -1318,19 +1317,18 @@ __device__ __forceinline__ void interp2d_run(const MemDev& md, const St& cur, co
     if (!(P.wall_y && (cy < 0 || cy >= P.ny))) {
       const int yw = wrap(cy, P.ny), xw = wrap(cx, P.nx);
       const long long node = (long long)yw * P.nx + xw;
+      // neighbour rows and columns of the stencil node, wrapped once
+      const long long rlo = (long long)(yw == 0 ? P.ny - 1 : yw - 1) * P.nx;
+      const long long rhi = (long long)(yw == P.ny - 1 ? 0 : yw + 1) * P.nx;
+      const int xlo = xw == 0 ? P.nx - 1 : xw - 1, xhi = xw == P.nx - 1 ? 0 : xw + 1;
+      const bool wlo = P.wall_y && yw == 0, whi = P.wall_y && yw == P.ny - 1;
       double d = 0, jx = 0, jy = 0;
 #pragma unroll
       for (int i = 0; i < 9; i++) {
-        const int sy = yw - L::cy[i];
-        long long sn;
-        int dir = i;
-        if (P.wall_y && (sy < 0 || sy >= P.ny)) {
-          sn = node;
-          dir = L::opp[i];
-        } else {
-          sn = (long long)wrap(sy, P.ny) * P.nx + wrap(xw - L::cx[i], P.nx);
-        }
-        const double v = (double)cur.template load<R>(0, dir, sn);
+        const bool back = L::cy[i] > 0 ? wlo : (L::cy[i] < 0 ? whi : false);
+        const long long row = L::cy[i] > 0 ? rlo : (L::cy[i] < 0 ? rhi : node - xw);
+        const int col = L::cx[i] > 0 ? xlo : (L::cx[i] < 0 ? xhi : xw);
+        const double v = (double)cur.template load<R>(0, back ? L::opp[i] : i, back ? node : row + col);
         d += v;
         jx += L::cx[i] * v;
         jy += L::cy[i] * v;

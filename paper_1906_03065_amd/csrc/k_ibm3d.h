@@ -985,17 +985,22 @@ __global__ __launch_bounds__(NT) void k_coupling3d(MemDev md, MeshDev mh, TileMa
       if (valid && wband) {
         using L = Lattice<19>;
         psi = cur.rest(2, node);
+        // neighbour planes, rows and columns of the node, wrapped once
+        const long long pl = (long long)ca.ny * ca.nx;
+        const long long zlo = (xi[2] == 0 ? ca.nz - 1 : xi[2] - 1) * pl, zc = xi[2] * pl;
+        const long long zhi = (xi[2] == ca.nz - 1 ? 0 : xi[2] + 1) * pl;
+        const long long ylo = (long long)(xi[1] == 0 ? ca.ny - 1 : xi[1] - 1) * ca.nx;
+        const long long yhi = (long long)(xi[1] == ca.ny - 1 ? 0 : xi[1] + 1) * ca.nx;
+        const long long yc = (long long)xi[1] * ca.nx;
+        const int xlo = xi[0] == 0 ? ca.nx - 1 : xi[0] - 1, xhi = xi[0] == ca.nx - 1 ? 0 : xi[0] + 1;
+        const bool wylo = ca.wall_y && xi[1] == 0, wyhi = ca.wall_y && xi[1] == ca.ny - 1;
+        const bool wzlo = ca.wall_z && xi[2] == 0, wzhi = ca.wall_z && xi[2] == ca.nz - 1;
         for (int i = 1; i < 19; i++) {
-          const int sy = xi[1] - L::cy[i], sz = xi[2] - L::cz[i];
-          long long sn;
-          int dir = i;
-          if ((ca.wall_y && (sy < 0 || sy >= ca.ny)) || (ca.wall_z && (sz < 0 || sz >= ca.nz))) {
-            sn = node;
-            dir = L::opp[i];
-          } else {
-            sn = ((long long)wrap(sz, ca.nz) * ca.ny + wrap(sy, ca.ny)) * ca.nx + wrap(xi[0] - L::cx[i], ca.nx);
-          }
-          psi += (double)cur.template load<R>(2, dir, sn);
+          const int ex = L::cx[i], ey = L::cy[i], ez = L::cz[i];
+          const bool back = (ey > 0 ? wylo : (ey < 0 ? wyhi : false)) || (ez > 0 ? wzlo : (ez < 0 ? wzhi : false));
+          const long long sn = (ez > 0 ? zlo : (ez < 0 ? zhi : zc)) + (ey > 0 ? ylo : (ey < 0 ? yhi : yc)) +
+                               (ex > 0 ? xlo : (ex < 0 ? xhi : xi[0]));
+          psi += (double)cur.template load<R>(2, back ? L::opp[i] : i, back ? node : sn);
         }
       }
       // an empty hash table (the previous tile flushed it before its last barrier)
@@ -1297,18 +1302,22 @@ __global__ void k_interp3d(MemDev md, St cur, LBParams P, const double* __restri
     if (!((P.wall_y && (cy < 0 || cy >= P.ny)) || (P.wall_z && (cz < 0 || cz >= P.nz)))) {
       const int xw = wrap(cx, P.nx), yw = wrap(cy, P.ny), zw = wrap(cz, P.nz);
       const long long node = ((long long)zw * P.ny + yw) * P.nx + xw;
+      // neighbour planes, rows and columns of the stencil node, wrapped once
+      const long long pl = (long long)P.ny * P.nx;
+      const long long zlo = (zw == 0 ? P.nz - 1 : zw - 1) * pl, zc = zw * pl;
+      const long long zhi = (zw == P.nz - 1 ? 0 : zw + 1) * pl;
+      const long long ylo = (long long)(yw == 0 ? P.ny - 1 : yw - 1) * P.nx;
+      const long long yhi = (long long)(yw == P.ny - 1 ? 0 : yw + 1) * P.nx, yc = (long long)yw * P.nx;
+      const int xlo = xw == 0 ? P.nx - 1 : xw - 1, xhi = xw == P.nx - 1 ? 0 : xw + 1;
+      const bool wylo = P.wall_y && yw == 0, wyhi = P.wall_y && yw == P.ny - 1;
+      const bool wzlo = P.wall_z && zw == 0, wzhi = P.wall_z && zw == P.nz - 1;
       double d = 0, j[3] = {0, 0, 0};
       for (int i = 0; i < 19; i++) {
-        const int sy = yw - L::cy[i], sz = zw - L::cz[i];
-        long long sn;
-        int dir = i;
-        if ((P.wall_y && (sy < 0 || sy >= P.ny)) || (P.wall_z && (sz < 0 || sz >= P.nz))) {
-          sn = node;
-          dir = L::opp[i];
-        } else {
-          sn = ((long long)wrap(sz, P.nz) * P.ny + wrap(sy, P.ny)) * P.nx + wrap(xw - L::cx[i], P.nx);
-        }
-        const double v = (double)cur.template load<R>(0, dir, sn);
+        const int ex = L::cx[i], ey = L::cy[i], ez = L::cz[i];
+        const bool back = (ey > 0 ? wylo : (ey < 0 ? wyhi : false)) || (ez > 0 ? wzlo : (ez < 0 ? wzhi : false));
+        const long long sn = (ez > 0 ? zlo : (ez < 0 ? zhi : zc)) + (ey > 0 ? ylo : (ey < 0 ? yhi : yc)) +
+                             (ex > 0 ? xlo : (ex < 0 ? xhi : xw));
+        const double v = (double)cur.template load<R>(0, back ? L::opp[i] : i, back ? node : sn);
         d += v;
         j[0] += L::cx[i] * v;
         j[1] += L::cy[i] * v;
